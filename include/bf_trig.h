@@ -1,0 +1,149 @@
+/*
+ * bf_trig.h -- C ABI of the constant-time trigonometric bilateral filter for
+ * AMD MI355X (gfx950).
+ *
+ * The filter is the unbiased bilateral filter of Chaudhury, Sage and Unser,
+ * "Fast O(1) bilateral filtering using trigonometric range kernels":
+ *
+ *     out(x) = sum_y w(y) phi(f(x-y) - f(x)) f(x-y) / eta(x)         eq. (BF)
+ *     eta(x) = sum_y w(y) phi(f(x-y) - f(x))                 eq. (normalization)
+ *
+ * with the raised-cosine range kernel phi(s) = cos(alpha s)^N of Sec. 2.3,
+ * scaled as in Sec. 2.5 / Algorithm 1 (gamma = pi/2T, rho = gamma sigma_r,
+ * alpha = gamma/(rho sqrt N) = 1/(sigma_r sqrt N)), and a separable spatial
+ * kernel w(dy,dx) = k(dy) k(dx) where k is the convolution of n_boxes
+ * unit-height boxes of widths 2 radius[i] + 1 (the O(1) box / iterated-box
+ * averaging of Sec. 2.1).  The sums run over pixels inside the image (the
+ * auxiliary images are zero-extended).  The library evaluates it in O(1) per
+ * pixel per term through the binomial expansion of Sec. 2.3 and eq.
+ * (final-form): pairs of auxiliary images exp(+-j m alpha f), f exp(+-j m
+ * alpha f) are filtered by running box sums and demodulated per pixel.
+ *
+ * Conventions shared by every entry point:
+ *  - Images are row-major H x W float32 arrays in DEVICE memory owned by the
+ *    caller (e.g. torch tensors); the library never frees them.
+ *  - Input intensities are expected in [0, T] (Sec. 2.1); this precondition
+ *    keeps the kernel non-negative and is not checked on the hot path.
+ *  - eta uses the unnormalised integer box weights (the mass of w cancels in
+ *    the ratio).
+ *  - Calls are asynchronous on opts->stream (a hipStream_t; NULL = the null
+ *    stream).  Argument errors are reported synchronously, before anything is
+ *    enqueued; launch errors as BF_EDEVICE.  No function throws.
+ *  - bf_last_error() returns a thread-local description of the last failure.
+ */
+#ifndef BF_TRIG_H
+#define BF_TRIG_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    BF_OK = 0,
+    BF_EINVAL = 1,       /* null pointer, non-positive size, bad spec, aliasing */
+    BF_ERANGE = 2,       /* degree below the bound of Sec. 2.5, N or radius too large */
+    BF_ENOMEM = 3,       /* device or host allocation failed */
+    BF_EDEVICE = 4,      /* HIP runtime / launch error */
+    BF_ECAPTURE = 5,     /* call not allowed while the stream is being captured */
+    BF_EUNSUPPORTED = 6  /* valid request outside what this build implements */
+} bf_status;
+
+#define BF_MAX_BOXES 4      /* iterated boxes per axis */
+#define BF_MAX_RADIUS 128   /* per box */
+#define BF_MAX_DEGREE 1024  /* largest raised-cosine degree N */
+
+/* Spatial kernel: n_boxes boxes per axis (1 = plain box; 3 approximates a
+ * Gaussian, Sec. 2.1 and Algorithm 1 step 4).  radius[i] >= 0; box i has
+ * 2 radius[i] + 1 taps, the same in x and y. */
+typedef struct {
+    int32_t n_boxes;
+    int32_t radius[BF_MAX_BOXES];
+} bf_spatial_spec;
+
+/* Optional per-call settings; a NULL bf_opts* means all defaults. */
+typedef struct {
+    void* stream;        /* hipStream_t; NULL = null stream */
+    int32_t N;           /* 0 = ceil((2T/(pi sigma_r))^2) (Algorithm 1 step 2);
+                            else the degree, which must be >= that bound */
+    float* eta_out;      /* optional H*W device buffer for eta (the backward
+                            needs it); NULL = not written */
+    int32_t tile_h;      /* 0 = library choice; else output tile rows */
+    int32_t tile_w;      /* 0 = library choice; else output tile columns */
+} bf_opts;
+
+/* Algorithm 1 steps 1-2: N = ceil((gamma sigma_r)^-2), gamma = pi/(2T).
+ * T > 0, sigma_r > 0.  BF_ERANGE if N would exceed BF_MAX_DEGREE. */
+bf_status bf_range_degree(double T, double sigma_r, int32_t* N_out);
+
+/* Sec. 2.3 binomial expansion folded into cosine pairs:
+ *   cos^N(t) = sum_q c[q] cos(m_q t),  m_q = (N mod 2) + 2q,
+ *   c[q] = 2^-N C(N, N/2) for m_q = 0, else 2^(1-N) C(N, (N-m_q)/2),
+ * computed in extended precision and rounded to float.  Writes
+ * n = floor(N/2)+1 values to c_out (capacity cap); *n_out = n. */
+bf_status bf_range_coeffs(int32_t N, float* c_out, int32_t cap, int32_t* n_out);
+
+/* Radii of n_boxes iterated boxes whose combined variance approximates
+ * sigma_s^2 (a Gaussian spatial filter of Algorithm 1 step 4): ideal width
+ * sqrt(12 sigma_s^2 / n + 1), mixing the nearest odd widths below and above,
+ * the narrower ones first, ties to the narrower. */
+bf_status bf_spatial_gaussian(double sigma_s, int32_t n_boxes, bf_spatial_spec* out);
+
+/* Forward filter, eq. (BF)/(normalization) with the raised-cosine kernel.
+ * f: H*W input; out: H*W output (must not overlap f).  sigma_r > 0, T > 0.
+ * Equivalent to bf_trig_forward_ex with opts == NULL. */
+bf_status bf_trig_forward(const float* f, int64_t H, int64_t W, float T, float sigma_r,
+                          const bf_spatial_spec* spatial_spec, float* out);
+
+bf_status bf_trig_forward_ex(const float* f, int64_t H, int64_t W, float T, float sigma_r,
+                             const bf_spatial_spec* spatial_spec, float* out,
+                             const bf_opts* opts);
+
+/* Adjoint: grad_f = (d out / d f)^T grad_out, the exact derivative of eq.
+ * (BF)/(normalization) for the raised-cosine kernel.  out and eta are the
+ * forward's outputs for the same f and parameters (opts->N must match).
+ * All five buffers are H*W; grad_f must not overlap the inputs. */
+bf_status bf_trig_backward(const float* f, const float* out, const float* eta,
+                           const float* grad_out, int64_t H, int64_t W, float T,
+                           float sigma_r, const bf_spatial_spec* spatial_spec,
+                           float* grad_f, const bf_opts* opts);
+
+/* Direct-window filter: the same eq. (BF)/(normalization) summed pixel by
+ * pixel over the whole window, O((2R+1)^2) per pixel (the baseline the paper
+ * compares its O(1) method with).  Same arguments as the forward. */
+bf_status bf_direct_forward(const float* f, int64_t H, int64_t W, float T, float sigma_r,
+                            const bf_spatial_spec* spatial_spec, float* out,
+                            const bf_opts* opts);
+
+/* ---- batches of images of different sizes and parameters ------------------
+ * A plan fixes the images' sizes and parameters and owns every device table
+ * and workspace; bf_batch_bind attaches device buffers (pointer arrays in host
+ * memory, n entries each; target/grad_f/loss may be NULL for a forward-only
+ * batch); bf_batch_launch enqueues the whole batch -- forward, SSD loss
+ * gradient 2(out - target) and adjoint -- as one persistent kernel, allocates
+ * and synchronises nothing, and may be captured into a hipGraph.  */
+typedef struct {
+    int64_t H, W;
+    float T, sigma_r;
+    int32_t N;                   /* 0 = automatic degree */
+    bf_spatial_spec spatial;
+} bf_image_desc;
+
+typedef struct bf_batch_plan bf_batch_plan;
+
+bf_status bf_batch_plan_create(const bf_image_desc* descs, int32_t n, bf_batch_plan** plan);
+bf_status bf_batch_bind(bf_batch_plan* plan, const float* const* f, const float* const* target,
+                        float* const* out, float* const* eta, float* const* grad_f,
+                        float* loss /* device, n floats: per-image SSD, or NULL */);
+bf_status bf_batch_launch(bf_batch_plan* plan, void* stream);
+void bf_batch_plan_destroy(bf_batch_plan* plan);
+
+const char* bf_status_string(bf_status s);
+const char* bf_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* BF_TRIG_H */

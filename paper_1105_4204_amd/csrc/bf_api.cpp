@@ -1,0 +1,101 @@
+// extern "C" entry points of libbftrig: argument validation, parameter
+// derivation and dispatch to the HIP kernels.  Nothing here allocates on the
+// single-image paths, so they may be captured into a hipGraph.
+#include "bf_internal.h"
+
+using namespace bf;
+
+namespace {
+
+struct Common {
+    RangeParams rp;
+    SpatialParams sp;
+    hipStream_t stream;
+};
+
+bf_status prepare(const float* f, int64_t H, int64_t W, float T, float sigma_r,
+                  const bf_spatial_spec* spec, const bf_opts* opts, Common* c) {
+    bf_status st = check_image(f, H, W, "f");
+    if (st != BF_OK) return st;
+    st = make_spatial(spec, &c->sp);
+    if (st != BF_OK) return st;
+    st = make_range((double)T, (double)sigma_r, opts ? opts->N : 0, &c->rp);
+    if (st != BF_OK) return st;
+    c->stream = opts ? (hipStream_t)opts->stream : nullptr;
+    return BF_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+bf_status bf_trig_forward_ex(const float* f, int64_t H, int64_t W, float T, float sigma_r,
+                             const bf_spatial_spec* spatial_spec, float* out,
+                             const bf_opts* opts) {
+    Common c;
+    bf_status st = prepare(f, H, W, T, sigma_r, spatial_spec, opts, &c);
+    if (st != BF_OK) return st;
+    st = check_image(out, H, W, "out");
+    if (st != BF_OK) return st;
+    const int64_t bytes = H * W * (int64_t)sizeof(float);
+    float* eta = opts ? opts->eta_out : nullptr;
+    if (overlaps(f, out, bytes) || overlaps(f, eta, bytes) || overlaps(out, eta, bytes)) {
+        set_error("out / eta_out must not overlap f or each other");
+        return BF_EINVAL;
+    }
+    TileGeom g;
+    st = plan_fwd_tiles(H, W, c.sp, opts ? opts->tile_h : 0, opts ? opts->tile_w : 0, &g);
+    if (st != BF_OK) return st;
+    return launch_fwd(f, out, eta, H, W, c.rp, c.sp, g, c.stream);
+}
+
+bf_status bf_trig_forward(const float* f, int64_t H, int64_t W, float T, float sigma_r,
+                          const bf_spatial_spec* spatial_spec, float* out) {
+    return bf_trig_forward_ex(f, H, W, T, sigma_r, spatial_spec, out, nullptr);
+}
+
+bf_status bf_direct_forward(const float* f, int64_t H, int64_t W, float T, float sigma_r,
+                            const bf_spatial_spec* spatial_spec, float* out,
+                            const bf_opts* opts) {
+    Common c;
+    bf_status st = prepare(f, H, W, T, sigma_r, spatial_spec, opts, &c);
+    if (st != BF_OK) return st;
+    st = check_image(out, H, W, "out");
+    if (st != BF_OK) return st;
+    const int64_t bytes = H * W * (int64_t)sizeof(float);
+    float* eta = opts ? opts->eta_out : nullptr;
+    if (overlaps(f, out, bytes) || overlaps(f, eta, bytes) || overlaps(out, eta, bytes)) {
+        set_error("out / eta_out must not overlap f or each other");
+        return BF_EINVAL;
+    }
+    return launch_direct(f, out, eta, H, W, c.rp, c.sp, c.stream);
+}
+
+bf_status bf_trig_backward(const float* f, const float* out, const float* eta,
+                           const float* grad_out, int64_t H, int64_t W, float T, float sigma_r,
+                           const bf_spatial_spec* spatial_spec, float* grad_f,
+                           const bf_opts* opts) {
+    Common c;
+    bf_status st = prepare(f, H, W, T, sigma_r, spatial_spec, opts, &c);
+    if (st != BF_OK) return st;
+    const void* bufs[4] = {out, eta, grad_out, grad_f};
+    const char* names[4] = {"out", "eta", "grad_out", "grad_f"};
+    for (int i = 0; i < 4; ++i) {
+        st = check_image(bufs[i], H, W, names[i]);
+        if (st != BF_OK) return st;
+    }
+    const int64_t bytes = H * W * (int64_t)sizeof(float);
+    const void* ins[4] = {f, out, eta, grad_out};
+    for (int i = 0; i < 4; ++i) {
+        if (overlaps(ins[i], grad_f, bytes)) {
+            set_error("grad_f must not overlap the inputs");
+            return BF_EINVAL;
+        }
+    }
+    TileGeom g;
+    st = plan_bwd_tiles(H, W, c.sp, opts ? opts->tile_h : 0, opts ? opts->tile_w : 0, &g);
+    if (st != BF_OK) return st;
+    return launch_bwd(f, out, eta, grad_out, grad_f, H, W, c.rp, c.sp, g, c.stream);
+}
+
+}  // extern "C"

@@ -1,0 +1,220 @@
+// Host-side parameter derivation and argument checking for the trigonometric
+// bilateral filter: degree rule (Algorithm 1 steps 1-2), binomial cosine-pair
+// coefficients (Sec. 2.3), iterated-box radii for a Gaussian spatial filter,
+// validation and the thread-local error text.
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include "bf_internal.h"
+
+namespace bf {
+
+static thread_local char g_err[512] = "";
+
+void set_error(const char* fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof(g_err), fmt, ap);
+    va_end(ap);
+}
+
+// ceil((2T / (pi sigma_r))^2), i.e. ceil(rho^-2) with rho = gamma sigma_r and
+// gamma = pi / 2T (Algorithm 1 steps 1-2, Sec. 2.5); at least 1.
+static bf_status degree_rule(double T, double sigma_r, int32_t* N) {
+    if (!(T > 0.0) || !(sigma_r > 0.0) || !isfinite(T) || !isfinite(sigma_r)) {
+        set_error("T and sigma_r must be positive and finite (T=%g, sigma_r=%g)", T, sigma_r);
+        return BF_EINVAL;
+    }
+    const double rho = (M_PI / (2.0 * T)) * sigma_r;
+    const double n = ceil(1.0 / (rho * rho));
+    if (n > (double)BF_MAX_DEGREE) {
+        set_error("degree %.0f needed for sigma_r=%g, T=%g exceeds BF_MAX_DEGREE=%d", n, sigma_r,
+                  T, BF_MAX_DEGREE);
+        return BF_ERANGE;
+    }
+    *N = n < 1.0 ? 1 : (int32_t)n;
+    return BF_OK;
+}
+
+// c[q] for the pair m_q = (N mod 2) + 2q of cos^N = sum_n 2^-N C(N,n) e^{j(2n-N)t}:
+// the terms n and N-n share frequency |2n-N| and fold to 2 * 2^-N C(N,n) cos(m t).
+// log C(N,n) - N log 2 in long double, then exp and one rounding to float.
+static void pair_coeffs(int32_t N, float* c, int32_t* n_out) {
+    const int32_t np = N / 2 + 1;
+    const long double lN = lgammal((long double)N + 1.0L) - (long double)N * logl(2.0L);
+    for (int32_t q = 0; q < np; ++q) {
+        const int32_t m = (N & 1) + 2 * q;
+        const int32_t n = (N - m) / 2;
+        const long double lc =
+            lN - lgammal((long double)n + 1.0L) - lgammal((long double)(N - n) + 1.0L);
+        long double v = expl(lc);
+        if (m > 0) v *= 2.0L;
+        c[q] = (float)v;
+    }
+    *n_out = np;
+}
+
+bf_status make_range(double T, double sigma_r, int32_t N_req, RangeParams* rp) {
+    int32_t Nmin = 0;
+    bf_status st = degree_rule(T, sigma_r, &Nmin);
+    if (st != BF_OK) return st;
+    int32_t N = Nmin;
+    if (N_req != 0) {
+        if (N_req < 0 || N_req > BF_MAX_DEGREE) {
+            set_error("degree N=%d outside [1, %d]", N_req, BF_MAX_DEGREE);
+            return BF_ERANGE;
+        }
+        if (N_req < Nmin) {
+            set_error("degree N=%d below the bound ceil((2T/(pi sigma_r))^2)=%d: the raised "
+                      "cosine would turn negative inside [-T, T]", N_req, Nmin);
+            return BF_ERANGE;
+        }
+        N = N_req;
+    }
+    rp->N = N;
+    rp->odd = N & 1;
+    rp->alpha = 1.0 / (sigma_r * sqrt((double)N));
+    rp->center = (float)(0.5 * T);
+    int32_t np = 0;
+    pair_coeffs(N, rp->chat, &np);
+    // Coefficients that round to exactly zero in float contribute exactly zero.
+    while (np > 1 && rp->chat[np - 1] == 0.0f) --np;
+    rp->npairs = np;
+    return BF_OK;
+}
+
+bf_status make_spatial(const bf_spatial_spec* spec, SpatialParams* sp) {
+    if (!spec) {
+        set_error("spatial_spec is NULL");
+        return BF_EINVAL;
+    }
+    if (spec->n_boxes < 1 || spec->n_boxes > BF_MAX_BOXES) {
+        set_error("n_boxes=%d outside [1, %d]", spec->n_boxes, BF_MAX_BOXES);
+        return BF_EINVAL;
+    }
+    sp->nb = spec->n_boxes;
+    sp->R = 0;
+    for (int i = 0; i < BF_MAX_BOXES; ++i) sp->r[i] = 0;
+    for (int i = 0; i < spec->n_boxes; ++i) {
+        if (spec->radius[i] < 0) {
+            set_error("radius[%d]=%d is negative", i, spec->radius[i]);
+            return BF_EINVAL;
+        }
+        if (spec->radius[i] > BF_MAX_RADIUS) {
+            set_error("radius[%d]=%d exceeds BF_MAX_RADIUS=%d", i, spec->radius[i], BF_MAX_RADIUS);
+            return BF_ERANGE;
+        }
+        sp->r[i] = spec->radius[i];
+        sp->R += spec->radius[i];
+    }
+    return BF_OK;
+}
+
+bf_status check_image(const void* p, int64_t H, int64_t W, const char* name) {
+    if (!p) {
+        set_error("%s is NULL", name);
+        return BF_EINVAL;
+    }
+    if (H <= 0 || W <= 0) {
+        set_error("image size %lld x %lld must be positive", (long long)H, (long long)W);
+        return BF_EINVAL;
+    }
+    if (H > (1 << 20) || W > (1 << 20) || H * W > (int64_t)1 << 31) {
+        set_error("image size %lld x %lld too large", (long long)H, (long long)W);
+        return BF_ERANGE;
+    }
+    return BF_OK;
+}
+
+bool overlaps(const void* a, const void* b, int64_t bytes) {
+    if (!a || !b) return false;
+    const char* pa = (const char*)a;
+    const char* pb = (const char*)b;
+    return pa < pb + bytes && pb < pa + bytes;
+}
+
+}  // namespace bf
+
+using namespace bf;
+
+extern "C" {
+
+bf_status bf_range_degree(double T, double sigma_r, int32_t* N_out) {
+    if (!N_out) {
+        set_error("N_out is NULL");
+        return BF_EINVAL;
+    }
+    return degree_rule(T, sigma_r, N_out);
+}
+
+bf_status bf_range_coeffs(int32_t N, float* c_out, int32_t cap, int32_t* n_out) {
+    if (!c_out || !n_out) {
+        set_error("c_out / n_out is NULL");
+        return BF_EINVAL;
+    }
+    if (N < 0 || N > BF_MAX_DEGREE) {
+        set_error("N=%d outside [0, %d]", N, BF_MAX_DEGREE);
+        return BF_ERANGE;
+    }
+    if (cap < N / 2 + 1) {
+        set_error("capacity %d < %d coefficients", cap, N / 2 + 1);
+        return BF_EINVAL;
+    }
+    pair_coeffs(N, c_out, n_out);
+    return BF_OK;
+}
+
+bf_status bf_spatial_gaussian(double sigma_s, int32_t n_boxes, bf_spatial_spec* out) {
+    if (!out) {
+        set_error("out is NULL");
+        return BF_EINVAL;
+    }
+    if (!(sigma_s >= 0.0) || !isfinite(sigma_s) || n_boxes < 1 || n_boxes > BF_MAX_BOXES) {
+        set_error("sigma_s=%g must be >= 0 and n_boxes=%d in [1, %d]", sigma_s, n_boxes,
+                  BF_MAX_BOXES);
+        return BF_EINVAL;
+    }
+    // A box of odd width w has variance (w^2 - 1)/12; n boxes of ideal width
+    // w* = sqrt(12 sigma^2/n + 1) reach sigma^2.  Use m boxes of the largest odd
+    // width wl <= w* and n - m of wl + 2, with m the rounded solution of
+    // m (wl^2-1)/12 + (n-m) ((wl+2)^2-1)/12 = sigma^2.
+    const double wideal = sqrt(12.0 * sigma_s * sigma_s / n_boxes + 1.0);
+    int wl = (int)floor(wideal);
+    if (wl % 2 == 0) --wl;
+    if (wl < 1) wl = 1;
+    const int wu = wl + 2;
+    const double mideal = (n_boxes * (double)wl * wl + 4.0 * n_boxes * wl + 3.0 * n_boxes -
+                           12.0 * sigma_s * sigma_s) / (4.0 * wl + 4.0);
+    int m = (int)floor(mideal + 0.5);
+    if (m < 0) m = 0;
+    if (m > n_boxes) m = n_boxes;
+    out->n_boxes = n_boxes;
+    for (int i = 0; i < BF_MAX_BOXES; ++i) out->radius[i] = 0;
+    for (int i = 0; i < n_boxes; ++i) out->radius[i] = ((i < m ? wl : wu) - 1) / 2;
+    for (int i = 0; i < n_boxes; ++i) {
+        if (out->radius[i] > BF_MAX_RADIUS) {
+            set_error("sigma_s=%g needs radius %d > BF_MAX_RADIUS", sigma_s, out->radius[i]);
+            return BF_ERANGE;
+        }
+    }
+    return BF_OK;
+}
+
+const char* bf_status_string(bf_status s) {
+    switch (s) {
+        case BF_OK: return "BF_OK";
+        case BF_EINVAL: return "BF_EINVAL: invalid argument";
+        case BF_ERANGE: return "BF_ERANGE: parameter out of range";
+        case BF_ENOMEM: return "BF_ENOMEM: out of memory";
+        case BF_EDEVICE: return "BF_EDEVICE: HIP runtime error";
+        case BF_ECAPTURE: return "BF_ECAPTURE: not allowed during stream capture";
+        case BF_EUNSUPPORTED: return "BF_EUNSUPPORTED: not supported by this build";
+    }
+    return "unknown bf_status";
+}
+
+const char* bf_last_error(void) { return g_err; }
+
+}  // extern "C"

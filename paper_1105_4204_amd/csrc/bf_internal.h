@@ -1,0 +1,60 @@
+// Internal declarations shared by the host code and the HIP kernels of the
+// trigonometric bilateral filter library.  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/bf_trig.h"
+
+namespace bf {
+
+// Largest number of cosine pairs: floor(BF_MAX_DEGREE / 2) + 1.
+constexpr int kMaxPairs = BF_MAX_DEGREE / 2 + 1;
+
+// Host-side description of one filter evaluation: everything derived from
+// (T, sigma_r, N, radii) before a launch.
+struct RangeParams {
+    int32_t N;        // degree of the raised cosine
+    int32_t npairs;   // cosine pairs actually evaluated (trailing zero coefficients dropped)
+    int32_t odd;      // N mod 2: the first pair has m = 1 instead of m = 0
+    double alpha;     // 1 / (sigma_r sqrt N): phase per unit of intensity and unit of m
+    float center;     // T/2: intensities are re-centred before modulation
+    float chat[kMaxPairs];
+};
+
+struct SpatialParams {
+    int32_t nb;       // boxes per axis
+    int32_t r[BF_MAX_BOXES];
+    int32_t R;        // sum of radii: half-width of the composite kernel
+};
+
+// Host helpers (bf_host.cpp).
+void set_error(const char* fmt, ...);
+bf_status make_range(double T, double sigma_r, int32_t N_req, RangeParams* rp);
+bf_status make_spatial(const bf_spatial_spec* spec, SpatialParams* sp);
+bf_status check_image(const void* p, int64_t H, int64_t W, const char* name);
+bool overlaps(const void* a, const void* b, int64_t bytes);
+
+// Tile geometry of the fused forward/backward kernels.
+struct TileGeom {
+    int TH, TW;       // output tile
+    int EH, EW;       // extended tile (output + halo of R on every side)
+    int tiles_x, tiles_y;
+    size_t lds_bytes;
+};
+
+bf_status plan_fwd_tiles(int64_t H, int64_t W, const SpatialParams& sp, int req_h, int req_w,
+                         TileGeom* g);
+bf_status launch_fwd(const float* f, float* out, float* eta, int64_t H, int64_t W,
+                     const RangeParams& rp, const SpatialParams& sp, const TileGeom& g,
+                     hipStream_t stream);
+bf_status launch_direct(const float* f, float* out, float* eta, int64_t H, int64_t W,
+                        const RangeParams& rp, const SpatialParams& sp, hipStream_t stream);
+bf_status plan_bwd_tiles(int64_t H, int64_t W, const SpatialParams& sp, int req_h, int req_w,
+                         TileGeom* g);
+bf_status launch_bwd(const float* f, const float* out, const float* eta, const float* gout,
+                     float* gf, int64_t H, int64_t W, const RangeParams& rp,
+                     const SpatialParams& sp, const TileGeom& g, hipStream_t stream);
+
+}  // namespace bf

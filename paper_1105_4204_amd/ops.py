@@ -1,0 +1,100 @@
+"""PyTorch-facing calls of the trigonometric bilateral filter.
+
+PyTorch supplies device memory and the current HIP stream; every value is
+computed by the HIP kernels of libbftrig.so through the C ABI (see
+``_native``).  Inputs must be contiguous float32 CUDA (HIP) tensors.
+"""
+from __future__ import annotations
+
+import ctypes
+
+import torch
+
+from . import _native as nat
+
+
+def _stream_ptr():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _check_img(x: torch.Tensor, name: str):
+    if not isinstance(x, torch.Tensor) or not x.is_cuda:
+        raise TypeError(f"{name} must be a CUDA/HIP tensor")
+    if x.dtype != torch.float32 or x.dim() != 2 or not x.is_contiguous():
+        raise TypeError(f"{name} must be a contiguous 2-D float32 tensor, got "
+                        f"{x.dtype} {tuple(x.shape)}")
+
+
+def _ptr(x):
+    return ctypes.c_void_p(x.data_ptr()) if x is not None else None
+
+
+def trig_forward(f: torch.Tensor, T: float, sigma_r: float, radii, N: int = 0,
+                 return_eta: bool = False, tile=None, out: torch.Tensor | None = None):
+    """O(1) raised-cosine bilateral filter of a 2-D image (fused HIP kernel)."""
+    _check_img(f, "f")
+    H, W = f.shape
+    out = torch.empty_like(f) if out is None else out
+    eta = torch.empty_like(f) if return_eta else None
+    spec = nat.SpatialSpec.of(radii)
+    opts = nat.make_opts(_stream_ptr(), N, _ptr(eta), tile)
+    nat.check(nat.lib().bf_trig_forward_ex(_ptr(f), H, W, float(T), float(sigma_r),
+                                           ctypes.byref(spec), _ptr(out), ctypes.byref(opts)),
+              "bf_trig_forward_ex")
+    return (out, eta) if return_eta else out
+
+
+def direct_forward(f: torch.Tensor, T: float, sigma_r: float, radii, N: int = 0,
+                   return_eta: bool = False):
+    """Direct-window (O((2R+1)^2) per pixel) filter on the GPU."""
+    _check_img(f, "f")
+    H, W = f.shape
+    out = torch.empty_like(f)
+    eta = torch.empty_like(f) if return_eta else None
+    spec = nat.SpatialSpec.of(radii)
+    opts = nat.make_opts(_stream_ptr(), N, _ptr(eta))
+    nat.check(nat.lib().bf_direct_forward(_ptr(f), H, W, float(T), float(sigma_r),
+                                          ctypes.byref(spec), _ptr(out), ctypes.byref(opts)),
+              "bf_direct_forward")
+    return (out, eta) if return_eta else out
+
+
+def trig_backward(f, out, eta, grad_out, T: float, sigma_r: float, radii, N: int = 0,
+                  tile=None):
+    """grad_f = J^T grad_out for the forward that produced (out, eta)."""
+    for x, n in ((f, "f"), (out, "out"), (eta, "eta"), (grad_out, "grad_out")):
+        _check_img(x, n)
+    H, W = f.shape
+    gf = torch.empty_like(f)
+    spec = nat.SpatialSpec.of(radii)
+    opts = nat.make_opts(_stream_ptr(), N, None, tile)
+    nat.check(nat.lib().bf_trig_backward(_ptr(f), _ptr(out), _ptr(eta), _ptr(grad_out), H, W,
+                                         float(T), float(sigma_r), ctypes.byref(spec), _ptr(gf),
+                                         ctypes.byref(opts)),
+              "bf_trig_backward")
+    return gf
+
+
+class BFTrig(torch.autograd.Function):
+    """Autograd wrapper: forward saves (f, out, eta); backward calls the
+    hand-written adjoint kernel.  T, sigma_r, radii and N are constants."""
+
+    @staticmethod
+    def forward(ctx, f, T, sigma_r, radii, N):
+        f = f.contiguous()
+        out, eta = trig_forward(f, T, sigma_r, radii, N, return_eta=True)
+        ctx.save_for_backward(f, out, eta)
+        ctx.params = (T, sigma_r, tuple(radii), N)
+        return out
+
+    @staticmethod
+    def backward(ctx, grad_out):
+        f, out, eta = ctx.saved_tensors
+        T, sigma_r, radii, N = ctx.params
+        gf = trig_backward(f, out, eta, grad_out.contiguous(), T, sigma_r, radii, N)
+        return gf, None, None, None, None
+
+
+def bf_trig(f: torch.Tensor, T: float = 255.0, sigma_r: float = 30.0, radii=(5,), N: int = 0):
+    """Differentiable O(1) bilateral filter of a 2-D float32 image."""
+    return BFTrig.apply(f, float(T), float(sigma_r), tuple(int(r) for r in radii), int(N))

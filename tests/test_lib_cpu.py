@@ -1,0 +1,129 @@
+"""CPU-side tests of libbftrig: it loads, exports every symbol the header
+declares, and its host logic (degree rule, cosine-pair coefficients, box radii,
+argument validation) is right.  No call here reaches the GPU: the validation
+paths return before anything is enqueued."""
+import ctypes
+import math
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_1105_4204_amd import _native as nat
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "bf_trig.h")
+GOLD = os.path.join(ROOT, "tests", "golden")
+
+
+def _declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:bf_status|void|const char\*)\s+(bf_\w+)\s*\(", src, re.M)))
+
+
+def test_library_exports_every_declared_symbol():
+    L = nat.lib()
+    decl = _declared_functions()
+    assert len(decl) >= 13
+    for name in decl:
+        assert hasattr(L, name), name
+    assert sorted(nat.EXPORTS) == decl
+
+
+def test_degree_rule_table1():
+    rows = np.loadtxt(os.path.join(GOLD, "table1_degree_estimate.txt"))
+    for sigma, est in rows:
+        assert nat.range_degree(255.0, sigma) == int(est)
+    assert nat.range_degree(255.0, 20.0) == 66
+    assert nat.range_degree(255.0, 10.0) == 264
+    assert nat.range_degree(255.0, 25.0) == 43
+
+
+def test_coefficients_are_correctly_rounded_binomials():
+    for N in (1, 2, 7, 30, 43, 66, 264, 1024):
+        c = nat.range_coeffs(N)
+        assert len(c) == N // 2 + 1
+        for q, v in enumerate(c):
+            m = (N % 2) + 2 * q
+            n = (N - m) // 2
+            exact = math.comb(N, n) * (1 if m == 0 else 2)
+            ref = np.float32(exact / 2 ** N) if exact / 2 ** N > 1e-300 else np.float32(0)
+            # python's int/int division is correctly rounded to double; the
+            # float32 rounding of that double can differ from direct rounding
+            # only at a double-rounding tie, so allow one float32 ulp
+            assert abs(np.float32(v) - ref) <= np.spacing(ref) if ref != 0 else v == 0.0
+
+
+def test_coefficient_expansion_reproduces_cos_power():
+    t = np.linspace(-math.pi / 2, math.pi / 2, 1001)
+    for N in (5, 30, 66, 264):
+        c = np.array(nat.range_coeffs(N), dtype=np.float64)
+        m = (N % 2) + 2 * np.arange(c.size)
+        phi = (c[None, :] * np.cos(np.outer(t, m))).sum(axis=1)
+        assert np.max(np.abs(phi - np.cos(t) ** N)) < 2e-7
+        assert abs(c.sum() - 1.0) < 1e-6
+
+
+@pytest.mark.parametrize("sigma", [2.0, 3.7, 6.0, 10.0, 16.0, 30.0, 0.0])
+def test_spatial_gaussian_variance(sigma):
+    radii = nat.spatial_gaussian(sigma, 3)
+    var = sum(((2 * r + 1) ** 2 - 1) / 12.0 for r in radii)
+    # the best mix of two adjacent odd widths is within one width step
+    wl = 2 * min(radii) + 1
+    step = ((wl + 2) ** 2 - wl ** 2) / 12.0
+    assert abs(var - sigma ** 2) <= step / 2 + 1e-9
+    assert radii == sorted(radii)
+    assert max(radii) - min(radii) <= 1
+
+
+def test_spatial_gaussian_integer_sigmas():
+    assert nat.spatial_gaussian(10.0) == [9, 9, 10]
+    assert nat.spatial_gaussian(6.0) == [5, 5, 6]
+    assert nat.spatial_gaussian(30.0) == [29, 29, 30]
+
+
+FAKE = ctypes.c_void_p(0x10000000)
+FAKE2 = ctypes.c_void_p(0x20000000)
+
+
+def _fwd(f=FAKE, H=16, W=16, T=255.0, sr=30.0, radii=(2,), out=FAKE2, N=0, spec=None):
+    L = nat.lib()
+    s = spec if spec is not None else nat.SpatialSpec.of(radii)
+    o = nat.make_opts(None, N)
+    return L.bf_trig_forward_ex(f, H, W, T, sr, ctypes.byref(s), out, ctypes.byref(o))
+
+
+def test_validation_errors():
+    assert _fwd(f=None) == 1
+    assert _fwd(out=None) == 1
+    assert _fwd(H=0) == 1
+    assert _fwd(W=-3) == 1
+    assert _fwd(sr=0.0) == 1
+    assert _fwd(T=-1.0) == 1
+    assert _fwd(out=FAKE) == 1                      # aliasing f
+    assert _fwd(N=5, sr=30.0) == 2                  # below ceil((2T/(pi sr))^2) = 30
+    assert _fwd(N=5000) == 2
+    bad = nat.SpatialSpec()
+    bad.n_boxes = 0
+    assert _fwd(spec=bad) == 1
+    bad.n_boxes = 2
+    bad.radius[0], bad.radius[1] = 3, -1
+    assert _fwd(spec=bad) == 1
+    bad.radius[1] = 1000
+    assert _fwd(spec=bad) == 2
+    assert "BF_ERANGE" in nat.lib().bf_status_string(2).decode()
+    assert "radius" in nat.lib().bf_last_error().decode()
+
+
+def test_backward_and_direct_validation():
+    L = nat.lib()
+    s = nat.SpatialSpec.of([2])
+    o = nat.make_opts(None, 0)
+    assert L.bf_trig_backward(FAKE, None, FAKE, FAKE, 8, 8, 255.0, 30.0, ctypes.byref(s), FAKE2,
+                              ctypes.byref(o)) == 1
+    assert L.bf_trig_backward(FAKE, FAKE2, FAKE, FAKE, 8, 8, 255.0, 30.0, ctypes.byref(s), FAKE2,
+                              ctypes.byref(o)) == 1   # grad_f aliases out
+    assert L.bf_direct_forward(FAKE, 8, 8, 255.0, -2.0, ctypes.byref(s), FAKE2,
+                               ctypes.byref(o)) == 1
