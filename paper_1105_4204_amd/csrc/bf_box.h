@@ -1,0 +1,52 @@
+// Register-resident running box sums over a line held in a static array.
+//
+// A lane keeps one line (a row or a column of a tile) in registers and
+// applies the box stages of the separable spatial kernel in place.  The box
+// radius is a template parameter, so every index is a compile-time constant
+// and the line stays in VGPRs; box_dispatch() selects the instantiation for a
+// run-time radius with a wave-uniform switch.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace bf {
+
+constexpr int kBoxMaxRadius = 31;   // radii handled by the register-line kernels
+
+// v[i] <- sum_{d=0}^{2R} v[i+d] for i in [0, L-2R): the box of width 2R+1
+// whose output at i is centred at i + R.  Running sum s += (enter - leave);
+// the difference for the next output is taken before the current output
+// overwrites its slot, so each new sum lands in place without register moves.
+template <int L, int R>
+__device__ __forceinline__ void box_stage(float (&v)[L]) {
+    static_assert(2 * R < L, "line shorter than the box");
+    constexpr int W = 2 * R + 1;
+    float s = 0.0f;
+#pragma unroll
+    for (int d = 0; d < W; ++d) s += v[d];
+    float t = (W < L) ? v[W] - v[0] : 0.0f;
+    v[0] = s;
+#pragma unroll
+    for (int i = 1; i < L - 2 * R; ++i) {
+        const float tn = (i + W < L) ? v[i + W] - v[i] : 0.0f;
+        s += t;
+        v[i] = s;
+        t = tn;
+    }
+}
+
+// Applies box_stage<L, r> for a wave-uniform run-time r.  The candidates are
+// tried one after another, each in its own block separated by a compiler
+// barrier: a single multi-way branch would make the compiler merge 32 copies
+// of the line at one join and spill it, while a chain of two-way joins keeps
+// the line in the same registers.
+template <int L, int R = 0>
+__device__ __forceinline__ void box_dispatch(float (&v)[L], int r) {
+    if constexpr (R <= kBoxMaxRadius && 2 * R < L) {
+        if (r == R) box_stage<L, R>(v);
+        asm volatile("" ::: "memory");
+        box_dispatch<L, R + 1>(v, r);
+    }
+}
+
+}  // namespace bf
