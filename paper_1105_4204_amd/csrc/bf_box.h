@@ -35,16 +35,16 @@ __device__ __forceinline__ void box_stage(float (&v)[L]) {
     }
 }
 
-// Applies box_stage<L, r> for a wave-uniform run-time r.  The candidates are
-// tried one after another, each in its own block separated by a compiler
-// barrier: a single multi-way branch would make the compiler merge 32 copies
-// of the line at one join and spill it, while a chain of two-way joins keeps
-// the line in the same registers.
+// Applies box_stage<L, r> for a wave-uniform run-time r (held in an SGPR).
+// The candidates are tried one after another, each in its own block: the
+// empty asm makes r opaque between blocks, so the compiler cannot fold the
+// chain into one multi-way branch, whose single join would merge 32 copies of
+// the line and spill it; a chain of two-way joins keeps the line in place.
 template <int L, int R = 0>
 __device__ __forceinline__ void box_dispatch(float (&v)[L], int r) {
     if constexpr (R <= kBoxMaxRadius && 2 * R < L) {
         if (r == R) box_stage<L, R>(v);
-        asm volatile("" ::: "memory");
+        asm volatile("" : "+s"(r));
         box_dispatch<L, R + 1>(v, r);
     }
 }

@@ -1,0 +1,122 @@
+"""GPU parity of the fused adjoint kernel against the FP64 oracle.
+
+The oracle's gradient is the exact derivative of the direct window sum; it is
+itself pinned by finite differences in test_oracle_grad.  Tolerance (no value
+is given by the paper or the benchmark spec; derived from the FP32 arithmetic of
+the forward, whose outputs feed the adjoint): per pixel
+|g - g_ref| <= 1e-3 * max|g_ref| + 1e-3 * |g_ref|.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1105_4204_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def _ops():
+    from paper_1105_4204_amd import ops
+    return ops
+
+
+def _cuda(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).cuda()
+
+
+def _check(g, ref, what):
+    g = np.asarray(g, dtype=np.float64)
+    scale = np.abs(ref).max()
+    err = np.abs(g - ref)
+    tol = 1e-3 * scale + 1e-3 * np.abs(ref)
+    bad = int((err > tol).sum())
+    print(f"{what}: max_abs={err.max():.3e} scale={scale:.3e} bad={bad}/{err.size}", flush=True)
+    assert np.all(np.isfinite(g)), what
+    assert bad == 0, what
+
+
+CASES = [
+    (24, 31, 30.0, 0, [2]),
+    (29, 22, 25.0, 0, [1, 1, 2]),       # odd N = 43
+    (20, 26, 20.0, 0, [2, 2, 3]),       # even N = 66
+    (16, 40, 60.0, 9, [3]),
+    (1, 50, 30.0, 0, [3]),
+    (18, 18, 12.0, 0, [1, 1, 1]),       # N = 181
+]
+
+
+@pytest.mark.parametrize("case", CASES, ids=[f"{c[0]}x{c[1]}-sr{c[2]}-r{c[4]}" for c in CASES])
+def test_backward_small_full_parity(case):
+    H, W, sr, N, radii = case
+    print(f"case {case}", flush=True)
+    f = synth.piecewise_smooth(H, W, seed=H + 7 * W, n_shapes=3)
+    G = np.random.default_rng(H * W).normal(size=(H, W))
+    Nuse = N or oracle.range_degree(255.0, sr)
+    ref = oracle.grad(f, sr, Nuse, radii, G)
+    ops = _ops()
+    fg = _cuda(f)
+    out, eta = ops.trig_forward(fg, 255.0, sr, radii, N=N, return_eta=True)
+    gf = ops.trig_backward(fg, out, eta, _cuda(G), 255.0, sr, radii, N=N)
+    torch.cuda.synchronize()
+    _check(gf.cpu().numpy(), ref, f"grad {case}")
+
+
+def test_autograd_matches_explicit_backward():
+    f_np = synth.rectangles(40, 36, seed=3)
+    t_np = synth.rectangles(40, 36, seed=4)
+    ops = _ops()
+    f = _cuda(f_np).requires_grad_(True)
+    out = ops.bf_trig(f, 255.0, 25.0, (2, 2, 3))
+    loss = ((out - _cuda(t_np)) ** 2).sum()
+    loss.backward()
+    fd = _cuda(f_np)
+    o2, e2 = ops.trig_forward(fd, 255.0, 25.0, [2, 2, 3], return_eta=True)
+    g2 = ops.trig_backward(fd, o2, e2, 2.0 * (o2 - _cuda(t_np)), 255.0, 25.0, [2, 2, 3])
+    torch.cuda.synchronize()
+    assert torch.equal(f.grad, g2)
+
+
+def test_config4_ssd_gradient_vs_fd_and_oracle():
+    """Batch of 16 512x512 images, sigma_s = 6 (boxes 5,5,6), sigma_r = 25
+    (N = 43); loss = SSD to a second seeded image; dL/df on 32 random pixels
+    of image 0 against FP64 central differences and the oracle gradient; the
+    other 15 images checked against the oracle on 4 pixels each."""
+    fb, tb = synth.diff_batch(16)
+    radii, sr = [5, 5, 6], 25.0
+    N = oracle.range_degree(255.0, sr)
+    ops = _ops()
+    grads = []
+    for i in range(16):
+        f = _cuda(fb[i])
+        out, eta = ops.trig_forward(f, 255.0, sr, radii, return_eta=True)
+        grads.append(ops.trig_backward(f, out, eta, 2.0 * (out - _cuda(tb[i])), 255.0, sr, radii))
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(44)
+    idx = rng.integers(0, 512 * 512, size=32)
+    g0 = grads[0].cpu().numpy().reshape(-1)[idx]
+    fd = oracle.ssd_loss_fd(fb[0], tb[0], sr, N, radii, idx, h=1e-3)
+    fd2 = oracle.ssd_loss_fd(fb[0], tb[0], sr, N, radii, idx, h=5e-4)
+    ref = oracle.ssd_grad_at(fb[0], tb[0], sr, N, radii, idx)
+    scale = np.abs(ref).max()
+    assert np.max(np.abs(fd - fd2)) <= 1e-6 * scale + 1e-6
+    assert np.max(np.abs(ref - fd)) <= 1e-6 * scale + 1e-6
+    _check(g0, ref, "config4 image 0 (32 px) vs oracle")
+    _check(g0, fd, "config4 image 0 (32 px) vs FD")
+    for i in range(1, 16):
+        ii = rng.integers(0, 512 * 512, size=4)
+        ref_i = oracle.ssd_grad_at(fb[i], tb[i], sr, N, radii, ii)
+        gi = grads[i].cpu().numpy().reshape(-1)[ii]
+        err = np.abs(gi - ref_i)
+        assert np.all(err <= 1e-3 * max(np.abs(ref_i).max(), scale * 0.1) + 1e-3 * np.abs(ref_i)), i
+
+
+def test_backward_deterministic():
+    f = _cuda(synth.piecewise_smooth(200, 190, seed=5))
+    ops = _ops()
+    out, eta = ops.trig_forward(f, 255.0, 20.0, [9, 9, 10], return_eta=True)
+    G = torch.randn_like(f)
+    a = ops.trig_backward(f, out, eta, G, 255.0, 20.0, [9, 9, 10])
+    b = ops.trig_backward(f, out, eta, G, 255.0, 20.0, [9, 9, 10])
+    torch.cuda.synchronize()
+    assert torch.equal(a, b)
