@@ -117,17 +117,29 @@ bf_status bf_direct_forward(const float* f, int64_t H, int64_t W, float T, float
                             const bf_opts* opts);
 
 /* ---- batches of images of different sizes and parameters ------------------
- * A plan fixes the images' sizes and parameters and owns every device table
- * and workspace; bf_batch_bind attaches device buffers (pointer arrays in host
- * memory, n entries each; target/grad_f/loss may be NULL for a forward-only
- * batch); bf_batch_launch enqueues the whole batch -- forward, SSD loss
- * gradient 2(out - target) and adjoint -- as one persistent kernel, allocates
- * and synchronises nothing, and may be captured into a hipGraph.  */
+ * For callers that filter many images (e.g. the colour channels of Fig. 4 or
+ * a training batch) in one launch.  A plan fixes the images' sizes and
+ * parameters and owns every device table and workspace it needs.
+ * bf_batch_bind attaches the caller's device buffers (host arrays of n device
+ * pointers each; it uploads them synchronously and may not be called during
+ * stream capture).  With target and grad_f non-NULL the batch computes, per
+ * image, out = BF(f), the SSD loss sum((out - target)^2) (into loss[i] if loss
+ * is non-NULL) and grad_f = d loss / d f; eta must then be non-NULL.  With
+ * grad_f NULL only the forward runs.  bf_batch_launch enqueues the whole batch
+ * as one persistent work-queue kernel (plus a tiny counter-reset kernel) on
+ * stream: forward tiles first, longest first, then the per-image loss
+ * reductions, then the adjoint tiles, each of which waits (bounded) until all
+ * forward tiles of its image are done.  It allocates and synchronises
+ * nothing, so it may be captured into a hipGraph and replayed.
+ * bf_batch_check synchronises the device and reports BF_EDEVICE if a wait in
+ * the last launch hit its bound (the results are then invalid). */
 typedef struct {
     int64_t H, W;
     float T, sigma_r;
     int32_t N;                   /* 0 = automatic degree */
     bf_spatial_spec spatial;
+    int32_t tile_h, tile_w;      /* forward tile; 0 = library choice */
+    int32_t bwd_tile_h, bwd_tile_w; /* adjoint tile; 0 = library choice */
 } bf_image_desc;
 
 typedef struct bf_batch_plan bf_batch_plan;
@@ -135,8 +147,9 @@ typedef struct bf_batch_plan bf_batch_plan;
 bf_status bf_batch_plan_create(const bf_image_desc* descs, int32_t n, bf_batch_plan** plan);
 bf_status bf_batch_bind(bf_batch_plan* plan, const float* const* f, const float* const* target,
                         float* const* out, float* const* eta, float* const* grad_f,
-                        float* loss /* device, n floats: per-image SSD, or NULL */);
+                        float* loss /* device, n floats, or NULL */);
 bf_status bf_batch_launch(bf_batch_plan* plan, void* stream);
+bf_status bf_batch_check(bf_batch_plan* plan);
 void bf_batch_plan_destroy(bf_batch_plan* plan);
 
 const char* bf_status_string(bf_status s);

@@ -23,8 +23,8 @@ STATUS = {0: "BF_OK", 1: "BF_EINVAL", 2: "BF_ERANGE", 3: "BF_ENOMEM", 4: "BF_EDE
 # exported symbols, in the order include/bf_trig.h declares them
 EXPORTS = ["bf_range_degree", "bf_range_coeffs", "bf_spatial_gaussian", "bf_trig_forward",
            "bf_trig_forward_ex", "bf_trig_backward", "bf_direct_forward",
-           "bf_batch_plan_create", "bf_batch_bind", "bf_batch_launch", "bf_batch_plan_destroy",
-           "bf_status_string", "bf_last_error"]
+           "bf_batch_plan_create", "bf_batch_bind", "bf_batch_launch", "bf_batch_check",
+           "bf_batch_plan_destroy", "bf_status_string", "bf_last_error"]
 
 
 class BFError(RuntimeError):
@@ -59,7 +59,9 @@ class Opts(ctypes.Structure):
 
 class ImageDesc(ctypes.Structure):
     _fields_ = [("H", ctypes.c_int64), ("W", ctypes.c_int64), ("T", ctypes.c_float),
-                ("sigma_r", ctypes.c_float), ("N", ctypes.c_int32), ("spatial", SpatialSpec)]
+                ("sigma_r", ctypes.c_float), ("N", ctypes.c_int32), ("spatial", SpatialSpec),
+                ("tile_h", ctypes.c_int32), ("tile_w", ctypes.c_int32),
+                ("bwd_tile_h", ctypes.c_int32), ("bwd_tile_w", ctypes.c_int32)]
 
 
 _lib = None
@@ -89,6 +91,7 @@ def lib():
         "bf_batch_bind": [vp, ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(vp),
                           ctypes.POINTER(vp), ctypes.POINTER(vp), vp],
         "bf_batch_launch": [vp, vp],
+        "bf_batch_check": [vp],
         "bf_batch_plan_destroy": [vp],
     }
     for name, args in sig.items():

@@ -1,0 +1,124 @@
+"""Tile-shape autotuner for the fused kernels.
+
+For a (spatial radii, degree N, mode) key it times a few candidate output
+tiles of the fused forward / adjoint kernel on a synthetic image (median of
+several launches timed with HIP events) and keeps the fastest.  Results are
+cached in a JSON file (BF_TUNE_CACHE, default ~/.cache/bftrig/tune.json) keyed
+by device name, so a batch plan reuses them without re-timing.  Candidates
+are odd tile sides (odd LDS pitches) that fit the kernel's limits; invalid
+ones are rejected by the library and skipped.
+"""
+from __future__ import annotations
+
+import json
+import os
+import statistics
+
+import torch
+
+from . import _native as nat
+from . import ops, synth
+
+DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "bftrig", "tune.json")
+
+
+class Tuner:
+    def __init__(self, cache_path: str | None = None, reps: int = 5, probe_hw: int = 384):
+        self.path = cache_path or os.environ.get("BF_TUNE_CACHE", DEFAULT_CACHE)
+        self.reps = reps
+        self.probe_hw = probe_hw
+        self.table = {}
+        if os.path.exists(self.path):
+            try:
+                with open(self.path) as fh:
+                    self.table = json.load(fh)
+            except (OSError, ValueError):
+                self.table = {}
+
+    @staticmethod
+    def _radii(spec):
+        r = spec.get("radii")
+        if r is None:
+            r = nat.spatial_gaussian(float(spec["sigma_s"]), int(spec.get("n_boxes", 3)))
+        return [int(x) for x in r]
+
+    def key(self, spec, mode):
+        T = float(spec.get("T", 255.0))
+        N = int(spec.get("N", 0)) or nat.range_degree(T, float(spec["sigma_r"]))
+        nbucket = 1 << max(0, (N - 1).bit_length())          # N rounded up to a power of 2
+        dev = torch.cuda.get_device_name(0) if torch.cuda.is_available() else "cpu"
+        return f"{dev}|{mode}|r={','.join(map(str, self._radii(spec)))}|N<={nbucket}"
+
+    def candidates(self, R, mode):
+        """Odd square and near-square tiles whose extended tile fits a line."""
+        ext_max = 48 * 256 if mode == "fwd" else 40 * 256
+        smax = 0
+        for s in range(1, 129, 2):
+            if s + 2 * R <= 128 and (s + 2 * R) ** 2 <= ext_max:
+                smax = s
+        if smax == 0:
+            return []
+        cands = []
+        for dh, dw in ((0, 0), (-8, 0), (0, -8), (-8, -8), (-16, -16), (-32, -32)):
+            th, tw = smax + dh, smax + dw
+            if th >= 1 and tw >= 1 and (th, tw) not in cands:
+                cands.append((th, tw))
+        return cands
+
+    def _time(self, fn):
+        fn()
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(self.reps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            fn()
+            e1.record()
+            torch.cuda.synchronize()
+            ts.append(e0.elapsed_time(e1))
+        return statistics.median(ts)
+
+    def tune(self, spec, mode="fwd"):
+        k = self.key(spec, mode)
+        if k in self.table:
+            return tuple(self.table[k]["tile"])
+        radii = self._radii(spec)
+        R = sum(radii)
+        T = float(spec.get("T", 255.0))
+        sr = float(spec["sigma_r"])
+        N = int(spec.get("N", 0))
+        hw = self.probe_hw
+        f = torch.from_numpy(synth.piecewise_smooth(hw, hw, seed=99)).cuda()
+        out, eta = ops.trig_forward(f, T, sr, radii, N=N, return_eta=True)
+        G = torch.randn_like(f)
+        best = None
+        for tile in self.candidates(R, mode):
+            try:
+                if mode == "fwd":
+                    t = self._time(lambda: ops.trig_forward(f, T, sr, radii, N=N, tile=tile))
+                else:
+                    t = self._time(lambda: ops.trig_backward(f, out, eta, G, T, sr, radii, N=N,
+                                                             tile=tile))
+            except nat.BFError:
+                continue
+            # cost per output pixel: tiles do not divide the probe exactly
+            if best is None or t < best[0]:
+                best = (t, tile)
+        if best is None:
+            return (0, 0)
+        self.table[k] = {"tile": list(best[1]), "ms": best[0]}
+        self.save()
+        return best[1]
+
+    def tile_for(self, spec, mode):
+        k = self.key(spec, mode)
+        if k in self.table:
+            return tuple(self.table[k]["tile"])
+        return None
+
+    def save(self):
+        os.makedirs(os.path.dirname(self.path), exist_ok=True)
+        tmp = self.path + ".tmp"
+        with open(tmp, "w") as fh:
+            json.dump(self.table, fh, indent=1, sort_keys=True)
+        os.replace(tmp, self.path)

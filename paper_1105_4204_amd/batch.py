@@ -1,0 +1,121 @@
+"""Batched persistent launch over many images of different sizes and
+parameters (C ABI bf_batch_*), capturable into a HIP graph.
+
+``BatchPlan(specs)`` fixes sizes and parameters; ``bind`` attaches torch
+tensors (allocated by the caller or by ``allocate``); ``launch`` enqueues the
+forward, per-image SSD loss and adjoint of every image as one persistent
+kernel on the current stream.  All arithmetic runs in libbftrig.
+"""
+from __future__ import annotations
+
+import ctypes
+
+import torch
+
+from . import _native as nat
+
+
+def _spec_desc(s) -> nat.ImageDesc:
+    d = nat.ImageDesc()
+    d.H, d.W = int(s["H"]), int(s["W"])
+    d.T = float(s.get("T", 255.0))
+    d.sigma_r = float(s["sigma_r"])
+    d.N = int(s.get("N", 0))
+    radii = s.get("radii")
+    if radii is None:
+        radii = nat.spatial_gaussian(float(s["sigma_s"]), int(s.get("n_boxes", 3)))
+    d.spatial = nat.SpatialSpec.of(radii)
+    th, tw = s.get("tile") or (0, 0)
+    bh, bw = s.get("bwd_tile") or (0, 0)
+    d.tile_h, d.tile_w, d.bwd_tile_h, d.bwd_tile_w = int(th), int(tw), int(bh), int(bw)
+    return d
+
+
+class BatchPlan:
+    """A plan for one fixed list of images; see include/bf_trig.h."""
+
+    def __init__(self, specs, tuner=None):
+        specs = [dict(s) for s in specs]
+        if tuner is not None:
+            for s in specs:
+                s.setdefault("tile", tuner.tile_for(s, "fwd"))
+                s.setdefault("bwd_tile", tuner.tile_for(s, "bwd"))
+        self.specs = specs
+        arr = (nat.ImageDesc * len(specs))(*[_spec_desc(s) for s in specs])
+        self._descs = arr
+        h = ctypes.c_void_p()
+        nat.check(nat.lib().bf_batch_plan_create(arr, len(specs), ctypes.byref(h)),
+                  "bf_batch_plan_create")
+        self._h = h
+        self._bound = None
+
+    def __len__(self):
+        return len(self.specs)
+
+    def allocate(self, device="cuda", backward=True):
+        """Output tensors matching the plan (out, eta, grad_f, loss)."""
+        out = [torch.empty(s["H"], s["W"], device=device) for s in self.specs]
+        eta = [torch.empty_like(o) for o in out]
+        gf = [torch.empty_like(o) for o in out] if backward else None
+        loss = torch.empty(len(self.specs), device=device)
+        return out, eta, gf, loss
+
+    def bind(self, f, target=None, out=None, eta=None, grad_f=None, loss=None):
+        n = len(self.specs)
+
+        def arr(xs, name, required):
+            if xs is None:
+                if required:
+                    raise ValueError(f"{name} is required")
+                return None
+            if len(xs) != n:
+                raise ValueError(f"{name}: expected {n} tensors")
+            for x, s in zip(xs, self.specs):
+                if (not x.is_cuda or x.dtype != torch.float32 or not x.is_contiguous()
+                        or tuple(x.shape) != (s["H"], s["W"])):
+                    raise TypeError(f"{name}: need contiguous float32 CUDA tensors of the "
+                                    "planned shapes")
+            return (ctypes.c_void_p * n)(*[x.data_ptr() for x in xs])
+
+        pf = arr(f, "f", True)
+        pt = arr(target, "target", False)
+        po = arr(out, "out", True)
+        pe = arr(eta, "eta", False)
+        pg = arr(grad_f, "grad_f", False)
+        ploss = ctypes.c_void_p(loss.data_ptr()) if loss is not None else None
+        nat.check(nat.lib().bf_batch_bind(self._h, pf, pt, po, pe, pg, ploss), "bf_batch_bind")
+        # keep the tensors alive while bound
+        self._bound = (f, target, out, eta, grad_f, loss)
+
+    def launch(self, stream=None):
+        s = stream if stream is not None else torch.cuda.current_stream()
+        nat.check(nat.lib().bf_batch_launch(self._h, ctypes.c_void_p(s.cuda_stream)),
+                  "bf_batch_launch")
+
+    def check(self):
+        nat.check(nat.lib().bf_batch_check(self._h), "bf_batch_check")
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            nat.lib().bf_batch_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def capture(plan: BatchPlan, warmup: int = 1) -> torch.cuda.CUDAGraph:
+    """Capture plan.launch() into a graph (after `warmup` eager launches)."""
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        for _ in range(warmup):
+            plan.launch(s)
+    torch.cuda.current_stream().wait_stream(s)
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        plan.launch()
+    return g

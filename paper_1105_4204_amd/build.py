@@ -8,7 +8,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libbftrig.so")
-SOURCES = ["bf_host.cpp", "bf_api.cpp", "bf_batch.cpp", "bf_tile.hip",
+SOURCES = ["bf_host.cpp", "bf_api.cpp", "bf_batch.hip", "bf_tile.hip",
            "bf_direct.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

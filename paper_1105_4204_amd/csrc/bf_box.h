@@ -42,6 +42,7 @@ __device__ __forceinline__ void box_stage(float (&v)[L]) {
 // the line and spill it; a chain of two-way joins keeps the line in place.
 template <int L, int R = 0>
 __device__ __forceinline__ void box_dispatch(float (&v)[L], int r) {
+    if constexpr (R == 0) r = __builtin_amdgcn_readfirstlane(r);
     if constexpr (R <= kBoxMaxRadius && 2 * R < L) {
         if (r == R) box_stage<L, R>(v);
         asm volatile("" : "+s"(r));

@@ -1,0 +1,145 @@
+"""GPU tests of the batched persistent launch (ragged images, per-image
+sigma_s, sigma_r and N) and of its capture into a HIP graph.
+
+Each image of a batch must equal the single-image forward and adjoint kernels
+bit for bit (the batch runs the same tile code with the same tile shapes), the
+per-image SSD loss must equal the sum of squared differences of its outputs,
+and a sample of the ragged workload is checked against the FP64 oracle.
+Graph replays are compared with the eager result after each replay, with
+eager work on the stream between replays.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1105_4204_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def _mods():
+    from paper_1105_4204_amd import batch, ops
+    return batch, ops
+
+
+def _cuda(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).cuda()
+
+
+SPECS = [
+    dict(H=97, W=131, sigma_s=3.0, sigma_r=30.0),
+    dict(H=64, W=64, radii=[5], sigma_r=60.0),
+    dict(H=150, W=80, sigma_s=6.0, sigma_r=25.0),
+    dict(H=33, W=200, sigma_s=2.0, sigma_r=12.0),
+    dict(H=1, W=77, radii=[3], sigma_r=40.0),
+    dict(H=260, W=211, sigma_s=10.0, sigma_r=20.0),
+]
+
+
+def _run_batch(specs, seed0=100):
+    batch, ops = _mods()
+    f = [_cuda(synth.piecewise_smooth(s["H"], s["W"], seed=seed0 + i, n_shapes=3))
+         for i, s in enumerate(specs)]
+    t = [_cuda(synth.piecewise_smooth(s["H"], s["W"], seed=seed0 + 50 + i, n_shapes=3))
+         for i, s in enumerate(specs)]
+    plan = batch.BatchPlan(specs)
+    out, eta, gf, loss = plan.allocate()
+    plan.bind(f, t, out, eta, gf, loss)
+    plan.launch()
+    plan.check()
+    return plan, f, t, out, eta, gf, loss
+
+
+def test_batch_matches_single_image_kernels():
+    batch, ops = _mods()
+    plan, f, t, out, eta, gf, loss = _run_batch(SPECS)
+    from paper_1105_4204_amd import _native as nat
+    for i, s in enumerate(SPECS):
+        radii = s.get("radii") or nat.spatial_gaussian(s["sigma_s"], 3)
+        o1, e1 = ops.trig_forward(f[i], 255.0, s["sigma_r"], radii, return_eta=True)
+        g1 = ops.trig_backward(f[i], o1, e1, 2.0 * (o1 - t[i]), 255.0, s["sigma_r"], radii)
+        torch.cuda.synchronize()
+        print(f"image {i} {s}: out eq={torch.equal(o1, out[i])} grad eq={torch.equal(g1, gf[i])}",
+              flush=True)
+        assert torch.equal(o1, out[i]), i
+        assert torch.equal(e1, eta[i]), i
+        assert torch.equal(g1, gf[i]), i
+        ssd = float(((out[i].double() - t[i].double()) ** 2).sum())
+        assert abs(float(loss[i]) - ssd) <= 1e-5 * ssd + 1e-3, (i, float(loss[i]), ssd)
+
+
+def test_batch_forward_only_and_rebind():
+    batch, ops = _mods()
+    plan = batch.BatchPlan(SPECS[:3])
+    f = [_cuda(synth.rectangles(s["H"], s["W"], seed=7 + i)) for i, s in enumerate(SPECS[:3])]
+    out, eta, _, _ = plan.allocate(backward=False)
+    plan.bind(f, out=out)
+    plan.launch()
+    plan.check()
+    from paper_1105_4204_amd import _native as nat
+    for i, s in enumerate(SPECS[:3]):
+        radii = s.get("radii") or nat.spatial_gaussian(s["sigma_s"], 3)
+        assert torch.equal(ops.trig_forward(f[i], 255.0, s["sigma_r"], radii), out[i])
+    # rebind to new buffers
+    f2 = [x.flip(0).contiguous() for x in f]
+    out2 = [torch.empty_like(x) for x in out]
+    plan.bind(f2, out=out2)
+    plan.launch()
+    plan.check()
+    for i, s in enumerate(SPECS[:3]):
+        radii = s.get("radii") or nat.spatial_gaussian(s["sigma_s"], 3)
+        assert torch.equal(ops.trig_forward(f2[i], 255.0, s["sigma_r"], radii), out2[i])
+
+
+def test_batch_graph_replay():
+    batch, ops = _mods()
+    plan, f, t, out, eta, gf, loss = _run_batch(SPECS, seed0=300)
+    torch.cuda.synchronize()
+    ref_out = [o.clone() for o in out]
+    ref_gf = [g.clone() for g in gf]
+    ref_loss = loss.clone()
+    g = batch.capture(plan)
+    for rep in range(3):
+        for o in out:
+            o.fill_(-1.0)          # eager work between replays
+        for x in gf:
+            x.zero_()
+        loss.fill_(0.0)
+        g.replay()
+        torch.cuda.synchronize()
+        for i in range(len(SPECS)):
+            assert torch.equal(out[i], ref_out[i]), (rep, i)
+            assert torch.equal(gf[i], ref_gf[i]), (rep, i)
+        assert torch.equal(loss, ref_loss), rep
+
+
+def test_ragged_workload_sample_vs_oracle():
+    """24 images drawn like the 256-image ragged workload (H, W in [64,1024],
+    sigma_s in [2,16], sigma_r in [10,60]); per image 24 random pixels of the
+    forward and 6 of the SSD gradient against the FP64 oracle."""
+    batch, ops = _mods()
+    specs = synth.ragged_batch_specs(24, seed=5)
+    fs, ts = synth.ragged_batch_images(specs)
+    plan = batch.BatchPlan(specs)
+    out, eta, gf, loss = plan.allocate()
+    plan.bind([_cuda(x) for x in fs], [_cuda(x) for x in ts], out, eta, gf, loss)
+    plan.launch()
+    plan.check()
+    torch.cuda.synchronize()
+    from paper_1105_4204_amd import _native as nat
+    rng = np.random.default_rng(11)
+    for i, s in enumerate(specs):
+        radii = nat.spatial_gaussian(s["sigma_s"], 3)
+        N = oracle.range_degree(255.0, s["sigma_r"])
+        H, W = s["H"], s["W"]
+        idx = rng.integers(0, H * W, size=24)
+        ref = oracle.forward_at(fs[i], s["sigma_r"], N, radii, idx)
+        got = out[i].cpu().numpy().reshape(-1)[idx].astype(np.float64)
+        err = np.abs(got - ref)
+        assert np.all(err <= 1e-2 + 1e-4 * np.abs(ref)), (i, s, err.max())
+        gidx = rng.integers(0, H * W, size=6)
+        gref = oracle.ssd_grad_at(fs[i], ts[i], s["sigma_r"], N, radii, gidx)
+        gg = gf[i].cpu().numpy().reshape(-1)[gidx].astype(np.float64)
+        scale = max(np.abs(gref).max(), 1e-6)
+        assert np.all(np.abs(gg - gref) <= 1e-3 * scale + 1e-3 * np.abs(gref) + 2e-3), (i, gg, gref)
