@@ -43,29 +43,50 @@ WORKLOADS = {
                          "sigma_r=25, N=43"),
 }
 
-# HBM bytes per launch of the forward kernel measured with rocprofv3 --pmc
-# FETCH_SIZE / WRITE_SIZE on the config2 workload, scaled by a copy-kernel
-# calibration; valid only for the kernel source they were taken on.
+# HBM bytes per launch of the fused kernels measured with rocprofv3 --pmc
+# FETCH_SIZE and WRITE_SIZE (separate runs), each scaled by the factor that
+# maps the same counter of a plain copy kernel onto its known size; valid only
+# for the kernel sources they were taken on (hash of TILE_SOURCES).
 MEASURED_TRAFFIC = {}
+TILE_SOURCES = ("bf_tile.h", "bf_box.h", "bf_tile.hip")
 
 
-def _src_hash(name: str) -> str:
-    p = os.path.join(ROOT, "paper_1105_4204_amd", "csrc", name)
-    return hashlib.sha1(open(p, "rb").read()).hexdigest()[:12]
+def _src_hash(names=TILE_SOURCES) -> str:
+    h = hashlib.sha1()
+    for name in names:
+        with open(os.path.join(ROOT, "paper_1105_4204_amd", "csrc", name), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:12]
 
 
-def fwd_flops_per_pixel(N: int, nb: int) -> int:
+def copy_calibration(mib: int = 512, reps: int = 3):
+    """A plain device copy of `mib` MiB (torch's copy kernel), for scaling the
+    FETCH_SIZE / WRITE_SIZE counters: each launch reads and writes exactly
+    mib MiB."""
+    import torch
+    n = mib * (1 << 20) // 4
+    src = torch.ones(n, device="cuda:0")
+    dst = torch.empty_like(src)
+    for _ in range(reps):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_calibration_bytes": n * 4, "reps": reps,
+                      "src_hash": _src_hash()}), flush=True)
+
+
+def fwd_flops_per_pixel(N: int, nb: int, aux: bool = False) -> int:
     """Algorithmic FP32 flops per output pixel of one forward (FMA = 2).
 
     Per cosine pair with m > 0: phase step z <- z*u (complex multiply, 6),
     modulated products g*C, g*S (2), four channels filtered by nb boxes in two
     directions with running sums (4 * nb * 2 * 2), demodulation and
-    accumulation into num and den (2 * 5).  The centre pair (m = 0, even N)
+    accumulation into num and den (4 FMA = 8).  With the auxiliary sums P, Q
+    of the adjoint, four more FMAs (8).  The centre pair (m = 0, even N)
     filters two channels (1, g) and accumulates 2 * 2.
     """
     pairs = N // 2 + 1
     full = pairs - (0 if N % 2 else 1)
-    per_pair = 6 + 2 + 16 * nb + 10
+    per_pair = 6 + 2 + 16 * nb + 8 + (8 if aux else 0)
     centre = 0 if N % 2 else (8 * nb + 4)
     return full * per_pair + centre
 
@@ -73,17 +94,17 @@ def fwd_flops_per_pixel(N: int, nb: int) -> int:
 def bwd_flops_per_pixel(N: int, nb: int) -> int:
     """Algorithmic flops per pixel of the adjoint (FMA = 2).
 
-    Per pair with m > 0: phase step (6), six modulated products A*C, A*S,
-    B*C, B*S, g*C, g*S (6), eight channels filtered by nb boxes in two
-    directions (8 * nb * 2 * 2), eight coefficients (about 3 flops each, 24)
-    and eight accumulations (8 * 2).  The centre pair filters A alone
-    (4 * nb + 2).
+    Per pair with m > 0: phase step of Y = A Z (6), modulated products h*Re Y,
+    h*Im Y (2), four channels filtered by nb boxes in two directions
+    (4 * nb * 2 * 2), four coefficients (C - ma g S, S + ma g C: 4 each; ma S,
+    ma C: 1 each) and four accumulations (4 * 2).  The centre pair filters A
+    alone (4 * nb + 2).  Plus the per-pixel closing term a (A P - B Q) (6).
     """
     pairs = N // 2 + 1
     full = pairs - (0 if N % 2 else 1)
-    per_pair = 6 + 6 + 32 * nb + 24 + 16
+    per_pair = 6 + 2 + 16 * nb + 10 + 8
     centre = 0 if N % 2 else (4 * nb + 2)
-    return full * per_pair + centre
+    return full * per_pair + centre + 6
 
 
 def batch_bench(reps: int = 3):
@@ -148,6 +169,8 @@ def main():
     ap.add_argument("--no-direct", action="store_true")
     ap.add_argument("--fwd-only", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a 512 MiB device copy (counter calibration) and exit")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -157,6 +180,10 @@ def main():
                                    "images), but no multi-GPU path is built; run with --gpus 1"}),
               flush=True)
         sys.exit(2)
+
+    if args.copy_calibration:
+        copy_calibration()
+        return
 
     import numpy as np
     import torch
@@ -182,24 +209,29 @@ def main():
     stream = torch.cuda.current_stream()
     do_bwd = not args.fwd_only
     try:
-        ops.trig_backward(f, f.clone(), torch.ones_like(f), torch.zeros_like(f), T, sr, radii)
+        ops.trig_forward(f, T, sr, radii, return_aux=True)
     except _native.BFError as e:
         if e.code == 6:
             do_bwd = False
         else:
             raise
 
+    # the training step: forward (with the sums the adjoint needs) + adjoint
+    # of the SSD loss; events on the launch stream around each kernel
     def step(ev=None):
         if ev is not None:
             ev[0].record(stream)
-        out, eta = ops.trig_forward(f, T, sr, radii, return_eta=True)
+        if do_bwd:
+            out, eta, aux = ops.trig_forward(f, T, sr, radii, return_aux=True)
+        else:
+            out = ops.trig_forward(f, T, sr, radii)
         if ev is not None:
             ev[1].record(stream)
         if do_bwd:
             g = 2.0 * (out - target)
             if ev is not None:
                 ev[2].record(stream)
-            gf = ops.trig_backward(f, out, eta, g, T, sr, radii)
+            gf = ops.trig_backward(f, out, eta, aux, g, T, sr, radii)
             if ev is not None:
                 ev[3].record(stream)
             return gf
@@ -219,8 +251,20 @@ def main():
     wall = time.perf_counter() - t0
     total_ms = start.elapsed_time(end)
     ms_step = total_ms / args.steps
-    fwd_ms = float(np.mean([e[0].elapsed_time(e[1]) for e in evs]))
+    step_fwd_ms = float(np.mean([e[0].elapsed_time(e[1]) for e in evs]))
     bwd_ms = float(np.mean([e[2].elapsed_time(e[3]) for e in evs])) if do_bwd else None
+
+    # inference forward alone (no auxiliary sums)
+    out_buf = torch.empty_like(f)
+    ops.trig_forward(f, T, sr, radii, out=out_buf)
+    torch.cuda.synchronize()
+    fevs = [[torch.cuda.Event(enable_timing=True) for _ in range(2)] for _ in range(args.steps)]
+    for k in range(args.steps):
+        fevs[k][0].record(stream)
+        ops.trig_forward(f, T, sr, radii, out=out_buf)
+        fevs[k][1].record(stream)
+    torch.cuda.synchronize()
+    fwd_ms = float(np.mean([e[0].elapsed_time(e[1]) for e in fevs]))
 
     mpix = H * W / 1e6
     value = mpix / (ms_step / 1e3)
@@ -241,23 +285,26 @@ def main():
         direct = {"ms": direct_ms, "mpix_s": mpix / (direct_ms / 1e3),
                   "fwd_speedup_vs_direct": direct_ms / fwd_ms}
 
-    # dominant kernel: the fused forward (the backward once present is timed too)
+    # dominant kernel of the step: the forward with auxiliary sums or the adjoint
     fwd_flops = fwd_flops_per_pixel(N, nb) * H * W
-    dom = ("bf_fwd_kernel", fwd_ms, fwd_flops)
-    if do_bwd and bwd_ms is not None and bwd_ms > fwd_ms:
-        dom = ("bf_bwd_kernel", bwd_ms, bwd_flops_per_pixel(N, nb) * H * W)
+    dom = ("bf_tile_kernel<kForward,false>", fwd_ms, fwd_flops)
+    if do_bwd:
+        dom = ("bf_tile_kernel<kForward,true>", step_fwd_ms,
+               fwd_flops_per_pixel(N, nb, aux=True) * H * W)
+        if bwd_ms > step_fwd_ms:
+            dom = ("bf_tile_kernel<kBackward,false>", bwd_ms, bwd_flops_per_pixel(N, nb) * H * W)
     name, kms, kflops = dom
     achieved = kflops / (kms / 1e3) / 1e12
-    src = {"bf_fwd_kernel": "bf_fwd.hip", "bf_bwd_kernel": "bf_bwd.hip"}[name]
     tr = MEASURED_TRAFFIC.get((name, args.workload))
-    traffic = tr["bytes"] if tr and tr["src"] == _src_hash(src) else None
+    traffic = tr["bytes"] if tr and tr["src"] == _src_hash() else None
     roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP32_TFLOPS,
                 "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_TFLOPS, 4),
                 "traffic": traffic, "kernel": name, "kernel_ms": round(kms, 4),
                 "flops_per_launch": kflops}
-    fwd_bytes = 12 * H * W       # read f, write out and eta
-    bwd_bytes = 20 * H * W       # read f, out, eta, grad_out; write grad_f
-    step_bytes = fwd_bytes + (bwd_bytes if do_bwd else 0)
+    fwd_bytes = 8 * H * W        # inference: read f, write out
+    fwd_aux_bytes = 20 * H * W   # training: read f; write out, eta, P, Q
+    bwd_bytes = 28 * H * W       # read f, out, eta, P, Q, grad_out; write grad_f
+    step_bytes = (fwd_aux_bytes + bwd_bytes) if do_bwd else fwd_bytes
     hbm = {"algorithmic_bytes_per_step": step_bytes,
            "achieved_GBs": round(step_bytes / (ms_step / 1e3) / 1e9, 2),
            "peak_GBs": PEAK_HBM_GBS,
@@ -288,6 +335,7 @@ def main():
                    "T": T, "N": N, "step": "fwd+bwd" if do_bwd else "fwd"},
         "fwd_mpix_s": round(fwd_mpix, 3),
         "fwd_ms": round(fwd_ms, 4),
+        "fwd_aux_ms": round(step_fwd_ms, 4) if do_bwd else None,
         "bwd_ms": round(bwd_ms, 4) if bwd_ms is not None else None,
         "fwd_bwd_mpix_s": round(value, 3) if do_bwd else None,
         "direct_gpu": direct,

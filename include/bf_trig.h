@@ -71,6 +71,9 @@ typedef struct {
                             needs it); NULL = not written */
     int32_t tile_h;      /* 0 = library choice; else output tile rows */
     int32_t tile_w;      /* 0 = library choice; else output tile columns */
+    float* aux_out;      /* forward only: optional 2*H*W device buffer for the
+                            two auxiliary sums the backward needs (see
+                            bf_trig_backward); NULL = not computed */
 } bf_opts;
 
 /* Algorithm 1 steps 1-2: N = ceil((gamma sigma_r)^-2), gamma = pi/(2T).
@@ -101,12 +104,17 @@ bf_status bf_trig_forward_ex(const float* f, int64_t H, int64_t W, float T, floa
                              const bf_opts* opts);
 
 /* Adjoint: grad_f = (d out / d f)^T grad_out, the exact derivative of eq.
- * (BF)/(normalization) for the raised-cosine kernel.  out and eta are the
- * forward's outputs for the same f and parameters (opts->N must match).
- * All five buffers are H*W; grad_f must not overlap the inputs. */
+ * (BF)/(normalization) for the raised-cosine kernel, evaluated term by term
+ * on the expansion of eq. (final-form).  out, eta and aux are the forward's
+ * outputs for the same f and parameters (opts->N must match): aux holds the
+ * planes P = sum_m c_m m (C_m F[g S_m] - S_m F[g C_m]) and
+ * Q = sum_m c_m m (C_m F[S_m] - S_m F[C_m]) (g = f - T/2, C_m + j S_m =
+ * exp(j m alpha g)), which the forward writes to opts->aux_out.  f, out, eta,
+ * grad_out and grad_f are H*W, aux 2*H*W; grad_f must not overlap the
+ * inputs.  opts->aux_out is ignored. */
 bf_status bf_trig_backward(const float* f, const float* out, const float* eta,
-                           const float* grad_out, int64_t H, int64_t W, float T,
-                           float sigma_r, const bf_spatial_spec* spatial_spec,
+                           const float* aux, const float* grad_out, int64_t H, int64_t W,
+                           float T, float sigma_r, const bf_spatial_spec* spatial_spec,
                            float* grad_f, const bf_opts* opts);
 
 /* Direct-window filter: the same eq. (BF)/(normalization) summed pixel by

@@ -54,7 +54,7 @@ class SpatialSpec(ctypes.Structure):
 class Opts(ctypes.Structure):
     _fields_ = [("stream", ctypes.c_void_p), ("N", ctypes.c_int32),
                 ("eta_out", ctypes.c_void_p), ("tile_h", ctypes.c_int32),
-                ("tile_w", ctypes.c_int32)]
+                ("tile_w", ctypes.c_int32), ("aux_out", ctypes.c_void_p)]
 
 
 class ImageDesc(ctypes.Structure):
@@ -85,7 +85,7 @@ def lib():
         "bf_spatial_gaussian": [f64, i32, sp],
         "bf_trig_forward": [vp, i64, i64, f32, f32, sp, vp],
         "bf_trig_forward_ex": [vp, i64, i64, f32, f32, sp, vp, op],
-        "bf_trig_backward": [vp, vp, vp, vp, i64, i64, f32, f32, sp, vp, op],
+        "bf_trig_backward": [vp, vp, vp, vp, vp, i64, i64, f32, f32, sp, vp, op],
         "bf_direct_forward": [vp, i64, i64, f32, f32, sp, vp, op],
         "bf_batch_plan_create": [ctypes.POINTER(ImageDesc), i32, ctypes.POINTER(vp)],
         "bf_batch_bind": [vp, ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(vp),
@@ -133,10 +133,11 @@ def spatial_gaussian(sigma_s: float, n_boxes: int = 3):
     return s.radii()
 
 
-def make_opts(stream=None, N=0, eta_out=None, tile=None) -> Opts:
+def make_opts(stream=None, N=0, eta_out=None, tile=None, aux_out=None) -> Opts:
     o = Opts()
     o.stream = stream
     o.N = int(N)
     o.eta_out = eta_out
     o.tile_h, o.tile_w = (0, 0) if tile is None else (int(tile[0]), int(tile[1]))
+    o.aux_out = aux_out
     return o

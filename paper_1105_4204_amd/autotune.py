@@ -50,17 +50,15 @@ class Tuner:
         return f"{dev}|{mode}|r={','.join(map(str, self._radii(spec)))}|N<={nbucket}"
 
     def candidates(self, R, mode):
-        """Odd square and near-square tiles whose extended tile fits a line."""
-        ext_max = 48 * 256 if mode == "fwd" else 40 * 256
-        smax = 0
-        for s in range(1, 129, 2):
-            if s + 2 * R <= 128 and (s + 2 * R) ** 2 <= ext_max:
-                smax = s
-        if smax == 0:
+        """Output tiles up to 64 x 64 whose extended sides fit a 128-long
+        register line; the library rejects those over the LDS budget."""
+        smax = min(64, 128 - 2 * R)
+        if smax < 1:
             return []
         cands = []
-        for dh, dw in ((0, 0), (-8, 0), (0, -8), (-8, -8), (-16, -16), (-32, -32)):
-            th, tw = smax + dh, smax + dw
+        for th, tw in ((smax, smax), (smax, smax - 8), (smax - 8, smax), (smax, smax - 16),
+                       (smax - 16, smax), (smax - 8, smax - 8), (smax - 16, smax - 16),
+                       (smax, smax // 2), (smax // 2, smax)):
             if th >= 1 and tw >= 1 and (th, tw) not in cands:
                 cands.append((th, tw))
         return cands
@@ -89,7 +87,7 @@ class Tuner:
         N = int(spec.get("N", 0))
         hw = self.probe_hw
         f = torch.from_numpy(synth.piecewise_smooth(hw, hw, seed=99)).cuda()
-        out, eta = ops.trig_forward(f, T, sr, radii, N=N, return_eta=True)
+        out, eta, aux = ops.trig_forward(f, T, sr, radii, N=N, return_aux=True)
         G = torch.randn_like(f)
         best = None
         for tile in self.candidates(R, mode):
@@ -97,8 +95,8 @@ class Tuner:
                 if mode == "fwd":
                     t = self._time(lambda: ops.trig_forward(f, T, sr, radii, N=N, tile=tile))
                 else:
-                    t = self._time(lambda: ops.trig_backward(f, out, eta, G, T, sr, radii, N=N,
-                                                             tile=tile))
+                    t = self._time(lambda: ops.trig_backward(f, out, eta, aux, G, T, sr, radii,
+                                                             N=N, tile=tile))
             except nat.BFError:
                 continue
             # cost per output pixel: tiles do not divide the probe exactly

@@ -39,14 +39,17 @@ bf_status bf_trig_forward_ex(const float* f, int64_t H, int64_t W, float T, floa
     if (st != BF_OK) return st;
     const int64_t bytes = H * W * (int64_t)sizeof(float);
     float* eta = opts ? opts->eta_out : nullptr;
-    if (overlaps(f, out, bytes) || overlaps(f, eta, bytes) || overlaps(out, eta, bytes)) {
-        set_error("out / eta_out must not overlap f or each other");
+    float* aux = opts ? opts->aux_out : nullptr;
+    if (overlaps(f, out, bytes) || overlaps(f, eta, bytes) || overlaps(out, eta, bytes) ||
+        overlaps(f, bytes, aux, 2 * bytes) || overlaps(out, bytes, aux, 2 * bytes) ||
+        overlaps(eta, bytes, aux, 2 * bytes)) {
+        set_error("out / eta_out / aux_out must not overlap f or each other");
         return BF_EINVAL;
     }
     TileGeom g;
     st = plan_fwd_tiles(H, W, c.sp, opts ? opts->tile_h : 0, opts ? opts->tile_w : 0, &g);
     if (st != BF_OK) return st;
-    return launch_fwd(f, out, eta, H, W, c.rp, c.sp, g, c.stream);
+    return launch_fwd(f, out, eta, aux, H, W, c.rp, c.sp, g, c.stream);
 }
 
 bf_status bf_trig_forward(const float* f, int64_t H, int64_t W, float T, float sigma_r,
@@ -72,22 +75,23 @@ bf_status bf_direct_forward(const float* f, int64_t H, int64_t W, float T, float
 }
 
 bf_status bf_trig_backward(const float* f, const float* out, const float* eta,
-                           const float* grad_out, int64_t H, int64_t W, float T, float sigma_r,
-                           const bf_spatial_spec* spatial_spec, float* grad_f,
-                           const bf_opts* opts) {
+                           const float* aux, const float* grad_out, int64_t H, int64_t W,
+                           float T, float sigma_r, const bf_spatial_spec* spatial_spec,
+                           float* grad_f, const bf_opts* opts) {
     Common c;
     bf_status st = prepare(f, H, W, T, sigma_r, spatial_spec, opts, &c);
     if (st != BF_OK) return st;
-    const void* bufs[4] = {out, eta, grad_out, grad_f};
-    const char* names[4] = {"out", "eta", "grad_out", "grad_f"};
-    for (int i = 0; i < 4; ++i) {
+    const void* bufs[5] = {out, eta, aux, grad_out, grad_f};
+    const char* names[5] = {"out", "eta", "aux", "grad_out", "grad_f"};
+    for (int i = 0; i < 5; ++i) {
         st = check_image(bufs[i], H, W, names[i]);
         if (st != BF_OK) return st;
     }
     const int64_t bytes = H * W * (int64_t)sizeof(float);
-    const void* ins[4] = {f, out, eta, grad_out};
-    for (int i = 0; i < 4; ++i) {
-        if (overlaps(ins[i], grad_f, bytes)) {
+    const void* ins[5] = {f, out, eta, aux, grad_out};
+    const int64_t sizes[5] = {bytes, bytes, bytes, 2 * bytes, bytes};
+    for (int i = 0; i < 5; ++i) {
+        if (overlaps(ins[i], sizes[i], grad_f, bytes)) {
             set_error("grad_f must not overlap the inputs");
             return BF_EINVAL;
         }
@@ -95,7 +99,7 @@ bf_status bf_trig_backward(const float* f, const float* out, const float* eta,
     TileGeom g;
     st = plan_bwd_tiles(H, W, c.sp, opts ? opts->tile_h : 0, opts ? opts->tile_w : 0, &g);
     if (st != BF_OK) return st;
-    return launch_bwd(f, out, eta, grad_out, grad_f, H, W, c.rp, c.sp, g, c.stream);
+    return launch_bwd(f, out, eta, aux, grad_out, grad_f, H, W, c.rp, c.sp, g, c.stream);
 }
 
 }  // extern "C"

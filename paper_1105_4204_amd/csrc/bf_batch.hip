@@ -43,8 +43,8 @@ __global__ void bf_batch_reset(unsigned* counters, int n) {
 
 __global__ void __launch_bounds__(kTileThreads)
 bf_batch_kernel(const BatchDev d) {
-    extern __shared__ float smem[];
-    __shared__ int item_sh;
+    extern __shared__ __align__(16) float smem[];
+    __shared__ __align__(16) int item_sh;
     const int t = threadIdx.x;
     for (;;) {
         if (t == 0) item_sh = (int)atomicAdd(&d.counters[0], 1u);
@@ -73,7 +73,7 @@ bf_batch_kernel(const BatchDev d) {
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         }
         if (w.kind == kItemFwd) {
-            tile_body<kForward>(d.jobs[2 * w.img], w.tile, smem);
+            tile_body<kForward, true>(d.jobs[2 * w.img], w.tile, smem);
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
             __syncthreads();
             if (t == 0) atomicAdd(&d.counters[kBatchCounters0 + w.img], 1u);
@@ -85,7 +85,7 @@ bf_batch_kernel(const BatchDev d) {
                 d.loss[w.img] = (float)s;
             }
         } else {
-            tile_body<kBackward>(d.jobs[2 * w.img + 1], w.tile, smem);
+            tile_body<kBackward, false>(d.jobs[2 * w.img + 1], w.tile, smem);
         }
         __syncthreads();
     }
@@ -102,6 +102,7 @@ struct bf_batch_plan {
     std::vector<TileGeom> gf, gb;
     std::vector<bf_image_desc> desc;
     std::vector<int> fwd_tiles, part_base;
+    std::vector<size_t> aux_off;   // per image: offset of its P, Q planes in aux_d
     int total_parts = 0;
     int n_items = 0;
     int grid = 0;
@@ -114,6 +115,7 @@ struct bf_batch_plan {
     int* part_base_d = nullptr;
     float* loss_part_d = nullptr;
     unsigned* counters_d = nullptr;
+    float* aux_d = nullptr;        // forward -> adjoint sums P, Q of every image
     float* loss = nullptr;
 };
 
@@ -125,6 +127,7 @@ static void free_plan(bf_batch_plan* p) {
     (void)hipFree(p->part_base_d);
     (void)hipFree(p->loss_part_d);
     (void)hipFree(p->counters_d);
+    (void)hipFree(p->aux_d);
     delete p;
 }
 
@@ -165,6 +168,8 @@ bf_status bf_batch_plan_create(const bf_image_desc* descs, int32_t n, bf_batch_p
     p->desc.assign(descs, descs + n);
     p->fwd_tiles.resize(n);
     p->part_base.resize(n);
+    p->aux_off.resize(n);
+    size_t aux_total = 0;
     for (int i = 0; i < n; ++i) {
         const bf_image_desc& d = descs[i];
         bf_status st;
@@ -182,6 +187,8 @@ bf_status bf_batch_plan_create(const bf_image_desc* descs, int32_t n, bf_batch_p
             return st;
         }
         p->fwd_tiles[i] = p->gf[i].tiles_x * p->gf[i].tiles_y;
+        p->aux_off[i] = aux_total;
+        aux_total += 2 * (size_t)d.H * d.W;
         p->part_base[i] = p->total_parts;
         p->total_parts += p->fwd_tiles[i];
         p->lds = std::max(p->lds, std::max(p->gf[i].lds_bytes, p->gb[i].lds_bytes));
@@ -200,7 +207,8 @@ bf_status bf_batch_plan_create(const bf_image_desc* descs, int32_t n, bf_batch_p
         (st = dev_alloc(&p->fwd_tiles_d, (size_t)n)) != BF_OK ||
         (st = dev_alloc(&p->part_base_d, (size_t)n)) != BF_OK ||
         (st = dev_alloc(&p->loss_part_d, (size_t)p->total_parts)) != BF_OK ||
-        (st = dev_alloc(&p->counters_d, (size_t)kBatchCounters0 + n)) != BF_OK) {
+        (st = dev_alloc(&p->counters_d, (size_t)kBatchCounters0 + n)) != BF_OK ||
+        (st = dev_alloc(&p->aux_d, aux_total)) != BF_OK) {
         free_plan(p);
         return st;
     }
@@ -260,8 +268,11 @@ bf_status bf_batch_bind(bf_batch_plan* p, const float* const* f, const float* co
         a.eta = eta ? eta[i] : nullptr;
         a.target = target ? target[i] : nullptr;
         a.loss_part = target ? p->loss_part_d + p->part_base[i] : nullptr;
+        a.aux = bwd ? p->aux_d + p->aux_off[i] : nullptr;
         fill_tile_args(a, d.H, d.W, p->rp[i], p->sp[i], p->gf[i], kForward);
-        const double fc = (double)a.nsteps * a.EH * a.EW;
+        // a tile's time is set by its channel steps (every wave runs the whole
+        // line program whatever its active lanes)
+        const double fc = (double)a.nsteps;
         for (int k = 0; k < p->fwd_tiles[i]; ++k) fw.push_back({fc, {i, kItemFwd, k}});
         TileArgs& b = jobs[2 * i + 1];
         b = TileArgs{};
@@ -272,8 +283,9 @@ bf_status bf_batch_bind(bf_batch_plan* p, const float* const* f, const float* co
             b.feta = eta[i];
             b.gout = nullptr;
             b.target = target[i];
+            b.paux = p->aux_d + p->aux_off[i];
             fill_tile_args(b, d.H, d.W, p->rp[i], p->sp[i], p->gb[i], kBackward);
-            const double bc = (double)b.nsteps * b.EH * b.EW;
+            const double bc = (double)b.nsteps;
             const int nb = p->gb[i].tiles_x * p->gb[i].tiles_y;
             for (int k = 0; k < nb; ++k) bw.push_back({bc, {i, kItemBwd, k}});
         }

@@ -129,10 +129,14 @@ bf_status check_image(const void* p, int64_t H, int64_t W, const char* name) {
 }
 
 bool overlaps(const void* a, const void* b, int64_t bytes) {
+    return overlaps(a, bytes, b, bytes);
+}
+
+bool overlaps(const void* a, int64_t abytes, const void* b, int64_t bbytes) {
     if (!a || !b) return false;
     const char* pa = (const char*)a;
     const char* pb = (const char*)b;
-    return pa < pb + bytes && pb < pa + bytes;
+    return pa < pb + bbytes && pb < pa + abytes;
 }
 
 }  // namespace bf

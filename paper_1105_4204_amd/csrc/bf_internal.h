@@ -34,27 +34,29 @@ void set_error(const char* fmt, ...);
 bf_status make_range(double T, double sigma_r, int32_t N_req, RangeParams* rp);
 bf_status make_spatial(const bf_spatial_spec* spec, SpatialParams* sp);
 bf_status check_image(const void* p, int64_t H, int64_t W, const char* name);
-bool overlaps(const void* a, const void* b, int64_t bytes);
+bool overlaps(const void* a, const void* b, int64_t bytes);   // two ranges of `bytes` each
+bool overlaps(const void* a, int64_t abytes, const void* b, int64_t bbytes);
 
 // Tile geometry of the fused forward/backward kernels.
 struct TileGeom {
     int TH, TW;       // output tile
     int EH, EW;       // extended tile (output + halo of R on every side)
+    int EWp, EHp;     // LDS pitches of extended rows and of transposed rows
     int tiles_x, tiles_y;
     size_t lds_bytes;
 };
 
 bf_status plan_fwd_tiles(int64_t H, int64_t W, const SpatialParams& sp, int req_h, int req_w,
                          TileGeom* g);
-bf_status launch_fwd(const float* f, float* out, float* eta, int64_t H, int64_t W,
+bf_status launch_fwd(const float* f, float* out, float* eta, float* aux, int64_t H, int64_t W,
                      const RangeParams& rp, const SpatialParams& sp, const TileGeom& g,
                      hipStream_t stream);
 bf_status launch_direct(const float* f, float* out, float* eta, int64_t H, int64_t W,
                         const RangeParams& rp, const SpatialParams& sp, hipStream_t stream);
 bf_status plan_bwd_tiles(int64_t H, int64_t W, const SpatialParams& sp, int req_h, int req_w,
                          TileGeom* g);
-bf_status launch_bwd(const float* f, const float* out, const float* eta, const float* gout,
-                     float* gf, int64_t H, int64_t W, const RangeParams& rp,
+bf_status launch_bwd(const float* f, const float* out, const float* eta, const float* aux,
+                     const float* gout, float* gf, int64_t H, int64_t W, const RangeParams& rp,
                      const SpatialParams& sp, const TileGeom& g, hipStream_t stream);
 
 }  // namespace bf

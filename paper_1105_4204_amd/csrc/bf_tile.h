@@ -1,41 +1,37 @@
 // Fused O(1) forward and adjoint kernels of the trigonometric bilateral
 // filter (gfx950).
 //
-// One workgroup owns an output tile of TH x TW pixels and the extended tile
-// (TH + 2R) x (TW + 2R) around it.  With g = f - T/2 (zero outside the image),
-// C_m = cos(m a g), S_m = sin(m a g) and F the separable iterated-box filter
-// with zero extension, the raised cosine's pair expansion (Sec. 2.3) turns
-// eq. (BF)/(normalization) into eq. (final-form):
+// One workgroup of four waves owns an output tile of TH x TW pixels and the
+// extended tile (EH x EW = (TH + 2R) x (TW + 2R)) around it.  With g = f - T/2
+// (zero outside the image), Z_m = exp(j m a g) = C_m + j S_m and F the
+// separable iterated-box filter with zero extension, the raised cosine's pair
+// expansion (Sec. 2.3) turns eq. (BF)/(normalization) into eq. (final-form):
 //     den = sum_m c_m (C F[C] + S F[S]),   num = sum_m c_m (C F[gC] + S F[gS]),
 //     out = T/2 + num/den,  eta = den.
-// The adjoint, for G = dL/dout, A = G/den and B = A (out - T/2), is
+// Differentiating eq. (BF)/(normalization) for G = dL/dout, A = G/den,
+// h = out - T/2, B = A h gives (F is self-adjoint: symmetric w, zero
+// extension)
 //     dL/df = sum_m c_m { (C - ma g S) F[A C] + (S + ma g C) F[A S]
-//                         + ma S F[B C] - ma C F[B S]
-//                         - ma A S F[gC] + ma A C F[gS]
-//                         + ma B S F[C] - ma B C F[S] },       ma = m a,
-// obtained by differentiating both the local factors C, S and the filtered
-// auxiliary images (F is self-adjoint: symmetric w, zero extension).
-// Either way every cosine pair is a list of channels, each an auxiliary image
-// built on the extended tile, filtered, multiplied by a per-pixel
-// coefficient and accumulated at the output pixels.  The auxiliary images
-// exist only in LDS and registers; nothing per term reaches HBM.
+//                         + ma S F[B C] - ma C F[B S] }  + a (A P - B Q),
+//     P = sum_m c_m m (C F[gS] - S F[gC]),   Q = sum_m c_m m (C F[S] - S F[C]),
+// with ma = m a.  P and Q are built from the forward's own filtered channels,
+// so the forward accumulates them when asked (AUX) and the adjoint filters
+// only the four channels A C, A S, B C, B S per pair.
 //
-// Phase: each thread keeps z = exp(j m a g) for its extended-tile pixels in
-// registers and advances it once per pair by a complex multiply,
-// z <- z * exp(j 2 a g), from the centre term (m = 0, z = 1) or from m = 1
-// (z = exp(j a g), evaluated in FP64) for odd N.  The step factor is
-// re-evaluated per pair from g by its Taylor series (|2 a g| <= pi/2 when f
-// lies in [0, T] and N meets the degree bound) rather than stored.
-//
-// Filtering: lanes hold one whole line in registers (bf_box.h): a row of the
-// extended tile for the horizontal pass, then a column of the row-filtered
-// tile for the vertical pass, every box stage a running sum
-// s += (x_enter - x_leave) with compile-time indices.  LDS carries only the
-// bulk hand-offs: the phase owners write the channel's auxiliary image
-// (plane) and its coefficients at the output pixels (coef), row lanes write
-// their results transposed (T), column lanes accumulate.  Rows of channel s
-// and columns of channel s-1 run at the same time on different waves; T and
-// coef are double-buffered for that.
+// Work split.  Waves 0-1 are row lanes: lane i owns row i of the extended
+// tile and keeps the phase Z (forward) or Y = A Z (adjoint) of all its pixels
+// in registers, advancing it once per pair by Z <- Z exp(j 2 a g) (from m = 0,
+// or m = 1 evaluated directly for odd N).  Waves 2-3 are column lanes: lane j
+// owns output column j, keeps Z at its output pixels and its accumulators in
+// registers.  Per channel step the row lanes build the channel's auxiliary
+// row from their phase (times g or h read from LDS), run the box stages along
+// it (bf_box.h) and store the result transposed into T[s & 1]; at the same
+// time the column lanes load the previous channel's transposed rows from
+// T[(s - 1) & 1], run the box stages down the column and accumulate.  Wave 2
+// takes the C-type channels (C, S; A C, A S) and wave 3 the others (gC, gS;
+// B C, B S), so each column wave filters two channels per pair.  The
+// auxiliary images exist only in registers and one transposed LDS buffer;
+// nothing per term reaches HBM.
 #pragma once
 
 #include "bf_box.h"
@@ -45,59 +41,49 @@ namespace bf {
 
 enum TileMode { kForward = 0, kBackward = 1 };
 
-constexpr int kTileThreads = 256;
-constexpr int kLine = 128;             // register line length (rows and columns)
-constexpr int kColLane0 = 128;         // threads [0,128) are row lanes, [128,256) column lanes
-constexpr int kPad = kLine;            // LDS slack after each line buffer
-constexpr int kChunk = 8;              // outputs stored per uniform guard
-
-template <int MODE>
-struct ModeTraits;
-template <>
-struct ModeTraits<kForward> {
-    static constexpr int kKMax = 48;   // extended pixels per thread
-    static constexpr int kAcc = 2;     // den, num
-};
-template <>
-struct ModeTraits<kBackward> {
-    static constexpr int kKMax = 40;
-    static constexpr int kAcc = 1;     // dL/df
-};
+constexpr int kTileThreads = 256;   // waves 0-1: row lanes, waves 2-3: column lanes
+constexpr int kLine = 128;          // register line length (extended rows and columns)
+constexpr int kOutMax = 64;         // output tile side limit (column-lane state)
+constexpr int kPad = kLine;         // LDS slack after each buffer
+constexpr int kChunk = 8;           // outputs stored per uniform guard
 
 struct TileArgs {
     const float* f;
-    float* out;          // forward: filtered image; backward: dL/df
+    float* out;          // forward: filtered image; adjoint: dL/df
     float* eta;          // forward: optional eta
-    const float* fout;   // backward: forward output
-    const float* feta;   // backward: forward eta
-    const float* gout;   // backward: dL/dout (NULL in a batch: 2 (fout - target))
-    const float* target; // batch: SSD target (forward: per-tile loss partial)
+    float* aux;          // forward: optional P and Q planes (2 H W)
+    const float* paux;   // adjoint: P and Q from the forward
+    const float* fout;   // adjoint: forward output
+    const float* feta;   // adjoint: forward eta
+    const float* gout;   // adjoint: dL/dout (NULL in a batch: 2 (fout - target))
+    const float* target; // batch: SSD target
     float* loss_part;    // batch forward: one partial SSD per tile
     int H, W;
-    int TH, TW, EH, EW, tiles_x;
+    int TH, TW, EH, EW, EWp, EHp, tiles_x;
     int R, nb;
     int r[BF_MAX_BOXES];
     int npairs, odd, nsteps;
+    float alpha_f;       // a
     float two_alpha;     // 2a: per-pair phase step per unit intensity
-    float alpha_f;       // a in float (m a factors of the adjoint)
-    double alpha;
-    float center;
+    float center;        // T/2
     float chat[kMaxPairs];
 };
 
-// LDS layout (floats): plane[EH*EW + kPad] | T0 | T1 | coef0 | coef1 | acc...
-// T holds (TW + kChunk) columns of EH plus kPad; coef and each accumulator
-// plane hold (TH + kChunk) rows of TW.  The pads let every lane load a whole
-// kLine-long line and store whole chunks unconditionally; values past a
-// line's end only reach outputs that are discarded.
-__host__ __device__ inline size_t tile_t_stride(int TW, int EH) {
-    return (size_t)(TW + kChunk) * EH + kPad;
-}
-__host__ __device__ inline size_t tile_o_plane(int TH, int TW) {
-    return (size_t)(TH + kChunk) * TW;
-}
-__host__ __device__ inline size_t tile_lds_floats(int TH, int TW, int EH, int EW, int nacc) {
-    return (size_t)EH * EW + kPad + 2 * tile_t_stride(TW, EH) + (2 + nacc) * tile_o_plane(TH, TW);
+// LDS pitch of a line of n floats: the smallest p >= n with p = 4 (mod 8), so
+// that lanes reading consecutive lines with 16-byte loads hit distinct banks.
+__host__ __device__ constexpr int tile_pitch(int n) { return ((n + 3) / 8) * 8 + 4; }
+__host__ __device__ inline int tile_round(int n) { return (n + kChunk - 1) / kChunk * kChunk; }
+__host__ __device__ inline int tile_plane_floats(int EH, int EWp) { return EH * EWp + kPad; }
+__host__ __device__ inline int tile_t_floats(int TW, int EHp) { return tile_round(TW) * EHp + kPad; }
+// Forward only: g at the output pixels, transposed (column j at j * kGtPitch).
+constexpr int kGtPitch = tile_pitch(kOutMax);
+constexpr int kGtFloats = kOutMax * kGtPitch;
+// LDS layout (floats): gplane | hplane (adjoint) | T0 | T1 | gT (forward).
+__host__ __device__ inline size_t tile_lds_floats(int mode, int TH, int TW, int R) {
+    const int EH = TH + 2 * R, EW = TW + 2 * R;
+    const int planes = mode == kForward ? 1 : 2;
+    return (size_t)planes * tile_plane_floats(EH, tile_pitch(EW)) +
+           2 * (size_t)tile_t_floats(TW, tile_pitch(EH)) + (mode == kForward ? kGtFloats : 0);
 }
 
 // exp(j x) for |x| <= pi/2 by the Taylor series of cos (to x^14) and sin (to
@@ -121,242 +107,401 @@ __device__ __forceinline__ void cis_small(float x, float& c, float& s) {
     s = fmaf(ps * x2, x, x);
 }
 
-// Channels of one cosine pair.  Forward: C, gC, S, gS (centre pair: C, gC).
-// Backward: AC, AS, BC, BS, gC, gS, C, S (centre pair: AC).
+// v[0..kLine) <- src[0..kLine) with 16-byte LDS loads (src 16-byte aligned).
+__device__ __forceinline__ void load_line(float (&v)[kLine], const float* src) {
+    const float4* s4 = reinterpret_cast<const float4*>(src);
+#pragma unroll
+    for (int k = 0; k < kLine / 4; ++k) {
+        const float4 q = s4[k];
+        v[4 * k] = q.x;
+        v[4 * k + 1] = q.y;
+        v[4 * k + 2] = q.z;
+        v[4 * k + 3] = q.w;
+    }
+}
+
+// (zr + j zi)[x] *= exp(j step g[x]) for x < n.
+template <int n, int L>
+__device__ __forceinline__ void phase_step(float (&zr)[L], float (&zi)[L], const float (&g)[kLine],
+                                           int goff, float step) {
+#pragma unroll
+    for (int x = 0; x < n; ++x) {
+        float cu, su;
+        cis_small(step * g[goff + x], cu, su);
+        const float nr = zr[x] * cu - zi[x] * su;
+        const float ni = zr[x] * su + zi[x] * cu;
+        zr[x] = nr;
+        zi[x] = ni;
+    }
+}
+
+// Channels per pair: forward C, gC, S, gS (centre pair: 1, g); adjoint A C,
+// B C, A S, B S (centre pair: A).  Channel ch goes to column wave 2 + (ch & 1).
 template <int MODE>
 __device__ __forceinline__ int pair_channels(bool centre) {
     if (MODE == kForward) return centre ? 2 : 4;
-    return centre ? 1 : 8;
+    return centre ? 1 : 4;
 }
 
-// Auxiliary-image value of channel ch at a pixel: phase component times a
-// per-pixel factor.
-template <int MODE>
-__device__ __forceinline__ float channel_input(int ch, float zr, float zi, float g, float A,
-                                               float B) {
-    if (MODE == kForward) {
-        const float base = (ch >= 2) ? zi : zr;
-        return (ch & 1) ? base * g : base;
-    }
-    const float base = (ch & 1) ? zi : zr;
-    const int kind = ch >> 1;   // 0: A, 1: B, 2: g, 3: 1
-    const float mul = kind == 0 ? A : kind == 1 ? B : kind == 2 ? g : 1.0f;
-    return base * mul;
-}
+// Geometry and LDS pointers of one tile, shared by the two roles.
+struct TileCtx {
+    int EH, EW, TH, TW, R, EWp, EHp, tfl;
+    int i0, j0, ei0, ej0;     // output and extended tile origins (image coordinates)
+    int t, wave, lane;
+    float* gpl;               // g = f - T/2 on the extended tile
+    float* hpl;               // adjoint: A, then h = out - T/2
+    float* Tb;                // T0 | T1: row results, transposed
+    float* gT;                // forward: g at the output pixels, column-major
+};
 
-// Coefficient multiplying F[channel ch] at an output pixel (c = c_m, ma = m a).
-template <int MODE>
-__device__ __forceinline__ float channel_coef(int ch, float c, float ma, float C, float S,
-                                              float g, float A, float B) {
-    if (MODE == kForward) return c * ((ch >= 2) ? S : C);
-    switch (ch) {
-        case 0: return c * (C - ma * g * S);
-        case 1: return c * (S + ma * g * C);
-        case 2: return c * ma * S;
-        case 3: return -c * ma * C;
-        case 4: return -c * ma * A * S;
-        case 5: return c * ma * A * C;
-        case 6: return c * ma * B * S;
-        default: return -c * ma * B * C;
+// Cooperative fill of an extended-tile plane (pitch gaps and pad zero):
+// value(k) for in-image pixels at flat image index k, 0 elsewhere.
+template <typename F>
+__device__ __forceinline__ void fill_plane(const TileArgs& a, const TileCtx& c, float* dst,
+                                           F value) {
+    const int n = tile_plane_floats(c.EH, c.EWp);
+    const uint32_t magic = (uint32_t)((0x100000000ull + c.EWp - 1) / c.EWp);
+    for (int p = c.t; p < n; p += kTileThreads) {
+        const int ei = (int)__umulhi((uint32_t)p, magic);
+        const int ej = p - ei * c.EWp;
+        const int gi = c.ei0 + ei, gj = c.ej0 + ej;
+        float x = 0.0f;
+        if (ei < c.EH && ej < c.EW && gi >= 0 && gi < a.H && gj >= 0 && gj < a.W)
+            x = value((size_t)gi * a.W + gj);
+        dst[p] = x;
     }
 }
 
-// Accumulator plane receiving channel ch (forward: den for C/S, num for gC/gS).
-template <int MODE>
-__device__ __forceinline__ int channel_acc(int ch) {
-    return MODE == kForward ? (ch & 1) : 0;
+// Barriers of the output phase, matched by both roles: hand-over of wave 3's
+// sums, then (batch forward) the loss partials, then the end of the tile.
+__device__ __forceinline__ int tile_out_barriers(const TileArgs& a, int mode) {
+    return (mode == kForward && a.loss_part) ? 3 : 2;
 }
 
-// One output tile of one image (tile index tile_id) for descriptor a; all
-// threads of the workgroup call it together.
+// Row role (waves 0-1): lane i owns extended row i.  State: A0 + j A1 = Z
+// (forward) or Y = A Z (adjoint) at the row's pixels; zero outside the image.
 template <int MODE>
-__device__ void tile_body(const TileArgs& a, int tile_id, float* smem) {
-    constexpr int KMAX = ModeTraits<MODE>::kKMax;
-    constexpr int NACC = ModeTraits<MODE>::kAcc;
-    const int EH = a.EH, EW = a.EW, TH = a.TH, TW = a.TW, R = a.R;
-    const int E = EH * EW;
-    const int THTW = TH * TW;
-    const size_t tstride = tile_t_stride(TW, EH);
-    const int OP = (int)tile_o_plane(TH, TW);
-    float* plane = smem;
-    float* Tbuf = plane + (size_t)E + kPad;
-    float* coef = Tbuf + 2 * tstride;
-    float* acc = coef + 2 * (size_t)OP;
-
-    const int t = threadIdx.x;
-    const int ty = tile_id / a.tiles_x, tx = tile_id - ty * a.tiles_x;
-    const int i0 = ty * TH, j0 = tx * TW;             // output tile origin (image coords)
-    const int ei0 = i0 - R, ej0 = j0 - R;             // extended tile origin
-    const uint32_t magic = (uint32_t)((0x100000000ull + EW - 1) / EW);
-
-    // ---- per-pixel state of the extended tile -----------------------------------
-    float zr[KMAX], zi[KMAX], gv[KMAX], av[KMAX], bv[KMAX];
-    uint64_t inimg = 0, inout = 0;
+__device__ __forceinline__ void row_role(const TileArgs& a, const TileCtx& c) {
+    const int i = c.t;
+    const bool act = i < c.EH;
+    float A0[kLine], A1[kLine], v[kLine];
+    if (act) {
+        load_line(v, c.gpl + i * c.EWp);
+        const int gi = c.ei0 + i;
+        const bool rin = gi >= 0 && gi < a.H;
+        const int xlo = c.ej0 < 0 ? -c.ej0 : 0;
+        const int xhi = min(c.EW, a.W - c.ej0);
+        if (a.odd) {
 #pragma unroll
-    for (int k = 0; k < KMAX; ++k) {
-        const int p = t + kTileThreads * k;
-        zr[k] = 0.0f;
-        zi[k] = 0.0f;
-        gv[k] = 0.0f;
-        av[k] = 0.0f;
-        bv[k] = 0.0f;
-        if (p < E) {
-            const int ei = EW == 1 ? p : (int)__umulhi((uint32_t)p, magic);
-            const int ej = p - ei * EW;
-            const int gi = ei0 + ei, gj = ej0 + ej;
-            if (ei >= R && ei < R + TH && ej >= R && ej < R + TW) inout |= (1ull << k);
-            if (gi >= 0 && gi < a.H && gj >= 0 && gj < a.W) {
-                inimg |= (1ull << k);
-                const size_t gidx = (size_t)gi * a.W + gj;
-                const float g = a.f[gidx] - a.center;
-                gv[k] = g;
-                if (a.odd) {
-                    double sn, cn;
-                    sincos(a.alpha * (double)g, &sn, &cn);
-                    zr[k] = (float)cn;
-                    zi[k] = (float)sn;
-                } else {
-                    zr[k] = 1.0f;
-                }
-                if (MODE == kBackward) {
-                    const float fo = a.fout[gidx];
-                    const float G = a.gout ? a.gout[gidx] : 2.0f * (fo - a.target[gidx]);
-                    const float A = G / a.feta[gidx];
-                    av[k] = A;
-                    bv[k] = A * (fo - a.center);
-                }
+            for (int x = 0; x < kLine; ++x) {
+                float cc, ss;
+                cis_small(a.alpha_f * v[x], cc, ss);
+                const bool in = rin && x >= xlo && x < xhi;
+                A0[x] = in ? cc : 0.0f;
+                A1[x] = in ? ss : 0.0f;
+            }
+        } else {
+#pragma unroll
+            for (int x = 0; x < kLine; ++x) {
+                const bool in = rin && x >= xlo && x < xhi;
+                A0[x] = in ? 1.0f : 0.0f;
+                A1[x] = 0.0f;
+            }
+        }
+        if (MODE == kBackward) {
+            load_line(v, c.hpl + i * c.EWp);   // A
+#pragma unroll
+            for (int x = 0; x < kLine; ++x) {
+                A0[x] *= v[x];
+                A1[x] *= v[x];
             }
         }
     }
-    for (int o = t; o < NACC * OP; o += kTileThreads) acc[o] = 0.0f;
-
-    // Channel steps s = 0 .. nsteps-1 run over all pairs; at step s the row
-    // lanes filter channel s into T[s & 1] while the column lanes filter
-    // channel s-1 out of T[(s-1) & 1] and accumulate with coef[(s-1) & 1].
-    int q = 0, ch = 0;           // pair and channel of step s
-    int pch = -1;                // channel of step s-1 (column lanes); -1: none
+    if (MODE == kBackward) {
+        __syncthreads();   // every row lane has read A
+        fill_plane(a, c, c.hpl, [&](size_t k) { return a.fout[k] - a.center; });
+        __syncthreads();
+    }
+    const float* mulpl = (MODE == kForward) ? c.gpl : c.hpl;
+    int q = 0, ch = 0;    // pair and channel of step s
     for (int s = 0; s <= a.nsteps; ++s) {
-        const bool have_row = s < a.nsteps;
-        if (have_row) {
-            const bool centre = (q == 0) && !a.odd;
+        if (s < a.nsteps && act) {
             if (ch == 0 && q > 0) {
+                load_line(v, c.gpl + i * c.EWp);
+                phase_step<kLine>(A0, A1, v, 0, a.two_alpha);
+            }
+            if (ch & 1) load_line(v, mulpl + i * c.EWp);
+            if (ch == 0) {
 #pragma unroll
-                for (int k = 0; k < KMAX; ++k) {
-                    if (inimg & (1ull << k)) {
-                        float cu, su;
-                        cis_small(a.two_alpha * gv[k], cu, su);
-                        const float nr = zr[k] * cu - zi[k] * su;
-                        const float ni = zr[k] * su + zi[k] * cu;
-                        zr[k] = nr;
-                        zi[k] = ni;
-                    }
+                for (int x = 0; x < kLine; ++x) v[x] = A0[x];
+            } else if (ch == 1) {
+#pragma unroll
+                for (int x = 0; x < kLine; ++x) v[x] *= A0[x];
+            } else if (ch == 2) {
+#pragma unroll
+                for (int x = 0; x < kLine; ++x) v[x] = A1[x];
+            } else {
+#pragma unroll
+                for (int x = 0; x < kLine; ++x) v[x] *= A1[x];
+            }
+            for (int b = 0; b < a.nb; ++b) box_dispatch<kLine>(v, a.r[b]);
+            float* dst = c.Tb + (s & 1) * c.tfl + i;
+#pragma unroll
+            for (int j0c = 0; j0c < kOutMax; j0c += kChunk) {
+                if (j0c < c.TW) {   // uniform; a chunk may run into the next row's slack
+#pragma unroll
+                    for (int jj = 0; jj < kChunk; ++jj) dst[(j0c + jj) * c.EHp] = v[j0c + jj];
                 }
             }
-#pragma unroll
-            for (int k = 0; k < KMAX; ++k) {
-                const int p = t + kTileThreads * k;
-                if (p < E) plane[p] = channel_input<MODE>(ch, zr[k], zi[k], gv[k], av[k], bv[k]);
-            }
-            const float c = a.chat[q];
-            const float ma = (float)(a.odd + 2 * q) * a.alpha_f;
-            float* cdst = coef + (size_t)(s & 1) * OP;
-            int tt = t;
-            asm volatile("" : "+v"(tt));   // recompute indices per step, not per kernel
-#pragma unroll
-            for (int k = 0; k < KMAX; ++k) {
-                if (inout & (1ull << k)) {
-                    const int p = tt + kTileThreads * k;
-                    const int ei = EW == 1 ? p : (int)__umulhi((uint32_t)p, magic);
-                    const int o = (ei - R) * TW + (p - ei * EW - R);
-                    cdst[o] = channel_coef<MODE>(ch, c, ma, zr[k], zi[k], gv[k], av[k], bv[k]);
-                }
-            }
-            (void)centre;
         }
         __syncthreads();
-        const bool is_row = t < kColLane0;
-        const bool active = is_row ? (have_row && t < EH) : (pch >= 0 && t - kColLane0 < TW);
-        if (active) {
-            const int lane = is_row ? t : t - kColLane0;
-            const float* src = is_row ? plane + (size_t)lane * EW
-                                      : Tbuf + (size_t)((s - 1) & 1) * tstride + (size_t)lane * EH;
-            float v[kLine];
+        if (s < a.nsteps && ++ch == pair_channels<MODE>(q == 0 && !a.odd)) {
+            ch = 0;
+            ++q;
+        }
+    }
+    for (int k = tile_out_barriers(a, MODE); k > 0; --k) __syncthreads();
+}
+
+// Column role (waves 2-3): lane j owns output column j.  State: A0[0..64) +
+// j A1[0..64) = Z at the column's outputs; tails: forward den|num (A0) and
+// Q|P (A1) on wave 2|3; adjoint g at the outputs (A0) and the partial sum
+// (A1).  Wave 2 filters the channels with even index, wave 3 the odd ones.
+template <int MODE, bool AUX>
+__device__ __forceinline__ void col_role(const TileArgs& a, const TileCtx& c, int tile_id) {
+    const int j = c.lane;
+    const bool act = j < c.TW;
+    const int TH = c.TH;
+    float A0[kLine], A1[kLine], v[kLine];
+    // v[0..kOutMax) <- g at the output pixels of column j (rows past TH: 0 or a repeat)
+    auto load_gcol = [&]() {
+        if (MODE == kForward) {
+            const float4* s4 = reinterpret_cast<const float4*>(c.gT + j * kGtPitch);
 #pragma unroll
-            for (int x = 0; x < kLine; ++x) v[x] = src[x];
+            for (int k = 0; k < kOutMax / 4; ++k) {
+                const float4 q4 = s4[k];
+                v[4 * k] = q4.x;
+                v[4 * k + 1] = q4.y;
+                v[4 * k + 2] = q4.z;
+                v[4 * k + 3] = q4.w;
+            }
+        } else {
+            const float* gcol = c.gpl + c.R * c.EWp + c.R + j;
+#pragma unroll
+            for (int k = 0; k < kOutMax; ++k) v[k] = gcol[min(k, TH - 1) * c.EWp];
+        }
+    };
+    if (act) {
+        load_gcol();
+        if (a.odd) {
+#pragma unroll
+            for (int k = 0; k < kOutMax; ++k) cis_small(a.alpha_f * v[k], A0[k], A1[k]);
+        } else {
+#pragma unroll
+            for (int k = 0; k < kOutMax; ++k) {
+                A0[k] = 1.0f;
+                A1[k] = 0.0f;
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < kOutMax; ++k) {
+            A0[kOutMax + k] = (MODE == kBackward) ? v[k] : 0.0f;
+            A1[kOutMax + k] = 0.0f;
+        }
+    }
+    if (MODE == kBackward) {
+        __syncthreads();
+        fill_plane(a, c, c.hpl, [&](size_t k) { return a.fout[k] - a.center; });
+        __syncthreads();
+    }
+    int q = 0, ch = 0;    // pair and channel of step s - 1
+    for (int s = 0; s <= a.nsteps; ++s) {
+        if (s > 0 && (ch & 1) == (c.wave - 2) && act) {
+            if ((ch >> 1) == 0 && q > 0) {
+                if (MODE == kBackward) {          // g kept in the A0 tail
+                    phase_step<kOutMax>(A0, A1, A0, kOutMax, a.two_alpha);
+                } else {
+                    load_gcol();
+                    phase_step<kOutMax>(A0, A1, v, 0, a.two_alpha);
+                }
+            }
+            load_line(v, c.Tb + ((s - 1) & 1) * c.tfl + j * c.EHp);
             for (int b = 0; b < a.nb; ++b) box_dispatch<kLine>(v, a.r[b]);
-            if (is_row) {
-                float* dst = Tbuf + (size_t)(s & 1) * tstride + lane;
+            const float cq = a.chat[q];
+            const float m = (float)(a.odd + 2 * q);
+            // accumulate over the output rows k < TH; the channel picks the
+            // coefficient (uniform), every index is a compile-time constant
+            auto accumulate = [&](auto coef_of, float (&acc)[kLine]) {
 #pragma unroll
-                for (int j0c = 0; j0c < kLine; j0c += kChunk) {
-                    if (j0c < TW) {   // uniform; a chunk may spill into the pad
+                for (int i0c = 0; i0c < kOutMax; i0c += kChunk) {
+                    if (i0c < TH) {
 #pragma unroll
-                        for (int jj = 0; jj < kChunk; ++jj)
-                            dst[(size_t)(j0c + jj) * EH] = v[j0c + jj];
+                        for (int ii = 0; ii < kChunk; ++ii) {
+                            const int k = i0c + ii;
+                            acc[kOutMax + k] = fmaf(coef_of(k), v[k], acc[kOutMax + k]);
+                        }
                     }
+                }
+            };
+            if (MODE == kForward) {
+                const float cm = cq * m;
+                if (ch < 2) {   // C F[.] into den|num; -m S F[.] into Q|P
+                    accumulate([&](int k) { return cq * A0[k]; }, A0);
+                    if (AUX) accumulate([&](int k) { return -cm * A1[k]; }, A1);
+                } else {        // S F[.] into den|num; m C F[.] into Q|P
+                    accumulate([&](int k) { return cq * A1[k]; }, A0);
+                    if (AUX) accumulate([&](int k) { return cm * A0[k]; }, A1);
                 }
             } else {
-                const float* cw = coef + (size_t)((s - 1) & 1) * OP + lane;
-                float* dst = acc + (size_t)channel_acc<MODE>(pch) * OP + lane;
-#pragma unroll
-                for (int i0c = 0; i0c < kLine; i0c += kChunk) {
-                    if (i0c < TH) {   // uniform; rows past TH land in the pad
-#pragma unroll
-                        for (int ii = 0; ii < kChunk; ++ii)
-                            dst[(i0c + ii) * TW] += cw[(i0c + ii) * TW] * v[i0c + ii];
-                    }
-                }
+                const float cma = cq * m * a.alpha_f;
+                if (ch == 0)        // A C: c (C - ma g S)
+                    accumulate(
+                        [&](int k) { return fmaf(-cma * A0[kOutMax + k], A1[k], cq * A0[k]); },
+                        A1);
+                else if (ch == 2)   // A S: c (S + ma g C)
+                    accumulate(
+                        [&](int k) { return fmaf(cma * A0[kOutMax + k], A0[k], cq * A1[k]); },
+                        A1);
+                else if (ch == 1)   // B C: c ma S
+                    accumulate([&](int k) { return cma * A1[k]; }, A1);
+                else                // B S: -c ma C
+                    accumulate([&](int k) { return -cma * A0[k]; }, A1);
             }
         }
         __syncthreads();
-        pch = have_row ? ch : -1;
-        if (have_row) {
-            if (++ch == pair_channels<MODE>((q == 0) && !a.odd)) {
-                ch = 0;
-                ++q;
+        if (s > 0 && ++ch == pair_channels<MODE>(q == 0 && !a.odd)) {
+            ch = 0;
+            ++q;
+        }
+    }
+
+    // ---- outputs: wave 3 hands its sums to wave 2, which finishes the pixels ----
+    float* xch = c.Tb;
+    const size_t HW = (size_t)a.H * a.W;
+    if (c.wave == 3 && act) {
+#pragma unroll
+        for (int i0c = 0; i0c < kOutMax; i0c += kChunk) {
+            if (i0c < TH) {
+#pragma unroll
+                for (int ii = 0; ii < kChunk; ++ii) {
+                    const int k = i0c + ii;
+                    if (k < TH) {
+                        xch[k * c.TW + j] = (MODE == kForward) ? A0[kOutMax + k] : A1[kOutMax + k];
+                        const int gi = c.i0 + k, gj = c.j0 + j;
+                        if (MODE == kForward && AUX && a.aux && gi < a.H && gj < a.W)
+                            a.aux[(size_t)gi * a.W + gj] = A1[kOutMax + k];          // P
+                    }
+                }
             }
         }
     }
-    double sq = 0.0;   // batch forward: this thread's share of the tile's SSD
-    for (int o = t; o < THTW; o += kTileThreads) {
-        const int oi = o / TW, oj = o - oi * TW;
-        const int gi = i0 + oi, gj = j0 + oj;
-        if (gi < a.H && gj < a.W) {
-            const size_t gidx = (size_t)gi * a.W + gj;
-            if (MODE == kForward) {
-                const float den = acc[o];
-                const float num = acc[OP + o];
-                const float y = (float)((double)a.center + (double)num / (double)den);
-                a.out[gidx] = y;
-                if (a.eta) a.eta[gidx] = den;
-                if (a.loss_part) {
-                    const double d = (double)y - (double)a.target[gidx];
-                    sq += d * d;
+    __syncthreads();
+    double sq = 0.0;   // batch forward: this lane's share of the tile's SSD
+    if (c.wave == 2 && act) {
+#pragma unroll
+        for (int i0c = 0; i0c < kOutMax; i0c += kChunk) {
+            if (i0c < TH) {
+#pragma unroll
+                for (int ii = 0; ii < kChunk; ++ii) {
+                    const int k = i0c + ii;
+                    const int gi = c.i0 + k, gj = c.j0 + j;
+                    if (k < TH && gi < a.H && gj < a.W) {
+                        const size_t gidx = (size_t)gi * a.W + gj;
+                        const float other = xch[k * c.TW + j];
+                        if (MODE == kForward) {
+                            const float den = A0[kOutMax + k];
+                            const float y =
+                                (float)((double)a.center + (double)other / (double)den);
+                            a.out[gidx] = y;
+                            if (a.eta) a.eta[gidx] = den;
+                            if (AUX && a.aux) a.aux[HW + gidx] = A1[kOutMax + k];  // Q
+                            if (a.loss_part) {
+                                const double d = (double)y - (double)a.target[gidx];
+                                sq += d * d;
+                            }
+                        } else {
+                            const float fo = a.fout[gidx];
+                            const float G = a.gout ? a.gout[gidx] : 2.0f * (fo - a.target[gidx]);
+                            const float Ak = G / a.feta[gidx];
+                            const float Bk = Ak * (fo - a.center);
+                            const float P = a.paux[gidx], Q = a.paux[HW + gidx];
+                            a.out[gidx] = (A1[kOutMax + k] + other) +
+                                          a.alpha_f * (Ak * P - Bk * Q);
+                        }
+                    }
                 }
-            } else {
-                a.out[gidx] = acc[o];
             }
         }
     }
     if (MODE == kForward && a.loss_part) {
-        // fixed-order tree reduction: the same partial on every run
+        // fixed-order reduction over the 64 column lanes: the same partial on every run
+        double* red = reinterpret_cast<double*>(c.gpl);
+        if (c.wave == 2) red[c.lane] = sq;
         __syncthreads();
-        double* red = reinterpret_cast<double*>(smem);
-        red[t] = sq;
-        __syncthreads();
-        for (int w = kTileThreads / 2; w > 0; w >>= 1) {
-            if (t < w) red[t] += red[t + w];
-            __syncthreads();
+        if (c.t == 2 * 64) {
+            double acc = 0.0;
+            for (int k = 0; k < 64; ++k) acc += red[k];
+            a.loss_part[tile_id] = (float)acc;
         }
-        if (t == 0) a.loss_part[tile_id] = (float)red[0];
     }
     __syncthreads();   // LDS is reused by the next tile of a persistent workgroup
 }
 
-template <int MODE>
+// One output tile of one image (tile index tile_id) for descriptor a; all
+// 256 threads of the workgroup call it together.
+template <int MODE, bool AUX>
+__device__ __forceinline__ void tile_body(const TileArgs& a, int tile_id, float* smem) {
+    TileCtx c;
+    c.EH = a.EH;
+    c.EW = a.EW;
+    c.TH = a.TH;
+    c.TW = a.TW;
+    c.R = a.R;
+    c.EWp = a.EWp;
+    c.EHp = a.EHp;
+    c.tfl = tile_t_floats(a.TW, a.EHp);
+    const int pfl = tile_plane_floats(a.EH, a.EWp);
+    c.gpl = smem;
+    c.hpl = c.gpl + pfl;
+    c.Tb = (MODE == kBackward) ? c.hpl + pfl : c.gpl + pfl;
+    c.gT = c.Tb + 2 * c.tfl;
+    c.t = threadIdx.x;
+    c.wave = __builtin_amdgcn_readfirstlane(c.t >> 6);
+    c.lane = c.t & 63;
+    const int ty = tile_id / a.tiles_x, tx = tile_id - ty * a.tiles_x;
+    c.i0 = ty * a.TH;
+    c.j0 = tx * a.TW;
+    c.ei0 = c.i0 - a.R;
+    c.ej0 = c.j0 - a.R;
+
+    fill_plane(a, c, c.gpl, [&](size_t k) { return a.f[k] - a.center; });
+    if (MODE == kBackward) {
+        // A = G / eta, staged where h goes once the row lanes have taken it
+        fill_plane(a, c, c.hpl, [&](size_t k) {
+            const float G = a.gout ? a.gout[k] : 2.0f * (a.fout[k] - a.target[k]);
+            return G / a.feta[k];
+        });
+    }
+    __syncthreads();
+    if (MODE == kForward) {
+        // output columns, contiguous, for the column lanes' 16-byte loads
+        for (int p = c.t; p < kGtFloats; p += kTileThreads) {
+            const int jj = p / kGtPitch, k = p - jj * kGtPitch;
+            c.gT[p] = (jj < a.TW && k < a.TH) ? c.gpl[(k + a.R) * a.EWp + a.R + jj] : 0.0f;
+        }
+        __syncthreads();
+    }
+    if (c.wave < 2)
+        row_role<MODE>(a, c);
+    else
+        col_role<MODE, AUX>(a, c, tile_id);
+}
+
+template <int MODE, bool AUX>
 __global__ void __launch_bounds__(kTileThreads)
 bf_tile_kernel(const TileArgs a) {
-    extern __shared__ float smem[];
-    tile_body<MODE>(a, blockIdx.x, smem);
+    extern __shared__ __align__(16) float smem[];
+    tile_body<MODE, AUX>(a, blockIdx.x, smem);
 }
 
 // Host helpers shared by the single-image and batched launchers (bf_tile.hip).

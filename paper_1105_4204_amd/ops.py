@@ -30,17 +30,24 @@ def _ptr(x):
 
 
 def trig_forward(f: torch.Tensor, T: float, sigma_r: float, radii, N: int = 0,
-                 return_eta: bool = False, tile=None, out: torch.Tensor | None = None):
-    """O(1) raised-cosine bilateral filter of a 2-D image (fused HIP kernel)."""
+                 return_eta: bool = False, tile=None, out: torch.Tensor | None = None,
+                 return_aux: bool = False):
+    """O(1) raised-cosine bilateral filter of a 2-D image (fused HIP kernel).
+
+    Returns out, or (out, eta) with return_eta, or (out, eta, aux) with
+    return_aux, where aux (2 x H x W) holds the sums the backward needs."""
     _check_img(f, "f")
     H, W = f.shape
     out = torch.empty_like(f) if out is None else out
-    eta = torch.empty_like(f) if return_eta else None
+    eta = torch.empty_like(f) if (return_eta or return_aux) else None
+    aux = torch.empty((2, H, W), device=f.device, dtype=f.dtype) if return_aux else None
     spec = nat.SpatialSpec.of(radii)
-    opts = nat.make_opts(_stream_ptr(), N, _ptr(eta), tile)
+    opts = nat.make_opts(_stream_ptr(), N, _ptr(eta), tile, _ptr(aux))
     nat.check(nat.lib().bf_trig_forward_ex(_ptr(f), H, W, float(T), float(sigma_r),
                                            ctypes.byref(spec), _ptr(out), ctypes.byref(opts)),
               "bf_trig_forward_ex")
+    if return_aux:
+        return out, eta, aux
     return (out, eta) if return_eta else out
 
 
@@ -59,39 +66,45 @@ def direct_forward(f: torch.Tensor, T: float, sigma_r: float, radii, N: int = 0,
     return (out, eta) if return_eta else out
 
 
-def trig_backward(f, out, eta, grad_out, T: float, sigma_r: float, radii, N: int = 0,
+def trig_backward(f, out, eta, aux, grad_out, T: float, sigma_r: float, radii, N: int = 0,
                   tile=None):
-    """grad_f = J^T grad_out for the forward that produced (out, eta)."""
+    """grad_f = J^T grad_out for the forward that produced (out, eta, aux)."""
     for x, n in ((f, "f"), (out, "out"), (eta, "eta"), (grad_out, "grad_out")):
         _check_img(x, n)
     H, W = f.shape
+    if (not isinstance(aux, torch.Tensor) or not aux.is_cuda or aux.dtype != torch.float32
+            or tuple(aux.shape) != (2, H, W) or not aux.is_contiguous()):
+        raise TypeError("aux must be the contiguous 2 x H x W float32 tensor of the forward")
     gf = torch.empty_like(f)
     spec = nat.SpatialSpec.of(radii)
     opts = nat.make_opts(_stream_ptr(), N, None, tile)
-    nat.check(nat.lib().bf_trig_backward(_ptr(f), _ptr(out), _ptr(eta), _ptr(grad_out), H, W,
-                                         float(T), float(sigma_r), ctypes.byref(spec), _ptr(gf),
-                                         ctypes.byref(opts)),
+    nat.check(nat.lib().bf_trig_backward(_ptr(f), _ptr(out), _ptr(eta), _ptr(aux),
+                                         _ptr(grad_out), H, W, float(T), float(sigma_r),
+                                         ctypes.byref(spec), _ptr(gf), ctypes.byref(opts)),
               "bf_trig_backward")
     return gf
 
 
 class BFTrig(torch.autograd.Function):
-    """Autograd wrapper: forward saves (f, out, eta); backward calls the
+    """Autograd wrapper: forward saves (f, out, eta, aux); backward calls the
     hand-written adjoint kernel.  T, sigma_r, radii and N are constants."""
 
     @staticmethod
     def forward(ctx, f, T, sigma_r, radii, N):
         f = f.contiguous()
-        out, eta = trig_forward(f, T, sigma_r, radii, N, return_eta=True)
-        ctx.save_for_backward(f, out, eta)
+        if ctx.needs_input_grad[0]:
+            out, eta, aux = trig_forward(f, T, sigma_r, radii, N, return_aux=True)
+            ctx.save_for_backward(f, out, eta, aux)
+        else:
+            out = trig_forward(f, T, sigma_r, radii, N)
         ctx.params = (T, sigma_r, tuple(radii), N)
         return out
 
     @staticmethod
     def backward(ctx, grad_out):
-        f, out, eta = ctx.saved_tensors
+        f, out, eta, aux = ctx.saved_tensors
         T, sigma_r, radii, N = ctx.params
-        gf = trig_backward(f, out, eta, grad_out.contiguous(), T, sigma_r, radii, N)
+        gf = trig_backward(f, out, eta, aux, grad_out.contiguous(), T, sigma_r, radii, N)
         return gf, None, None, None, None
 
 

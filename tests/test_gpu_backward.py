@@ -56,8 +56,8 @@ def test_backward_small_full_parity(case):
     ref = oracle.grad(f, sr, Nuse, radii, G)
     ops = _ops()
     fg = _cuda(f)
-    out, eta = ops.trig_forward(fg, 255.0, sr, radii, N=N, return_eta=True)
-    gf = ops.trig_backward(fg, out, eta, _cuda(G), 255.0, sr, radii, N=N)
+    out, eta, aux = ops.trig_forward(fg, 255.0, sr, radii, N=N, return_aux=True)
+    gf = ops.trig_backward(fg, out, eta, aux, _cuda(G), 255.0, sr, radii, N=N)
     torch.cuda.synchronize()
     _check(gf.cpu().numpy(), ref, f"grad {case}")
 
@@ -71,8 +71,8 @@ def test_autograd_matches_explicit_backward():
     loss = ((out - _cuda(t_np)) ** 2).sum()
     loss.backward()
     fd = _cuda(f_np)
-    o2, e2 = ops.trig_forward(fd, 255.0, 25.0, [2, 2, 3], return_eta=True)
-    g2 = ops.trig_backward(fd, o2, e2, 2.0 * (o2 - _cuda(t_np)), 255.0, 25.0, [2, 2, 3])
+    o2, e2, x2 = ops.trig_forward(fd, 255.0, 25.0, [2, 2, 3], return_aux=True)
+    g2 = ops.trig_backward(fd, o2, e2, x2, 2.0 * (o2 - _cuda(t_np)), 255.0, 25.0, [2, 2, 3])
     torch.cuda.synchronize()
     assert torch.equal(f.grad, g2)
 
@@ -89,8 +89,9 @@ def test_config4_ssd_gradient_vs_fd_and_oracle():
     grads = []
     for i in range(16):
         f = _cuda(fb[i])
-        out, eta = ops.trig_forward(f, 255.0, sr, radii, return_eta=True)
-        grads.append(ops.trig_backward(f, out, eta, 2.0 * (out - _cuda(tb[i])), 255.0, sr, radii))
+        out, eta, aux = ops.trig_forward(f, 255.0, sr, radii, return_aux=True)
+        grads.append(ops.trig_backward(f, out, eta, aux, 2.0 * (out - _cuda(tb[i])), 255.0, sr,
+                                       radii))
     torch.cuda.synchronize()
     rng = np.random.default_rng(44)
     idx = rng.integers(0, 512 * 512, size=32)
@@ -114,9 +115,9 @@ def test_config4_ssd_gradient_vs_fd_and_oracle():
 def test_backward_deterministic():
     f = _cuda(synth.piecewise_smooth(200, 190, seed=5))
     ops = _ops()
-    out, eta = ops.trig_forward(f, 255.0, 20.0, [9, 9, 10], return_eta=True)
+    out, eta, aux = ops.trig_forward(f, 255.0, 20.0, [9, 9, 10], return_aux=True)
     G = torch.randn_like(f)
-    a = ops.trig_backward(f, out, eta, G, 255.0, 20.0, [9, 9, 10])
-    b = ops.trig_backward(f, out, eta, G, 255.0, 20.0, [9, 9, 10])
+    a = ops.trig_backward(f, out, eta, aux, G, 255.0, 20.0, [9, 9, 10])
+    b = ops.trig_backward(f, out, eta, aux, G, 255.0, 20.0, [9, 9, 10])
     torch.cuda.synchronize()
     assert torch.equal(a, b)

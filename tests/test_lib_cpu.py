@@ -86,6 +86,7 @@ def test_spatial_gaussian_integer_sigmas():
 
 FAKE = ctypes.c_void_p(0x10000000)
 FAKE2 = ctypes.c_void_p(0x20000000)
+FAKE3 = ctypes.c_void_p(0x30000000)
 
 
 def _fwd(f=FAKE, H=16, W=16, T=255.0, sr=30.0, radii=(2,), out=FAKE2, N=0, spec=None):
@@ -121,9 +122,13 @@ def test_backward_and_direct_validation():
     L = nat.lib()
     s = nat.SpatialSpec.of([2])
     o = nat.make_opts(None, 0)
-    assert L.bf_trig_backward(FAKE, None, FAKE, FAKE, 8, 8, 255.0, 30.0, ctypes.byref(s), FAKE2,
-                              ctypes.byref(o)) == 1
-    assert L.bf_trig_backward(FAKE, FAKE2, FAKE, FAKE, 8, 8, 255.0, 30.0, ctypes.byref(s), FAKE2,
-                              ctypes.byref(o)) == 1   # grad_f aliases out
+    assert L.bf_trig_backward(FAKE, None, FAKE, FAKE3, FAKE, 8, 8, 255.0, 30.0, ctypes.byref(s),
+                              FAKE2, ctypes.byref(o)) == 1
+    assert L.bf_trig_backward(FAKE, FAKE2, FAKE, FAKE3, FAKE, 8, 8, 255.0, 30.0, ctypes.byref(s),
+                              FAKE2, ctypes.byref(o)) == 1   # grad_f aliases out
+    assert L.bf_trig_backward(FAKE, FAKE3, FAKE, None, FAKE, 8, 8, 255.0, 30.0, ctypes.byref(s),
+                              FAKE2, ctypes.byref(o)) == 1   # aux missing
+    assert L.bf_trig_backward(FAKE, FAKE3, FAKE, ctypes.c_void_p(0x20000000 - 256), FAKE, 8, 8, 255.0, 30.0,
+                              ctypes.byref(s), FAKE2, ctypes.byref(o)) == 1   # aux runs into grad_f
     assert L.bf_direct_forward(FAKE, 8, 8, 255.0, -2.0, ctypes.byref(s), FAKE2,
                                ctypes.byref(o)) == 1
