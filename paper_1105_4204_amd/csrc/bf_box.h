@@ -36,18 +36,43 @@ __device__ __forceinline__ void box_stage(float (&v)[L]) {
 }
 
 // Applies box_stage<L, r> for a wave-uniform run-time r (held in an SGPR).
-// The candidates are tried one after another, each in its own block: the
+//
+// box_tree: binary search over the instantiations, five uniform two-way
+// branches per call.  Its joins merge the line from both sides, which costs
+// register copies where a caller keeps much other state live.
+template <int L, int LO, int HI>
+__device__ __forceinline__ void box_tree(float (&v)[L], int r) {
+    if constexpr (LO == HI) {
+        if constexpr (2 * LO < L) box_stage<L, LO>(v);
+    } else {
+        constexpr int MID = (LO + HI) / 2;
+        if (r <= MID)
+            box_tree<L, LO, MID>(v, r);
+        else
+            box_tree<L, MID + 1, HI>(v, r);
+    }
+}
+
+// box_chain: the candidates one after another, each in its own block; the
 // empty asm makes r opaque between blocks, so the compiler cannot fold the
-// chain into one multi-way branch, whose single join would merge 32 copies of
-// the line and spill it; a chain of two-way joins keeps the line in place.
-template <int L, int R = 0>
-__device__ __forceinline__ void box_dispatch(float (&v)[L], int r) {
-    if constexpr (R == 0) r = __builtin_amdgcn_readfirstlane(r);
-    if constexpr (R <= kBoxMaxRadius && 2 * R < L) {
+// chain into one multi-way branch, and every join is two-way with the line
+// in place.  Costs a taken branch per candidate below r.
+template <int L, int R, int RE>
+__device__ __forceinline__ void box_chain(float (&v)[L], int r) {
+    if constexpr (R <= RE && 2 * R < L) {
         if (r == R) box_stage<L, R>(v);
         asm volatile("" : "+s"(r));
-        box_dispatch<L, R + 1>(v, r);
+        box_chain<L, R + 1, RE>(v, r);
     }
+}
+
+template <int L, bool TREE>
+__device__ __forceinline__ void box_dispatch(float (&v)[L], int r) {
+    r = __builtin_amdgcn_readfirstlane(r);
+    if constexpr (TREE)
+        box_tree<L, 0, kBoxMaxRadius>(v, r);
+    else
+        box_chain<L, 0, kBoxMaxRadius>(v, r);
 }
 
 }  // namespace bf

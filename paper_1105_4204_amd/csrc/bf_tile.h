@@ -86,24 +86,22 @@ __host__ __device__ inline size_t tile_lds_floats(int mode, int TH, int TW, int 
            2 * (size_t)tile_t_floats(TW, tile_pitch(EH)) + (mode == kForward ? kGtFloats : 0);
 }
 
-// exp(j x) for |x| <= pi/2 by the Taylor series of cos (to x^14) and sin (to
-// x^13); truncation error below 1e-9 on that interval.
+// exp(j x) for |x| <= pi/2: cos x = 1 + x^2 P(x^2), sin x = x + x^3 Q(x^2)
+// with P of degree 4 and Q of degree 3, near-minimax on that interval
+// (coefficients from gen_cis_coeffs.py); truncation error below 5e-9, so the
+// float32 rounding of the evaluation dominates.
 __device__ __forceinline__ void cis_small(float x, float& c, float& s) {
     const float x2 = x * x;
-    float pc = -1.0f / 87178291200.0f;                 // -1/14!
-    pc = fmaf(pc, x2, 1.0f / 479001600.0f);            //  1/12!
-    pc = fmaf(pc, x2, -1.0f / 3628800.0f);             // -1/10!
-    pc = fmaf(pc, x2, 1.0f / 40320.0f);                //  1/8!
-    pc = fmaf(pc, x2, -1.0f / 720.0f);                 // -1/6!
-    pc = fmaf(pc, x2, 1.0f / 24.0f);                   //  1/4!
-    pc = fmaf(pc, x2, -0.5f);                          // -1/2!
+    float pc = -2.607594922e-07f;
+    pc = fmaf(pc, x2, 2.476181544e-05f);
+    pc = fmaf(pc, x2, -1.388840145e-03f);
+    pc = fmaf(pc, x2, 4.166664183e-02f);
+    pc = fmaf(pc, x2, -5.000000000e-01f);
     c = fmaf(pc, x2, 1.0f);
-    float ps = 1.0f / 6227020800.0f;                   //  1/13!
-    ps = fmaf(ps, x2, -1.0f / 39916800.0f);            // -1/11!
-    ps = fmaf(ps, x2, 1.0f / 362880.0f);               //  1/9!
-    ps = fmaf(ps, x2, -1.0f / 5040.0f);                // -1/7!
-    ps = fmaf(ps, x2, 1.0f / 120.0f);                  //  1/5!
-    ps = fmaf(ps, x2, -1.0f / 6.0f);                   // -1/3!
+    float ps = 2.599969775e-06f;
+    ps = fmaf(ps, x2, -1.980657107e-04f);
+    ps = fmaf(ps, x2, 8.333016187e-03f);
+    ps = fmaf(ps, x2, -1.666665673e-01f);
     s = fmaf(ps * x2, x, x);
 }
 
@@ -244,7 +242,7 @@ __device__ __forceinline__ void row_role(const TileArgs& a, const TileCtx& c) {
 #pragma unroll
                 for (int x = 0; x < kLine; ++x) v[x] *= A1[x];
             }
-            for (int b = 0; b < a.nb; ++b) box_dispatch<kLine>(v, a.r[b]);
+            for (int b = 0; b < a.nb; ++b) box_dispatch<kLine, MODE == kForward>(v, a.r[b]);
             float* dst = c.Tb + (s & 1) * c.tfl + i;
 #pragma unroll
             for (int j0c = 0; j0c < kOutMax; j0c += kChunk) {
@@ -326,7 +324,7 @@ __device__ __forceinline__ void col_role(const TileArgs& a, const TileCtx& c, in
                 }
             }
             load_line(v, c.Tb + ((s - 1) & 1) * c.tfl + j * c.EHp);
-            for (int b = 0; b < a.nb; ++b) box_dispatch<kLine>(v, a.r[b]);
+            for (int b = 0; b < a.nb; ++b) box_dispatch<kLine, MODE == kForward>(v, a.r[b]);
             const float cq = a.chat[q];
             const float m = (float)(a.odd + 2 * q);
             // accumulate over the output rows k < TH; the channel picks the

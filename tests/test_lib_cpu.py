@@ -132,3 +132,26 @@ def test_backward_and_direct_validation():
                               ctypes.byref(s), FAKE2, ctypes.byref(o)) == 1   # aux runs into grad_f
     assert L.bf_direct_forward(FAKE, 8, 8, 255.0, -2.0, ctypes.byref(s), FAKE2,
                                ctypes.byref(o)) == 1
+
+
+def test_phase_polynomial_constants_and_accuracy():
+    """The constants of cis_small() in bf_tile.h are those the generator
+    derives, and their float32 evaluation is within 2e-7 of cos/sin on
+    |x| <= pi/2 (the range of the per-pair phase step when N meets the degree
+    bound and f lies in [0, T])."""
+    import importlib.util
+    import re
+    csrc = os.path.join(ROOT, "paper_1105_4204_amd", "csrc")
+    spec = importlib.util.spec_from_file_location("gen", os.path.join(csrc, "gen_cis_coeffs.py"))
+    gen = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(gen)
+    cc, sc = gen.coefficients()
+    src = open(os.path.join(csrc, "bf_tile.h")).read()
+    body = src[src.index("void cis_small"):src.index("void load_line")]
+    lits = [float(v) for v in re.findall(r"(-?\d\.\d+e[-+]\d+)f", body)]
+    assert lits == pytest.approx(cc[::-1] + sc[::-1], rel=1e-8)
+    x = np.linspace(-np.pi / 2, np.pi / 2, 100001)
+    c, s = gen.eval32(cc, sc, x)
+    xr = x.astype(np.float32).astype(np.float64)
+    assert np.abs(c - np.cos(xr)).max() < 2e-7
+    assert np.abs(s - np.sin(xr)).max() < 2e-7
