@@ -262,13 +262,9 @@ __device__ __forceinline__ void row_role(const TileArgs& a, const TileCtx& c) {
 }
 
 // Column role (waves 2-3): lane j owns output column j.  State: A0[0..64) +
-// j A1[0..64) = Z at the column's outputs; tails (A0 | A1): forward den | Q
-// on wave 2 and num | P on wave 3; adjoint, wave 2: the C-weighted sum
-// sum_m c_m (C F[A C] + S F[A S]) | its g-weighted partner
-// sum_m c_m m (C F[A S] - S F[A C]) (g at the output is the same for every m,
-// so a g is applied once at the end), wave 3: - | sum_m c_m m a (S F[B C] -
-// C F[B S]).  Wave 2 filters the channels with even index, wave 3 the odd
-// ones.
+// j A1[0..64) = Z at the column's outputs; tails: forward den|num (A0) and
+// Q|P (A1) on wave 2|3; adjoint g at the outputs (A0) and the partial sum
+// (A1).  Wave 2 filters the channels with even index, wave 3 the odd ones.
 template <int MODE, bool AUX>
 __device__ __forceinline__ void col_role(const TileArgs& a, const TileCtx& c, int tile_id) {
     const int j = c.lane;
@@ -288,15 +284,9 @@ __device__ __forceinline__ void col_role(const TileArgs& a, const TileCtx& c, in
                 v[4 * k + 3] = q4.w;
             }
         } else {
-            // strided column of the extended plane; the opaque offset keeps
-            // the 64 addresses from being hoisted (and spilled) across steps
-            int off = (c.R * c.EWp + c.R + j) * (int)sizeof(float);
-            asm volatile("" : "+v"(off));
-            const char* base = reinterpret_cast<const char*>(c.gpl) + off;
-            const int pitch = c.EWp * (int)sizeof(float);
+            const float* gcol = c.gpl + c.R * c.EWp + c.R + j;
 #pragma unroll
-            for (int k = 0; k < kOutMax; ++k)
-                v[k] = *reinterpret_cast<const float*>(base + min(k, TH - 1) * pitch);
+            for (int k = 0; k < kOutMax; ++k) v[k] = gcol[min(k, TH - 1) * c.EWp];
         }
     };
     if (act) {
@@ -313,7 +303,7 @@ __device__ __forceinline__ void col_role(const TileArgs& a, const TileCtx& c, in
         }
 #pragma unroll
         for (int k = 0; k < kOutMax; ++k) {
-            A0[kOutMax + k] = 0.0f;
+            A0[kOutMax + k] = (MODE == kBackward) ? v[k] : 0.0f;
             A1[kOutMax + k] = 0.0f;
         }
     }
@@ -326,8 +316,12 @@ __device__ __forceinline__ void col_role(const TileArgs& a, const TileCtx& c, in
     for (int s = 0; s <= a.nsteps; ++s) {
         if (s > 0 && (ch & 1) == (c.wave - 2) && act) {
             if ((ch >> 1) == 0 && q > 0) {
-                load_gcol();
-                phase_step<kOutMax>(A0, A1, v, 0, a.two_alpha);
+                if (MODE == kBackward) {          // g kept in the A0 tail
+                    phase_step<kOutMax>(A0, A1, A0, kOutMax, a.two_alpha);
+                } else {
+                    load_gcol();
+                    phase_step<kOutMax>(A0, A1, v, 0, a.two_alpha);
+                }
             }
             load_line(v, c.Tb + ((s - 1) & 1) * c.tfl + j * c.EHp);
             for (int b = 0; b < a.nb; ++b) box_dispatch<kLine, MODE == kForward>(v, a.r[b]);
@@ -347,21 +341,26 @@ __device__ __forceinline__ void col_role(const TileArgs& a, const TileCtx& c, in
                     }
                 }
             };
-            const float cm = cq * m;
-            if (MODE == kForward || c.wave == 2) {
-                // forward: den|num and Q|P; adjoint wave 2 (A C, A S): the
-                // C-weighted sum and its m-weighted partner, same shape
-                const bool two = MODE == kBackward || AUX;
-                if (ch < 2) {   // C F[.] into the A0 tail; -m S F[.] into the A1 tail
+            if (MODE == kForward) {
+                const float cm = cq * m;
+                if (ch < 2) {   // C F[.] into den|num; -m S F[.] into Q|P
                     accumulate([&](int k) { return cq * A0[k]; }, A0);
-                    if (two) accumulate([&](int k) { return -cm * A1[k]; }, A1);
-                } else {        // S F[.] into the A0 tail; m C F[.] into the A1 tail
+                    if (AUX) accumulate([&](int k) { return -cm * A1[k]; }, A1);
+                } else {        // S F[.] into den|num; m C F[.] into Q|P
                     accumulate([&](int k) { return cq * A1[k]; }, A0);
-                    if (two) accumulate([&](int k) { return cm * A0[k]; }, A1);
+                    if (AUX) accumulate([&](int k) { return cm * A0[k]; }, A1);
                 }
             } else {
-                const float cma = cm * a.alpha_f;
-                if (ch == 1)        // B C: c ma S
+                const float cma = cq * m * a.alpha_f;
+                if (ch == 0)        // A C: c (C - ma g S)
+                    accumulate(
+                        [&](int k) { return fmaf(-cma * A0[kOutMax + k], A1[k], cq * A0[k]); },
+                        A1);
+                else if (ch == 2)   // A S: c (S + ma g C)
+                    accumulate(
+                        [&](int k) { return fmaf(cma * A0[kOutMax + k], A0[k], cq * A1[k]); },
+                        A1);
+                else if (ch == 1)   // B C: c ma S
                     accumulate([&](int k) { return cma * A1[k]; }, A1);
                 else                // B S: -c ma C
                     accumulate([&](int k) { return -cma * A0[k]; }, A1);
@@ -424,10 +423,8 @@ __device__ __forceinline__ void col_role(const TileArgs& a, const TileCtx& c, in
                             const float Ak = G / a.feta[gidx];
                             const float Bk = Ak * (fo - a.center);
                             const float P = a.paux[gidx], Q = a.paux[HW + gidx];
-                            const float g = c.gpl[(k + c.R) * c.EWp + c.R + j];
-                            a.out[gidx] =
-                                (fmaf(a.alpha_f * g, A1[kOutMax + k], A0[kOutMax + k]) + other) +
-                                a.alpha_f * (Ak * P - Bk * Q);
+                            a.out[gidx] = (A1[kOutMax + k] + other) +
+                                          a.alpha_f * (Ak * P - Bk * Q);
                         }
                     }
                 }
