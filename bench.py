@@ -45,9 +45,15 @@ WORKLOADS = {
 
 # HBM bytes per launch of the fused kernels measured with rocprofv3 --pmc
 # FETCH_SIZE and WRITE_SIZE (separate runs), each scaled by the factor that
-# maps the same counter of a plain copy kernel onto its known size; valid only
-# for the kernel sources they were taken on (hash of TILE_SOURCES).
-MEASURED_TRAFFIC = {}
+# maps the same counter of a plain copy kernel onto its known size (FETCH_SIZE
+# x 2.0, WRITE_SIZE x 1.0 for a 512 MiB device copy); valid only for the
+# kernel sources they were taken on (hash of TILE_SOURCES).  Record:
+# profiles/bf_tile_kernels_2048x2048_N66_hbm_traffic.md.
+MEASURED_TRAFFIC = {
+    ("bf_tile_kernel<kForward,false>", "config2"): {"bytes": 54997835, "src": "5b5035567f95"},
+    ("bf_tile_kernel<kForward,true>", "config2"): {"bytes": 110853088, "src": "5b5035567f95"},
+    ("bf_tile_kernel<kBackward,false>", "config2"): {"bytes": 328799321, "src": "5b5035567f95"},
+}
 TILE_SOURCES = ("bf_tile.h", "bf_box.h", "bf_tile.hip")
 
 
@@ -308,7 +314,10 @@ def main():
     hbm = {"algorithmic_bytes_per_step": step_bytes,
            "achieved_GBs": round(step_bytes / (ms_step / 1e3) / 1e9, 2),
            "peak_GBs": PEAK_HBM_GBS,
-           "frac": round(step_bytes / (ms_step / 1e3) / 1e9 / PEAK_HBM_GBS, 5)}
+           "frac": round(step_bytes / (ms_step / 1e3) / 1e9 / PEAK_HBM_GBS, 5),
+           "dominant_kernel_measured_GBs": (round(traffic / (kms / 1e3) / 1e9, 2)
+                                            if traffic is not None else None),
+           "note": "ALU-bound: 2(N+1) filtered channels per pixel stay in registers and LDS"}
 
     batch_res = None
     if not args.no_batch and do_bwd and args.workload == "config2":
