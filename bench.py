@@ -38,6 +38,9 @@ WORKLOADS = {
     "config1": dict(H=256, W=256, radii=[5], sigma_r=30.0, gen="rect", seed=1,
                     desc="256x256 f32 12 rectangles over a ramp + N(0,10^2), box r=5, T=255, "
                          "sigma_r=30, N=30"),
+    "config3": dict(H=4096, W=4096, sigma_s=30.0, sigma_r=10.0, gen="smooth", seed=3,
+                    desc="4096x4096 f32 piecewise-smooth, sigma_s=30 as 3 boxes (29,29,30), T=255, "
+                         "sigma_r=10, N=264 (staged wide-kernel path, forward only)"),
     "config4": dict(H=512, W=512, sigma_s=6.0, sigma_r=25.0, gen="smooth", seed=4000,
                     desc="512x512 f32 piecewise-smooth, sigma_s=6 as 3 boxes (5,5,6), T=255, "
                          "sigma_r=25, N=43"),

@@ -74,6 +74,10 @@ typedef struct {
     float* aux_out;      /* forward only: optional 2*H*W device buffer for the
                             two auxiliary sums the backward needs (see
                             bf_trig_backward); NULL = not computed */
+    void* workspace;     /* forward only: device scratch for spatial kernels
+                            wider than the fused kernel handles (see
+                            bf_trig_workspace_bytes); NULL if none */
+    int64_t workspace_bytes;
 } bf_opts;
 
 /* Algorithm 1 steps 1-2: N = ceil((gamma sigma_r)^-2), gamma = pi/(2T).
@@ -92,6 +96,16 @@ bf_status bf_range_coeffs(int32_t N, float* c_out, int32_t cap, int32_t* n_out);
  * sqrt(12 sigma_s^2 / n + 1), mixing the nearest odd widths below and above,
  * the narrower ones first, ties to the narrower. */
 bf_status bf_spatial_gaussian(double sigma_s, int32_t n_boxes, bf_spatial_spec* out);
+
+/* Device workspace the forward needs for image size H x W and this spatial
+ * kernel: 0 when the fused single-pass kernel applies (sum of radii R <= 63,
+ * every radius <= 31); 24*H*W bytes for the staged path (63 < R <= 127,
+ * every radius <= 31), which filters the channels of each cosine pair in two
+ * separable passes through this workspace (Sec. 2.1, eq. (final-form)).
+ * BF_EUNSUPPORTED when neither path handles the kernel.  The staged path is
+ * forward only (no aux_out). */
+bf_status bf_trig_workspace_bytes(int64_t H, int64_t W, const bf_spatial_spec* spatial_spec,
+                                  int64_t* bytes_out);
 
 /* Forward filter, eq. (BF)/(normalization) with the raised-cosine kernel.
  * f: H*W input; out: H*W output (must not overlap f).  sigma_r > 0, T > 0.

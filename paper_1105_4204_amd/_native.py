@@ -21,7 +21,8 @@ STATUS = {0: "BF_OK", 1: "BF_EINVAL", 2: "BF_ERANGE", 3: "BF_ENOMEM", 4: "BF_EDE
           5: "BF_ECAPTURE", 6: "BF_EUNSUPPORTED"}
 
 # exported symbols, in the order include/bf_trig.h declares them
-EXPORTS = ["bf_range_degree", "bf_range_coeffs", "bf_spatial_gaussian", "bf_trig_forward",
+EXPORTS = ["bf_range_degree", "bf_range_coeffs", "bf_spatial_gaussian",
+           "bf_trig_workspace_bytes", "bf_trig_forward",
            "bf_trig_forward_ex", "bf_trig_backward", "bf_direct_forward",
            "bf_batch_plan_create", "bf_batch_bind", "bf_batch_launch", "bf_batch_check",
            "bf_batch_plan_destroy", "bf_status_string", "bf_last_error"]
@@ -54,7 +55,8 @@ class SpatialSpec(ctypes.Structure):
 class Opts(ctypes.Structure):
     _fields_ = [("stream", ctypes.c_void_p), ("N", ctypes.c_int32),
                 ("eta_out", ctypes.c_void_p), ("tile_h", ctypes.c_int32),
-                ("tile_w", ctypes.c_int32), ("aux_out", ctypes.c_void_p)]
+                ("tile_w", ctypes.c_int32), ("aux_out", ctypes.c_void_p),
+                ("workspace", ctypes.c_void_p), ("workspace_bytes", ctypes.c_int64)]
 
 
 class ImageDesc(ctypes.Structure):
@@ -83,6 +85,7 @@ def lib():
         "bf_range_degree": [f64, f64, ctypes.POINTER(i32)],
         "bf_range_coeffs": [i32, ctypes.POINTER(f32), i32, ctypes.POINTER(i32)],
         "bf_spatial_gaussian": [f64, i32, sp],
+        "bf_trig_workspace_bytes": [i64, i64, sp, ctypes.POINTER(i64)],
         "bf_trig_forward": [vp, i64, i64, f32, f32, sp, vp],
         "bf_trig_forward_ex": [vp, i64, i64, f32, f32, sp, vp, op],
         "bf_trig_backward": [vp, vp, vp, vp, vp, i64, i64, f32, f32, sp, vp, op],
@@ -133,11 +136,23 @@ def spatial_gaussian(sigma_s: float, n_boxes: int = 3):
     return s.radii()
 
 
-def make_opts(stream=None, N=0, eta_out=None, tile=None, aux_out=None) -> Opts:
+def make_opts(stream=None, N=0, eta_out=None, tile=None, aux_out=None, workspace=None,
+              workspace_bytes=0) -> Opts:
     o = Opts()
     o.stream = stream
     o.N = int(N)
     o.eta_out = eta_out
     o.tile_h, o.tile_w = (0, 0) if tile is None else (int(tile[0]), int(tile[1]))
     o.aux_out = aux_out
+    o.workspace = workspace
+    o.workspace_bytes = int(workspace_bytes)
     return o
+
+
+def workspace_bytes(H: int, W: int, radii) -> int:
+    """Device workspace the forward needs (0 for the fused single-pass kernel)."""
+    n = ctypes.c_int64()
+    spec = SpatialSpec.of(radii)
+    check(lib().bf_trig_workspace_bytes(int(H), int(W), ctypes.byref(spec), ctypes.byref(n)),
+          "bf_trig_workspace_bytes")
+    return int(n.value)

@@ -48,8 +48,53 @@ bf_status bf_trig_forward_ex(const float* f, int64_t H, int64_t W, float T, floa
     }
     TileGeom g;
     st = plan_fwd_tiles(H, W, c.sp, opts ? opts->tile_h : 0, opts ? opts->tile_w : 0, &g);
+    if (st == BF_EUNSUPPORTED && staged_supported(c.sp)) {
+        // spatial kernel wider than the fused kernel's register line
+        const size_t need = staged_workspace_bytes(H, W);
+        void* ws = opts ? opts->workspace : nullptr;
+        if (aux) {
+            set_error("R=%d: the adjoint's sums (aux_out) are only produced by the fused kernel "
+                      "(R <= 63)", c.sp.R);
+            return BF_EUNSUPPORTED;
+        }
+        if (!ws || opts->workspace_bytes < (int64_t)need) {
+            set_error("R=%d needs the staged path and a workspace of %zu bytes "
+                      "(bf_trig_workspace_bytes)", c.sp.R, need);
+            return BF_EINVAL;
+        }
+        if (overlaps(ws, (int64_t)need, f, bytes) || overlaps(ws, (int64_t)need, out, bytes) ||
+            overlaps(ws, (int64_t)need, eta, bytes)) {
+            set_error("workspace must not overlap the images");
+            return BF_EINVAL;
+        }
+        return launch_staged(f, out, eta, H, W, c.rp, c.sp, ws, c.stream);
+    }
     if (st != BF_OK) return st;
     return launch_fwd(f, out, eta, aux, H, W, c.rp, c.sp, g, c.stream);
+}
+
+bf_status bf_trig_workspace_bytes(int64_t H, int64_t W, const bf_spatial_spec* spatial_spec,
+                                  int64_t* bytes_out) {
+    if (!bytes_out) {
+        set_error("bytes_out is NULL");
+        return BF_EINVAL;
+    }
+    *bytes_out = 0;
+    if (H <= 0 || W <= 0) {
+        set_error("image size %lld x %lld must be positive", (long long)H, (long long)W);
+        return BF_EINVAL;
+    }
+    SpatialParams sp;
+    bf_status st = make_spatial(spatial_spec, &sp);
+    if (st != BF_OK) return st;
+    TileGeom g;
+    st = plan_fwd_tiles(H, W, sp, 0, 0, &g);
+    if (st == BF_OK) return BF_OK;
+    if (st == BF_EUNSUPPORTED && staged_supported(sp)) {
+        *bytes_out = (int64_t)staged_workspace_bytes(H, W);
+        return BF_OK;
+    }
+    return st;
 }
 
 bf_status bf_trig_forward(const float* f, int64_t H, int64_t W, float T, float sigma_r,

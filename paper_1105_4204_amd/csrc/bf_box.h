@@ -17,19 +17,38 @@ constexpr int kBoxMaxRadius = 31;   // radii handled by the register-line kernel
 // whose output at i is centred at i + R.  Running sum s += (enter - leave);
 // the difference for the next output is taken before the current output
 // overwrites its slot, so each new sum lands in place without register moves.
-template <int L, int R>
+// COMP adds Kahan compensation to the running sum (four adds per output
+// instead of one), which keeps its rounding from drifting along long lines of
+// large values; the fused kernel does not need it, the wide-kernel passes do.
+template <int L, int R, bool COMP = false>
 __device__ __forceinline__ void box_stage(float (&v)[L]) {
     static_assert(2 * R < L, "line shorter than the box");
     constexpr int W = 2 * R + 1;
-    float s = 0.0f;
+    float s = 0.0f, comp = 0.0f;
 #pragma unroll
-    for (int d = 0; d < W; ++d) s += v[d];
+    for (int d = 0; d < W; ++d) {
+        if (COMP) {
+            const float y = v[d] - comp;
+            const float u = s + y;
+            comp = (u - s) - y;
+            s = u;
+        } else {
+            s += v[d];
+        }
+    }
     float t = (W < L) ? v[W] - v[0] : 0.0f;
     v[0] = s;
 #pragma unroll
     for (int i = 1; i < L - 2 * R; ++i) {
         const float tn = (i + W < L) ? v[i + W] - v[i] : 0.0f;
-        s += t;
+        if (COMP) {
+            const float y = t - comp;
+            const float u = s + y;
+            comp = (u - s) - y;
+            s = u;
+        } else {
+            s += t;
+        }
         v[i] = s;
         t = tn;
     }
@@ -40,16 +59,16 @@ __device__ __forceinline__ void box_stage(float (&v)[L]) {
 // box_tree: binary search over the instantiations, five uniform two-way
 // branches per call.  Its joins merge the line from both sides, which costs
 // register copies where a caller keeps much other state live.
-template <int L, int LO, int HI>
+template <int L, int LO, int HI, bool COMP>
 __device__ __forceinline__ void box_tree(float (&v)[L], int r) {
     if constexpr (LO == HI) {
-        if constexpr (2 * LO < L) box_stage<L, LO>(v);
+        if constexpr (2 * LO < L) box_stage<L, LO, COMP>(v);
     } else {
         constexpr int MID = (LO + HI) / 2;
         if (r <= MID)
-            box_tree<L, LO, MID>(v, r);
+            box_tree<L, LO, MID, COMP>(v, r);
         else
-            box_tree<L, MID + 1, HI>(v, r);
+            box_tree<L, MID + 1, HI, COMP>(v, r);
     }
 }
 
@@ -57,22 +76,22 @@ __device__ __forceinline__ void box_tree(float (&v)[L], int r) {
 // empty asm makes r opaque between blocks, so the compiler cannot fold the
 // chain into one multi-way branch, and every join is two-way with the line
 // in place.  Costs a taken branch per candidate below r.
-template <int L, int R, int RE>
+template <int L, int R, int RE, bool COMP>
 __device__ __forceinline__ void box_chain(float (&v)[L], int r) {
     if constexpr (R <= RE && 2 * R < L) {
-        if (r == R) box_stage<L, R>(v);
+        if (r == R) box_stage<L, R, COMP>(v);
         asm volatile("" : "+s"(r));
-        box_chain<L, R + 1, RE>(v, r);
+        box_chain<L, R + 1, RE, COMP>(v, r);
     }
 }
 
-template <int L, bool TREE>
+template <int L, bool TREE, bool COMP = false>
 __device__ __forceinline__ void box_dispatch(float (&v)[L], int r) {
     r = __builtin_amdgcn_readfirstlane(r);
     if constexpr (TREE)
-        box_tree<L, 0, kBoxMaxRadius>(v, r);
+        box_tree<L, 0, kBoxMaxRadius, COMP>(v, r);
     else
-        box_chain<L, 0, kBoxMaxRadius>(v, r);
+        box_chain<L, 0, kBoxMaxRadius, COMP>(v, r);
 }
 
 }  // namespace bf

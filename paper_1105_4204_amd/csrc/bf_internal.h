@@ -55,6 +55,12 @@ bf_status launch_direct(const float* f, float* out, float* eta, int64_t H, int64
                         const RangeParams& rp, const SpatialParams& sp, hipStream_t stream);
 bf_status plan_bwd_tiles(int64_t H, int64_t W, const SpatialParams& sp, int req_h, int req_w,
                          TileGeom* g);
+// Staged forward for spatial radii beyond the fused kernel (bf_staged.hip).
+bool staged_supported(const SpatialParams& sp);
+size_t staged_workspace_bytes(int64_t H, int64_t W);
+bf_status launch_staged(const float* f, float* out, float* eta, int64_t H, int64_t W,
+                        const RangeParams& rp, const SpatialParams& sp, void* workspace,
+                        hipStream_t stream);
 bf_status launch_bwd(const float* f, const float* out, const float* eta, const float* aux,
                      const float* gout, float* gf, int64_t H, int64_t W, const RangeParams& rp,
                      const SpatialParams& sp, const TileGeom& g, hipStream_t stream);

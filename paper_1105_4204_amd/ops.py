@@ -42,7 +42,9 @@ def trig_forward(f: torch.Tensor, T: float, sigma_r: float, radii, N: int = 0,
     eta = torch.empty_like(f) if (return_eta or return_aux) else None
     aux = torch.empty((2, H, W), device=f.device, dtype=f.dtype) if return_aux else None
     spec = nat.SpatialSpec.of(radii)
-    opts = nat.make_opts(_stream_ptr(), N, _ptr(eta), tile, _ptr(aux))
+    nws = nat.workspace_bytes(H, W, radii)     # > 0: staged path for wide spatial kernels
+    ws = torch.empty(nws, device=f.device, dtype=torch.uint8) if nws else None
+    opts = nat.make_opts(_stream_ptr(), N, _ptr(eta), tile, _ptr(aux), _ptr(ws), nws)
     nat.check(nat.lib().bf_trig_forward_ex(_ptr(f), H, W, float(T), float(sigma_r),
                                            ctypes.byref(spec), _ptr(out), ctypes.byref(opts)),
               "bf_trig_forward_ex")

@@ -155,3 +155,31 @@ def test_phase_polynomial_constants_and_accuracy():
     xr = x.astype(np.float32).astype(np.float64)
     assert np.abs(c - np.cos(xr)).max() < 2e-7
     assert np.abs(s - np.sin(xr)).max() < 2e-7
+
+
+def test_workspace_query_and_staged_validation():
+    """R <= 63 (every radius <= 31) runs fused and needs no workspace; up to
+    R = 127 the staged path needs 24 bytes per pixel; wider kernels are
+    unsupported.  The forward rejects a staged request without workspace
+    (BF_EINVAL) and a request for the adjoint's sums (BF_EUNSUPPORTED)."""
+    assert nat.workspace_bytes(64, 80, [9, 9, 10]) == 0
+    assert nat.workspace_bytes(64, 80, [31, 31, 1]) == 0            # R = 63
+    assert nat.workspace_bytes(64, 80, [29, 29, 30]) == 24 * 64 * 80
+    assert nat.workspace_bytes(10, 10, [31, 31, 31, 31]) == 24 * 100   # R = 124
+    with pytest.raises(nat.BFError) as e:
+        nat.workspace_bytes(64, 80, [40])
+    assert e.value.code == 6
+    with pytest.raises(nat.BFError) as e:
+        nat.workspace_bytes(64, 80, [32, 31, 31])                 # a radius above 31
+    assert e.value.code == 6
+    L = nat.lib()
+    s = nat.SpatialSpec.of([29, 29, 30])
+    o = nat.make_opts(None, 0)
+    assert L.bf_trig_forward_ex(FAKE, 8, 8, 255.0, 10.0, ctypes.byref(s), FAKE2,
+                                ctypes.byref(o)) == 1          # no workspace
+    o2 = nat.make_opts(None, 0, None, None, FAKE3, ctypes.c_void_p(0x40000000), 24 * 64)
+    assert L.bf_trig_forward_ex(FAKE, 8, 8, 255.0, 10.0, ctypes.byref(s), FAKE2,
+                                ctypes.byref(o2)) == 6         # aux_out with the staged path
+    o3 = nat.make_opts(None, 0, None, None, None, ctypes.c_void_p(0x40000000), 24 * 64 - 4)
+    assert L.bf_trig_forward_ex(FAKE, 8, 8, 255.0, 10.0, ctypes.byref(s), FAKE2,
+                                ctypes.byref(o3)) == 1         # workspace too small
