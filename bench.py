@@ -148,6 +148,45 @@ def batch_bench(reps: int = 3):
                     "kernel replayed from a HIP graph"}
 
 
+def sigma_s_sweep(f, T, sr, sigmas=(2.0, 4.0, 6.0, 10.0, 16.0, 20.0, 30.0),
+                  direct_sigmas=(2.0, 10.0, 30.0), reps=3):
+    """Forward Mpixel/s at fixed sigma_r (fixed N) across spatial widths: the
+    O(1) filter's cost should not grow with sigma_s (the fused kernel up to
+    R = 63, the staged wide-kernel path beyond), while the direct-window
+    filter's grows with the window area."""
+    import torch
+
+    from paper_1105_4204_amd import _native, ops
+    H, W = f.shape
+    res = []
+    for ss in sigmas:
+        radii = _native.spatial_gaussian(ss, 3)
+        ops.trig_forward(f, T, sr, radii)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            ops.trig_forward(f, T, sr, radii)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        row = {"sigma_s": ss, "radii": radii, "R": sum(radii),
+               "path": "staged" if _native.workspace_bytes(H, W, radii) else "fused",
+               "fwd_ms": round(ms, 3), "fwd_mpix_s": round(H * W / 1e6 / (ms / 1e3), 1)}
+        if ss in direct_sigmas:
+            ops.direct_forward(f, T, sr, radii)
+            torch.cuda.synchronize()
+            e0.record()
+            ops.direct_forward(f, T, sr, radii)
+            e1.record()
+            torch.cuda.synchronize()
+            dms = e0.elapsed_time(e1)
+            row["direct_ms"] = round(dms, 3)
+            row["direct_mpix_s"] = round(H * W / 1e6 / (dms / 1e3), 1)
+        res.append(row)
+    return res
+
+
 def cpu_baseline(f, sigma_r, N, radii, budget_s=12.0, max_rows=1024):
     import numpy as np
     import oracle
@@ -178,6 +217,7 @@ def main():
     ap.add_argument("--no-direct", action="store_true")
     ap.add_argument("--fwd-only", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--no-sweep", action="store_true", help="skip the sigma_s sweep")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a 512 MiB device copy (counter calibration) and exit")
     args = ap.parse_args()
@@ -326,6 +366,10 @@ def main():
     if not args.no_batch and do_bwd and args.workload == "config2":
         batch_res = batch_bench()
 
+    sweep = None
+    if not args.no_sweep and args.workload == "config2":
+        sweep = sigma_s_sweep(f, T, sr)
+
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(f_np, sr, N, radii)
@@ -354,6 +398,7 @@ def main():
         "hbm": hbm,
         "roofline": roofline,
         "batch": batch_res,
+        "sigma_s_sweep": sweep,
         "cpu_baseline": cpu,
         "wall_s_timed": round(wall, 3),
     }

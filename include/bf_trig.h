@@ -97,13 +97,16 @@ bf_status bf_range_coeffs(int32_t N, float* c_out, int32_t cap, int32_t* n_out);
  * the narrower ones first, ties to the narrower. */
 bf_status bf_spatial_gaussian(double sigma_s, int32_t n_boxes, bf_spatial_spec* out);
 
-/* Device workspace the forward needs for image size H x W and this spatial
- * kernel: 0 when the fused single-pass kernel applies (sum of radii R <= 63,
- * every radius <= 31); 24*H*W bytes for the staged path (63 < R <= 127,
- * every radius <= 31), which filters the channels of each cosine pair in two
- * separable passes through this workspace (Sec. 2.1, eq. (final-form)).
+/* Device workspace the forward wants for image size H x W and this spatial
+ * kernel.  0: the fused single-pass kernel is used.  24*H*W bytes: the staged
+ * path, which filters the channels of each cosine pair in two separable
+ * passes through this workspace (Sec. 2.1, eq. (final-form)), is required
+ * (sum of radii 63 < R <= 127) or faster (the fused tiles shrink as R grows;
+ * from R of about 50 on a 2048^2 image).  Every radius must be <= 31;
  * BF_EUNSUPPORTED when neither path handles the kernel.  The staged path is
- * forward only (no aux_out). */
+ * forward only: with aux_out set the forward uses the fused kernel, which
+ * exists for R <= 63; without the workspace it also falls back to the fused
+ * kernel where that exists. */
 bf_status bf_trig_workspace_bytes(int64_t H, int64_t W, const bf_spatial_spec* spatial_spec,
                                   int64_t* bytes_out);
 

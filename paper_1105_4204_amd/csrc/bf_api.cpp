@@ -46,18 +46,27 @@ bf_status bf_trig_forward_ex(const float* f, int64_t H, int64_t W, float T, floa
         set_error("out / eta_out / aux_out must not overlap f or each other");
         return BF_EINVAL;
     }
-    TileGeom g;
-    st = plan_fwd_tiles(H, W, c.sp, opts ? opts->tile_h : 0, opts ? opts->tile_w : 0, &g);
-    if (st == BF_EUNSUPPORTED && staged_supported(c.sp)) {
-        // spatial kernel wider than the fused kernel's register line
-        const size_t need = staged_workspace_bytes(H, W);
-        void* ws = opts ? opts->workspace : nullptr;
+    TileGeom g = {};
+    const int req_h = opts ? opts->tile_h : 0, req_w = opts ? opts->tile_w : 0;
+    st = plan_fwd_tiles(H, W, c.sp, req_h, req_w, &g);
+    const bool fused_ok = st == BF_OK;
+    const size_t need = staged_workspace_bytes(H, W);
+    void* ws = opts ? opts->workspace : nullptr;
+    const bool have_ws = ws && opts->workspace_bytes >= (int64_t)need;
+    // the staged passes: where the fused kernel cannot hold the kernel width,
+    // or where its shrunken tiles cost more (and a workspace is given, no
+    // adjoint sums are requested and no tile shape was forced)
+    const bool staged =
+        staged_supported(c.sp) &&
+        (!fused_ok || (have_ws && !aux && req_h <= 0 && req_w <= 0 &&
+                       prefer_staged(H, W, c.sp, st, g)));
+    if (staged) {
         if (aux) {
             set_error("R=%d: the adjoint's sums (aux_out) are only produced by the fused kernel "
                       "(R <= 63)", c.sp.R);
             return BF_EUNSUPPORTED;
         }
-        if (!ws || opts->workspace_bytes < (int64_t)need) {
+        if (!have_ws) {
             set_error("R=%d needs the staged path and a workspace of %zu bytes "
                       "(bf_trig_workspace_bytes)", c.sp.R, need);
             return BF_EINVAL;
@@ -87,10 +96,10 @@ bf_status bf_trig_workspace_bytes(int64_t H, int64_t W, const bf_spatial_spec* s
     SpatialParams sp;
     bf_status st = make_spatial(spatial_spec, &sp);
     if (st != BF_OK) return st;
-    TileGeom g;
+    TileGeom g = {};
     st = plan_fwd_tiles(H, W, sp, 0, 0, &g);
-    if (st == BF_OK) return BF_OK;
-    if (st == BF_EUNSUPPORTED && staged_supported(sp)) {
+    if (st != BF_OK && st != BF_EUNSUPPORTED) return st;
+    if (prefer_staged(H, W, sp, st, g)) {
         *bytes_out = (int64_t)staged_workspace_bytes(H, W);
         return BF_OK;
     }

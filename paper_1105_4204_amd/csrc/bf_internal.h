@@ -57,6 +57,9 @@ bf_status plan_bwd_tiles(int64_t H, int64_t W, const SpatialParams& sp, int req_
                          TileGeom* g);
 // Staged forward for spatial radii beyond the fused kernel (bf_staged.hip).
 bool staged_supported(const SpatialParams& sp);
+struct TileGeom;
+bool prefer_staged(int64_t H, int64_t W, const SpatialParams& sp, bf_status fused_status,
+                   const TileGeom& g);
 size_t staged_workspace_bytes(int64_t H, int64_t W);
 bf_status launch_staged(const float* f, float* out, float* eta, int64_t H, int64_t W,
                         const RangeParams& rp, const SpatialParams& sp, void* workspace,

@@ -21,16 +21,19 @@
 // (the sum of w) against w(0), so where a pixel has few similar neighbours
 // the pair terms cancel heavily; both passes use compensated running sums.
 #include <algorithm>
+#include <cmath>
 
 #include "bf_tile.h"
 
 namespace bf {
 
 constexpr int kStLine = 256;      // register line of the staged passes
-constexpr int kStOutH = 64;       // outputs per horizontal line
-constexpr int kStVThreads = 256;  // columns per vertical workgroup
-constexpr int kStHRows = 64;      // rows per horizontal workgroup (one wave)
-constexpr int kStTrPitch = kStVThreads + 1;
+constexpr int kStThreads = 256;   // four waves: one per channel of a pair
+constexpr int kStCols = 64;       // vertical pass: columns per workgroup
+constexpr int kStOutV = 88;       // vertical pass: outputs per line, at most
+constexpr int kStRows = 64;       // horizontal pass: rows per workgroup
+constexpr int kStOutH = 64;       // horizontal pass: outputs per line, at most
+constexpr int kStPitch = kStCols + 1;
 
 struct StageArgs {
     const float* f;
@@ -41,8 +44,8 @@ struct StageArgs {
     float* eta;
     int H, W, R, nb;
     int r[BF_MAX_BOXES];
-    int nout_v;         // outputs per vertical line: 256 - 2R, at most 128
-    int nout_h;         // outputs per horizontal line: min(64, 256 - 2R)
+    int nout_v;         // outputs per vertical line: min(256 - 2R, kStOutV)
+    int nout_h;         // outputs per horizontal line: min(256 - 2R, kStOutH)
     int centre;         // this pair is m = 0 (channels 1, g)
     float c;            // c_m
     double malpha;      // m a
@@ -62,109 +65,108 @@ __device__ __forceinline__ void cis_direct(double malpha, float g, float& c, flo
     s = q == 0 ? sx : q == 1 ? cx : q == 2 ? -sx : -cx;
 }
 
+// Vertical pass.  Workgroup: 64 columns x one segment of nout_v output rows;
+// the 256 extended rows of g are staged in LDS once, then wave w builds
+// channel w (C, gC, S, gS; 1, g for m = 0) down its 64 columns, filters it
+// and writes it transposed through LDS.
 // One wave per SIMD: the 256-sample line needs the whole register file.
-__global__ void __launch_bounds__(kStVThreads) __attribute__((amdgpu_waves_per_eu(1, 1)))
+__global__ void __launch_bounds__(kStThreads) __attribute__((amdgpu_waves_per_eu(1, 1)))
 bf_stage_v(const StageArgs a) {
-    extern __shared__ __align__(16) float tr[];   // nout_v x kStTrPitch
+    extern __shared__ __align__(16) float lds[];
+    float* gtile = lds;                                   // [256][kStCols]
+    float* tr = lds + kStLine * kStCols;                  // [4][nout_v][kStPitch]
     const int t = threadIdx.x;
-    const int x = blockIdx.x * kStVThreads + t;
+    const int wave = __builtin_amdgcn_readfirstlane(t >> 6);
+    const int lane = t & 63;
+    const int x0 = blockIdx.x * kStCols;
     const int y0 = blockIdx.y * a.nout_v;
     const int ey0 = y0 - a.R;
-    const int xc = min(x, a.W - 1);
     const size_t HW = (size_t)a.H * a.W;
+    for (int p = t; p < kStLine * kStCols; p += kStThreads) {
+        const int yy = p / kStCols, xx = p - yy * kStCols;
+        const int gy = ey0 + yy, gx = x0 + xx;
+        gtile[p] = (gy >= 0 && gy < a.H && gx < a.W) ? a.f[(size_t)gy * a.W + gx] - a.center
+                                                     : 0.0f;
+    }
+    __syncthreads();
     const int nch = a.centre ? 2 : 4;
-    for (int ch = 0; ch < nch; ++ch) {
-        // opaque per channel: keeps the 256 row masks and addresses from being
-        // hoisted out of the channel loop (and spilled)
-        int eyo = ey0;
-        asm volatile("" : "+s"(eyo));
+    const int ch = wave;
+    float* trw = tr + (size_t)wave * a.nout_v * kStPitch;
+    if (ch < nch) {
+        const int x = x0 + lane;
         float v[kStLine];
 #pragma unroll
-        for (int y0c = 0; y0c < kStLine; y0c += kChunk) {
-            // a chunk of loads at a time: the barrier keeps the compiler from
-            // issuing all 256 loads (and holding their addresses) up front
-            asm volatile("" ::: "memory");
-#pragma unroll
-            for (int y = y0c; y < y0c + kChunk; ++y) {
-                const int gy = eyo + y;
-                const bool in = x < a.W && gy >= 0 && gy < a.H;
-                const int gyc = min(max(gy, 0), a.H - 1);
-                const float g = in ? a.f[(unsigned)(gyc * a.W + xc)] - a.center : 0.0f;
-                float val;
-                if (a.centre) {
-                    val = (ch == 0) ? 1.0f : g;
-                } else {
-                    float cc, ss;
-                    cis_direct(a.malpha, g, cc, ss);
-                    const float base = (ch >= 2) ? ss : cc;
-                    val = (ch & 1) ? g * base : base;
-                }
-                v[y] = in ? val : 0.0f;
+        for (int y = 0; y < kStLine; ++y) {
+            const int gy = ey0 + y;
+            const bool in = x < a.W && gy >= 0 && gy < a.H;
+            const float g = gtile[y * kStCols + lane];
+            float val;
+            if (a.centre) {
+                val = (ch == 0) ? 1.0f : g;
+            } else {
+                float cc, ss;
+                cis_direct(a.malpha, g, cc, ss);
+                const float base = (ch >= 2) ? ss : cc;
+                val = (ch & 1) ? g * base : base;
             }
+            v[y] = in ? val : 0.0f;
         }
         for (int b = 0; b < a.nb; ++b) box_dispatch<kStLine, false, true>(v, a.r[b]);
 #pragma unroll
-        for (int y0c = 0; y0c < 2 * kStOutH; y0c += kChunk) {
+        for (int y0c = 0; y0c < kStOutV; y0c += kChunk) {
             if (y0c < a.nout_v) {
 #pragma unroll
                 for (int yy = 0; yy < kChunk; ++yy)
-                    if (y0c + yy < a.nout_v) tr[(y0c + yy) * kStTrPitch + t] = v[y0c + yy];
+                    if (y0c + yy < a.nout_v) trw[(y0c + yy) * kStPitch + lane] = v[y0c + yy];
             }
         }
-        __syncthreads();
-        // transposed, coalesced write: consecutive threads, consecutive rows of one column
-        float* dst = a.vt + (size_t)ch * HW;
-        for (int p = t; p < kStVThreads * a.nout_v; p += kStVThreads) {
+    }
+    __syncthreads();
+    // transposed, coalesced writes: consecutive threads, consecutive rows of one column
+    for (int c2 = 0; c2 < nch; ++c2) {
+        const float* src = tr + (size_t)c2 * a.nout_v * kStPitch;
+        float* dst = a.vt + (size_t)c2 * HW;
+        for (int p = t; p < kStCols * a.nout_v; p += kStThreads) {
             const int xl = p / a.nout_v, yl = p - xl * a.nout_v;
-            const int X = blockIdx.x * kStVThreads + xl, Y = y0 + yl;
-            if (X < a.W && Y < a.H) dst[(size_t)X * a.H + Y] = tr[yl * kStTrPitch + xl];
+            const int X = x0 + xl, Y = y0 + yl;
+            if (X < a.W && Y < a.H) dst[(size_t)X * a.H + Y] = src[yl * kStPitch + xl];
         }
-        __syncthreads();
     }
 }
 
-__global__ void __launch_bounds__(kStHRows) __attribute__((amdgpu_waves_per_eu(1, 1)))
+// Horizontal pass.  Workgroup: 64 rows x nout_h output columns; wave w
+// filters channel w along its rows, demodulates with C or S at the outputs,
+// and the four contributions are summed in a fixed order into den and num.
+__global__ void __launch_bounds__(kStThreads) __attribute__((amdgpu_waves_per_eu(1, 1)))
 bf_stage_h(const StageArgs a) {
-    __shared__ float gt[kStHRows][kStOutH + 1];
+    __shared__ float gt[kStRows][kStOutH + 1];
+    __shared__ float red[4][kStOutH][kStRows + 1];
     const int t = threadIdx.x;
-    const int y = blockIdx.y * kStHRows + t;
+    const int wave = __builtin_amdgcn_readfirstlane(t >> 6);
+    const int lane = t & 63;
+    const int y = blockIdx.y * kStRows + lane;
     const int x0 = blockIdx.x * a.nout_h;
     const int ex0 = x0 - a.R;
     const int yc = min(y, a.H - 1);
     const size_t HW = (size_t)a.H * a.W;
-    for (int p = t; p < kStHRows * kStOutH; p += kStHRows) {
+    for (int p = t; p < kStRows * kStOutH; p += kStThreads) {
         const int yy = p / kStOutH, k = p - yy * kStOutH;
-        const int Y = blockIdx.y * kStHRows + yy, X = x0 + k;
+        const int Y = blockIdx.y * kStRows + yy, X = x0 + k;
         gt[yy][k] = (Y < a.H && X < a.W && k < a.nout_h) ? a.f[(size_t)Y * a.W + X] - a.center
                                                          : 0.0f;
     }
     __syncthreads();
-    float den[kStOutH], num[kStOutH], trig[kStOutH];
-#pragma unroll
-    for (int k = 0; k < kStOutH; ++k) {
-        den[k] = 0.0f;
-        num[k] = 0.0f;
-    }
     const int nch = a.centre ? 2 : 4;
-    for (int ch = 0; ch < nch; ++ch) {
-        if (!a.centre && (ch == 0 || ch == 2)) {   // C for channels 0, 1; S for 2, 3
-#pragma unroll
-            for (int k = 0; k < kStOutH; ++k) {
-                float cc, ss;
-                cis_direct(a.malpha, gt[t][k], cc, ss);
-                trig[k] = (ch == 0) ? cc : ss;
-            }
-        }
+    const int ch = wave;
+    if (ch < nch) {
         float v[kStLine];
         const float* src = a.vt + (size_t)ch * HW;
-        int exo = ex0;
-        asm volatile("" : "+s"(exo));
 #pragma unroll
         for (int x0c = 0; x0c < kStLine; x0c += 4 * kChunk) {
             asm volatile("" ::: "memory");
 #pragma unroll
             for (int x = x0c; x < x0c + 4 * kChunk; ++x) {
-                const int gx = exo + x;
+                const int gx = ex0 + x;
                 const bool in = y < a.H && gx >= 0 && gx < a.W;
                 const int gxc = min(max(gx, 0), a.W - 1);
                 const float val = src[(unsigned)(gxc * a.H + yc)];
@@ -172,23 +174,28 @@ bf_stage_h(const StageArgs a) {
             }
         }
         for (int b = 0; b < a.nb; ++b) box_dispatch<kStLine, false, true>(v, a.r[b]);
-        const bool to_num = ch & 1;   // gC, gS (g for the centre pair)
 #pragma unroll
         for (int k = 0; k < kStOutH; ++k) {
-            const float w = a.c * (a.centre ? 1.0f : trig[k]) * v[k];
-            if (to_num)
-                num[k] += w;
-            else
-                den[k] += w;
+            float w = a.c * v[k];
+            if (!a.centre) {
+                float cc, ss;
+                cis_direct(a.malpha, gt[lane][k], cc, ss);
+                w *= (ch >= 2) ? ss : cc;
+            }
+            red[ch][k][lane] = w;
         }
     }
-    if (y < a.H) {
-#pragma unroll
+    __syncthreads();
+    // fixed-order sums: den = (C F[C] + S F[S]), num = (C F[gC] + S F[gS])
+    if (wave == 0 && y < a.H) {
+#pragma unroll 8
         for (int k = 0; k < kStOutH; ++k) {
             const int X = x0 + k;
             if (k < a.nout_h && X < a.W) {
-                a.den_t[(size_t)X * a.H + y] += den[k];
-                a.num_t[(size_t)X * a.H + y] += num[k];
+                const float d = a.centre ? red[0][k][lane] : red[0][k][lane] + red[2][k][lane];
+                const float n = a.centre ? red[1][k][lane] : red[1][k][lane] + red[3][k][lane];
+                a.den_t[(size_t)X * a.H + y] += d;
+                a.num_t[(size_t)X * a.H + y] += n;
             }
         }
     }
@@ -238,6 +245,34 @@ bool staged_supported(const SpatialParams& sp) {
     return 2 * sp.R < kStLine;
 }
 
+// Cost model, per cosine pair, calibrated on MI355X (2048^2, N = 66): a round
+// of fused tiles (one workgroup per CU) takes about 26.5 us whatever the tile
+// size, a round of staged workgroups about 83 us per pass.  The fused tiles
+// shrink as R grows (the extended line is at most 128 samples), so past R of
+// about 50 the staged passes are cheaper.
+bool prefer_staged(int64_t H, int64_t W, const SpatialParams& sp, bf_status fused_status,
+                   const TileGeom& g) {
+    if (!staged_supported(sp)) return false;
+    if (fused_status != BF_OK) return true;
+    static int cus = 0;
+    if (cus == 0) {
+        int dev = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) !=
+                hipSuccess ||
+            cus <= 0)
+            cus = 256;
+    }
+    auto rounds = [&](double blocks) { return std::ceil(blocks / cus); };
+    const int nout_v = std::min(kStLine - 2 * sp.R, kStOutV);
+    const int nout_h = std::min(kStLine - 2 * sp.R, kStOutH);
+    const double bv = std::ceil((double)W / kStCols) * std::ceil((double)H / nout_v);
+    const double bh = std::ceil((double)W / nout_h) * std::ceil((double)H / kStRows);
+    const double fused_us = rounds((double)g.tiles_x * g.tiles_y) * 26.5;
+    const double staged_us = (rounds(bv) + rounds(bh)) * 83.0;
+    return staged_us < fused_us;
+}
+
 bf_status launch_staged(const float* f, float* out, float* eta, int64_t H, int64_t W,
                         const RangeParams& rp, const SpatialParams& sp, void* workspace,
                         hipStream_t stream) {
@@ -255,24 +290,25 @@ bf_status launch_staged(const float* f, float* out, float* eta, int64_t H, int64
     a.R = sp.R;
     a.nb = sp.nb;
     for (int k = 0; k < BF_MAX_BOXES; ++k) a.r[k] = sp.r[k];
-    a.nout_v = std::min(kStLine - 2 * sp.R, 2 * kStOutH);
+    a.nout_v = std::min(kStLine - 2 * sp.R, kStOutV);
     a.nout_h = std::min(kStLine - 2 * sp.R, kStOutH);
     a.center = rp.center;
-    const size_t lds_v = (size_t)a.nout_v * kStTrPitch * sizeof(float);
+    const size_t lds_v = ((size_t)kStLine * kStCols + 4 * (size_t)a.nout_v * kStPitch) *
+                         sizeof(float);
     (void)hipFuncSetAttribute((const void*)bf_stage_v, hipFuncAttributeMaxDynamicSharedMemorySize,
                               (int)lds_v);
     hipLaunchKernelGGL(bf_stage_zero, dim3(1024), dim3(256), 0, stream, a.den_t, 2 * HW);
-    const dim3 gv((unsigned)((W + kStVThreads - 1) / kStVThreads),
+    const dim3 gv((unsigned)((W + kStCols - 1) / kStCols),
                   (unsigned)((H + a.nout_v - 1) / a.nout_v));
     const dim3 gh((unsigned)((W + a.nout_h - 1) / a.nout_h),
-                  (unsigned)((H + kStHRows - 1) / kStHRows));
+                  (unsigned)((H + kStRows - 1) / kStRows));
     for (int q = 0; q < rp.npairs; ++q) {
         const int m = rp.odd + 2 * q;
         a.centre = (m == 0);
         a.c = rp.chat[q];
         a.malpha = (double)m * rp.alpha;
-        hipLaunchKernelGGL(bf_stage_v, gv, dim3(kStVThreads), lds_v, stream, a);
-        hipLaunchKernelGGL(bf_stage_h, gh, dim3(kStHRows), 0, stream, a);
+        hipLaunchKernelGGL(bf_stage_v, gv, dim3(kStThreads), lds_v, stream, a);
+        hipLaunchKernelGGL(bf_stage_h, gh, dim3(kStThreads), 0, stream, a);
     }
     hipLaunchKernelGGL(bf_stage_final, dim3((unsigned)((W + 31) / 32), (unsigned)((H + 31) / 32)),
                        dim3(256), 0, stream, a);
