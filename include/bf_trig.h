@@ -78,6 +78,9 @@ typedef struct {
                             wider than the fused kernel handles (see
                             bf_trig_workspace_bytes); NULL if none */
     int64_t workspace_bytes;
+    float trunc_tol;     /* 0 = every cosine pair; > 0 = drop the outer pairs
+                            while the bound of bf_range_truncate stays <= this
+                            many gray levels (forward and backward must agree) */
 } bf_opts;
 
 /* Algorithm 1 steps 1-2: N = ceil((gamma sigma_r)^-2), gamma = pi/(2T).
@@ -90,6 +93,18 @@ bf_status bf_range_degree(double T, double sigma_r, int32_t* N_out);
  * computed in extended precision and rounded to float.  Writes
  * n = floor(N/2)+1 values to c_out (capacity cap); *n_out = n. */
 bf_status bf_range_coeffs(int32_t N, float* c_out, int32_t cap, int32_t* n_out);
+
+/* Term truncation with an error bound (the acceleration for small sigma_r
+ * the paper leaves open in Sec. 3).  Removing the pairs q >= Q drops the
+ * binomial mass delta = sum_{q>=Q} c[q] from the kernel, |phi - phi_Q| <= delta,
+ * and since the normaliser of eq. (normalization) is at least w(0) (phi >= 0
+ * when N meets the degree bound, phi(0) = 1):
+ *     |out_Q - out| <= T delta sum(w) / (w(0) - delta sum(w)).
+ * Writes the fewest pairs Q whose bound is <= tol (gray levels) and the bound
+ * itself (0 when nothing is dropped).  Pairs whose float coefficient is zero
+ * are never counted. */
+bf_status bf_range_truncate(int32_t N, double T, const bf_spatial_spec* spatial_spec,
+                            double tol, int32_t* npairs_out, double* bound_out);
 
 /* Radii of n_boxes iterated boxes whose combined variance approximates
  * sigma_s^2 (a Gaussian spatial filter of Algorithm 1 step 4): ideal width
@@ -165,6 +180,7 @@ typedef struct {
     bf_spatial_spec spatial;
     int32_t tile_h, tile_w;      /* forward tile; 0 = library choice */
     int32_t bwd_tile_h, bwd_tile_w; /* adjoint tile; 0 = library choice */
+    float trunc_tol;             /* as bf_opts.trunc_tol; 0 = every pair */
 } bf_image_desc;
 
 typedef struct bf_batch_plan bf_batch_plan;

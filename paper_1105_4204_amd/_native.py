@@ -21,7 +21,7 @@ STATUS = {0: "BF_OK", 1: "BF_EINVAL", 2: "BF_ERANGE", 3: "BF_ENOMEM", 4: "BF_EDE
           5: "BF_ECAPTURE", 6: "BF_EUNSUPPORTED"}
 
 # exported symbols, in the order include/bf_trig.h declares them
-EXPORTS = ["bf_range_degree", "bf_range_coeffs", "bf_spatial_gaussian",
+EXPORTS = ["bf_range_degree", "bf_range_coeffs", "bf_range_truncate", "bf_spatial_gaussian",
            "bf_trig_workspace_bytes", "bf_trig_forward",
            "bf_trig_forward_ex", "bf_trig_backward", "bf_direct_forward",
            "bf_batch_plan_create", "bf_batch_bind", "bf_batch_launch", "bf_batch_check",
@@ -56,14 +56,16 @@ class Opts(ctypes.Structure):
     _fields_ = [("stream", ctypes.c_void_p), ("N", ctypes.c_int32),
                 ("eta_out", ctypes.c_void_p), ("tile_h", ctypes.c_int32),
                 ("tile_w", ctypes.c_int32), ("aux_out", ctypes.c_void_p),
-                ("workspace", ctypes.c_void_p), ("workspace_bytes", ctypes.c_int64)]
+                ("workspace", ctypes.c_void_p), ("workspace_bytes", ctypes.c_int64),
+                ("trunc_tol", ctypes.c_float)]
 
 
 class ImageDesc(ctypes.Structure):
     _fields_ = [("H", ctypes.c_int64), ("W", ctypes.c_int64), ("T", ctypes.c_float),
                 ("sigma_r", ctypes.c_float), ("N", ctypes.c_int32), ("spatial", SpatialSpec),
                 ("tile_h", ctypes.c_int32), ("tile_w", ctypes.c_int32),
-                ("bwd_tile_h", ctypes.c_int32), ("bwd_tile_w", ctypes.c_int32)]
+                ("bwd_tile_h", ctypes.c_int32), ("bwd_tile_w", ctypes.c_int32),
+                ("trunc_tol", ctypes.c_float)]
 
 
 _lib = None
@@ -84,6 +86,7 @@ def lib():
     sig = {
         "bf_range_degree": [f64, f64, ctypes.POINTER(i32)],
         "bf_range_coeffs": [i32, ctypes.POINTER(f32), i32, ctypes.POINTER(i32)],
+        "bf_range_truncate": [i32, f64, sp, f64, ctypes.POINTER(i32), ctypes.POINTER(f64)],
         "bf_spatial_gaussian": [f64, i32, sp],
         "bf_trig_workspace_bytes": [i64, i64, sp, ctypes.POINTER(i64)],
         "bf_trig_forward": [vp, i64, i64, f32, f32, sp, vp],
@@ -137,7 +140,7 @@ def spatial_gaussian(sigma_s: float, n_boxes: int = 3):
 
 
 def make_opts(stream=None, N=0, eta_out=None, tile=None, aux_out=None, workspace=None,
-              workspace_bytes=0) -> Opts:
+              workspace_bytes=0, trunc_tol=0.0) -> Opts:
     o = Opts()
     o.stream = stream
     o.N = int(N)
@@ -146,7 +149,18 @@ def make_opts(stream=None, N=0, eta_out=None, tile=None, aux_out=None, workspace
     o.aux_out = aux_out
     o.workspace = workspace
     o.workspace_bytes = int(workspace_bytes)
+    o.trunc_tol = float(trunc_tol)
     return o
+
+
+def range_truncate(N: int, T: float, radii, tol: float):
+    """(pairs kept, error bound in gray levels) for term truncation at tol."""
+    n = ctypes.c_int32()
+    b = ctypes.c_double()
+    spec = SpatialSpec.of(radii)
+    check(lib().bf_range_truncate(int(N), float(T), ctypes.byref(spec), float(tol),
+                                  ctypes.byref(n), ctypes.byref(b)), "bf_range_truncate")
+    return int(n.value), float(b.value)
 
 
 def workspace_bytes(H: int, W: int, radii) -> int:

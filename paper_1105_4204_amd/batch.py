@@ -28,6 +28,7 @@ def _spec_desc(s) -> nat.ImageDesc:
     th, tw = s.get("tile") or (0, 0)
     bh, bw = s.get("bwd_tile") or (0, 0)
     d.tile_h, d.tile_w, d.bwd_tile_h, d.bwd_tile_w = int(th), int(tw), int(bh), int(bw)
+    d.trunc_tol = float(s.get("trunc_tol", 0.0))
     return d
 
 

@@ -21,6 +21,10 @@ bf_status prepare(const float* f, int64_t H, int64_t W, float T, float sigma_r,
     if (st != BF_OK) return st;
     st = make_range((double)T, (double)sigma_r, opts ? opts->N : 0, &c->rp);
     if (st != BF_OK) return st;
+    if (opts && opts->trunc_tol != 0.0f) {
+        st = truncate_pairs(&c->rp, c->sp, (double)T, (double)opts->trunc_tol, nullptr);
+        if (st != BF_OK) return st;
+    }
     c->stream = opts ? (hipStream_t)opts->stream : nullptr;
     return BF_OK;
 }

@@ -178,6 +178,9 @@ bf_status bf_batch_plan_create(const bf_image_desc* descs, int32_t n, bf_batch_p
             st = BF_EINVAL;
         } else if ((st = make_spatial(&d.spatial, &p->sp[i])) == BF_OK &&
                    (st = make_range((double)d.T, (double)d.sigma_r, d.N, &p->rp[i])) == BF_OK &&
+                   (d.trunc_tol == 0.0f ||
+                    (st = truncate_pairs(&p->rp[i], p->sp[i], (double)d.T, (double)d.trunc_tol,
+                                         nullptr)) == BF_OK) &&
                    (st = plan_tiles(kForward, d.H, d.W, p->sp[i], d.tile_h, d.tile_w,
                                     &p->gf[i])) == BF_OK) {
             st = plan_tiles(kBackward, d.H, d.W, p->sp[i], d.bwd_tile_h, d.bwd_tile_w, &p->gb[i]);

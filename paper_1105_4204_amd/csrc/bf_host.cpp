@@ -85,6 +85,70 @@ bf_status make_range(double T, double sigma_r, int32_t N_req, RangeParams* rp) {
     return BF_OK;
 }
 
+// Composite 1-D kernel of the boxes (integer weights): its centre value k0 and
+// its mass.  w(0) = k0^2 and sum w = mass^2 for the separable 2-D kernel.
+static void kernel_centre_and_mass(const SpatialParams& sp, double* k0, double* mass) {
+    const int L = 2 * sp.R + 1;
+    double k[2 * BF_MAX_BOXES * BF_MAX_RADIUS + 1] = {0.0};
+    double t[2 * BF_MAX_BOXES * BF_MAX_RADIUS + 1];
+    k[sp.R] = 1.0;
+    for (int b = 0; b < sp.nb; ++b) {
+        for (int i = 0; i < L; ++i) {
+            double acc = 0.0;
+            for (int d = -sp.r[b]; d <= sp.r[b]; ++d)
+                if (i - d >= 0 && i - d < L) acc += k[i - d];
+            t[i] = acc;
+        }
+        for (int i = 0; i < L; ++i) k[i] = t[i];
+    }
+    double m = 1.0;
+    for (int b = 0; b < sp.nb; ++b) m *= (double)(2 * sp.r[b] + 1);
+    *k0 = k[sp.R];
+    *mass = m;
+}
+
+// Term truncation with an error bound.  Dropping the pairs q >= Q removes the
+// binomial mass delta = sum_{q >= Q} c_q, and |phi - phi_Q| <= delta on the
+// whole range.  With num and den the centred sums (|g| <= T/2, so |num/den|
+// <= T/2) and den >= w(0) (the centre pixel always counts with phi(0) = 1,
+// and phi >= 0 when N meets the degree bound):
+//     |out_Q - out| <= T delta sum(w) / (w(0) - delta sum(w)).
+// Keeps the fewest pairs whose bound is <= tol (tol in the units of f).
+bf_status truncate_pairs(RangeParams* rp, const SpatialParams& sp, double T, double tol,
+                         double* bound_out) {
+    if (!(tol > 0.0) || !isfinite(tol)) {
+        set_error("truncation tolerance must be positive and finite (%g)", tol);
+        return BF_EINVAL;
+    }
+    double k0 = 0.0, mass = 0.0;
+    kernel_centre_and_mass(sp, &k0, &mass);
+    const double w0 = k0 * k0, sw = mass * mass;
+    // exact tail masses in long double, from the same log-binomials as the
+    // coefficients
+    const int32_t N = rp->N, np = N / 2 + 1;
+    long double tail[kMaxPairs + 1];
+    tail[np] = 0.0L;
+    const long double lN = lgammal((long double)N + 1.0L) - (long double)N * logl(2.0L);
+    for (int32_t q = np - 1; q >= 0; --q) {
+        const int32_t m = (N & 1) + 2 * q;
+        const int32_t n = (N - m) / 2;
+        long double v = expl(lN - lgammal((long double)n + 1.0L) -
+                             lgammal((long double)(N - n) + 1.0L));
+        if (m > 0) v *= 2.0L;
+        tail[q] = tail[q + 1] + v;
+    }
+    auto bound = [&](int32_t Q) {
+        const double d = (double)tail[Q];
+        const double den = w0 - d * sw;
+        return den > 0.0 ? T * d * sw / den : INFINITY;
+    };
+    int32_t Q = 1;
+    while (Q < rp->npairs && !(bound(Q) <= tol)) ++Q;
+    if (Q < rp->npairs) rp->npairs = Q;
+    if (bound_out) *bound_out = Q < np ? bound(Q) : 0.0;
+    return BF_OK;
+}
+
 bf_status make_spatial(const bf_spatial_spec* spec, SpatialParams* sp) {
     if (!spec) {
         set_error("spatial_spec is NULL");
@@ -144,6 +208,32 @@ bool overlaps(const void* a, int64_t abytes, const void* b, int64_t bbytes) {
 using namespace bf;
 
 extern "C" {
+
+bf_status bf_range_truncate(int32_t N, double T, const bf_spatial_spec* spatial_spec,
+                            double tol, int32_t* npairs_out, double* bound_out) {
+    if (!npairs_out) {
+        set_error("npairs_out is NULL");
+        return BF_EINVAL;
+    }
+    if (N < 1 || N > BF_MAX_DEGREE || !(T > 0.0)) {
+        set_error("need 1 <= N <= %d and T > 0 (N=%d, T=%g)", BF_MAX_DEGREE, N, T);
+        return BF_ERANGE;
+    }
+    SpatialParams sp;
+    bf_status st = make_spatial(spatial_spec, &sp);
+    if (st != BF_OK) return st;
+    RangeParams rp;
+    rp.N = N;
+    rp.odd = N & 1;
+    int32_t np = 0;
+    pair_coeffs(N, rp.chat, &np);
+    while (np > 1 && rp.chat[np - 1] == 0.0f) --np;
+    rp.npairs = np;
+    st = truncate_pairs(&rp, sp, T, tol, bound_out);
+    if (st != BF_OK) return st;
+    *npairs_out = rp.npairs;
+    return BF_OK;
+}
 
 bf_status bf_range_degree(double T, double sigma_r, int32_t* N_out) {
     if (!N_out) {

@@ -33,6 +33,8 @@ struct SpatialParams {
 void set_error(const char* fmt, ...);
 bf_status make_range(double T, double sigma_r, int32_t N_req, RangeParams* rp);
 bf_status make_spatial(const bf_spatial_spec* spec, SpatialParams* sp);
+bf_status truncate_pairs(RangeParams* rp, const SpatialParams& sp, double T, double tol,
+                         double* bound_out);
 bf_status check_image(const void* p, int64_t H, int64_t W, const char* name);
 bool overlaps(const void* a, const void* b, int64_t bytes);   // two ranges of `bytes` each
 bool overlaps(const void* a, int64_t abytes, const void* b, int64_t bbytes);

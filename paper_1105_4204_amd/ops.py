@@ -31,7 +31,7 @@ def _ptr(x):
 
 def trig_forward(f: torch.Tensor, T: float, sigma_r: float, radii, N: int = 0,
                  return_eta: bool = False, tile=None, out: torch.Tensor | None = None,
-                 return_aux: bool = False):
+                 return_aux: bool = False, trunc_tol: float = 0.0):
     """O(1) raised-cosine bilateral filter of a 2-D image (fused HIP kernel).
 
     Returns out, or (out, eta) with return_eta, or (out, eta, aux) with
@@ -44,7 +44,7 @@ def trig_forward(f: torch.Tensor, T: float, sigma_r: float, radii, N: int = 0,
     spec = nat.SpatialSpec.of(radii)
     nws = nat.workspace_bytes(H, W, radii)     # > 0: staged path for wide spatial kernels
     ws = torch.empty(nws, device=f.device, dtype=torch.uint8) if nws else None
-    opts = nat.make_opts(_stream_ptr(), N, _ptr(eta), tile, _ptr(aux), _ptr(ws), nws)
+    opts = nat.make_opts(_stream_ptr(), N, _ptr(eta), tile, _ptr(aux), _ptr(ws), nws, trunc_tol)
     nat.check(nat.lib().bf_trig_forward_ex(_ptr(f), H, W, float(T), float(sigma_r),
                                            ctypes.byref(spec), _ptr(out), ctypes.byref(opts)),
               "bf_trig_forward_ex")
@@ -69,7 +69,7 @@ def direct_forward(f: torch.Tensor, T: float, sigma_r: float, radii, N: int = 0,
 
 
 def trig_backward(f, out, eta, aux, grad_out, T: float, sigma_r: float, radii, N: int = 0,
-                  tile=None):
+                  tile=None, trunc_tol: float = 0.0):
     """grad_f = J^T grad_out for the forward that produced (out, eta, aux)."""
     for x, n in ((f, "f"), (out, "out"), (eta, "eta"), (grad_out, "grad_out")):
         _check_img(x, n)
@@ -79,7 +79,7 @@ def trig_backward(f, out, eta, aux, grad_out, T: float, sigma_r: float, radii, N
         raise TypeError("aux must be the contiguous 2 x H x W float32 tensor of the forward")
     gf = torch.empty_like(f)
     spec = nat.SpatialSpec.of(radii)
-    opts = nat.make_opts(_stream_ptr(), N, None, tile)
+    opts = nat.make_opts(_stream_ptr(), N, None, tile, trunc_tol=trunc_tol)
     nat.check(nat.lib().bf_trig_backward(_ptr(f), _ptr(out), _ptr(eta), _ptr(aux),
                                          _ptr(grad_out), H, W, float(T), float(sigma_r),
                                          ctypes.byref(spec), _ptr(gf), ctypes.byref(opts)),
@@ -92,24 +92,29 @@ class BFTrig(torch.autograd.Function):
     hand-written adjoint kernel.  T, sigma_r, radii and N are constants."""
 
     @staticmethod
-    def forward(ctx, f, T, sigma_r, radii, N):
+    def forward(ctx, f, T, sigma_r, radii, N, trunc_tol):
         f = f.contiguous()
         if ctx.needs_input_grad[0]:
-            out, eta, aux = trig_forward(f, T, sigma_r, radii, N, return_aux=True)
+            out, eta, aux = trig_forward(f, T, sigma_r, radii, N, return_aux=True,
+                                         trunc_tol=trunc_tol)
             ctx.save_for_backward(f, out, eta, aux)
         else:
-            out = trig_forward(f, T, sigma_r, radii, N)
-        ctx.params = (T, sigma_r, tuple(radii), N)
+            out = trig_forward(f, T, sigma_r, radii, N, trunc_tol=trunc_tol)
+        ctx.params = (T, sigma_r, tuple(radii), N, trunc_tol)
         return out
 
     @staticmethod
     def backward(ctx, grad_out):
         f, out, eta, aux = ctx.saved_tensors
-        T, sigma_r, radii, N = ctx.params
-        gf = trig_backward(f, out, eta, aux, grad_out.contiguous(), T, sigma_r, radii, N)
-        return gf, None, None, None, None
+        T, sigma_r, radii, N, trunc_tol = ctx.params
+        gf = trig_backward(f, out, eta, aux, grad_out.contiguous(), T, sigma_r, radii, N,
+                           trunc_tol=trunc_tol)
+        return gf, None, None, None, None, None
 
 
-def bf_trig(f: torch.Tensor, T: float = 255.0, sigma_r: float = 30.0, radii=(5,), N: int = 0):
-    """Differentiable O(1) bilateral filter of a 2-D float32 image."""
-    return BFTrig.apply(f, float(T), float(sigma_r), tuple(int(r) for r in radii), int(N))
+def bf_trig(f: torch.Tensor, T: float = 255.0, sigma_r: float = 30.0, radii=(5,), N: int = 0,
+            trunc_tol: float = 0.0):
+    """Differentiable O(1) bilateral filter of a 2-D float32 image (trunc_tol > 0:
+    drop outer cosine pairs within that many gray levels, bf_range_truncate)."""
+    return BFTrig.apply(f, float(T), float(sigma_r), tuple(int(r) for r in radii), int(N),
+                        float(trunc_tol))

@@ -183,3 +183,73 @@ def test_workspace_query_and_staged_validation():
     o3 = nat.make_opts(None, 0, None, None, None, ctypes.c_void_p(0x40000000), 24 * 64 - 4)
     assert L.bf_trig_forward_ex(FAKE, 8, 8, 255.0, 10.0, ctypes.byref(s), FAKE2,
                                 ctypes.byref(o3)) == 1         # workspace too small
+
+
+def _tail_bound(N, T, radii, Q):
+    """Independent evaluation of the truncation bound T d S / (w0 - d S) with
+    exact binomials (fractions) and the explicitly convolved box kernel."""
+    from fractions import Fraction
+    np_ = N // 2 + 1
+    c = []
+    for q in range(np_):
+        m = (N % 2) + 2 * q
+        v = Fraction(math.comb(N, (N - m) // 2), 2 ** N)
+        c.append(v if m == 0 else 2 * v)
+    d = float(sum(c[Q:]))
+    k = np.array([1.0])
+    for r in radii:
+        k = np.convolve(k, np.ones(2 * r + 1))
+    w0 = k[len(k) // 2] ** 2
+    S = k.sum() ** 2
+    return T * d * S / (w0 - d * S) if w0 > d * S else math.inf
+
+
+@pytest.mark.parametrize("N,radii,tol", [(66, [9, 9, 10], 1e-3), (264, [29, 29, 30], 1e-2),
+                                         (43, [5, 5, 6], 0.1), (30, [5], 1e-2)])
+def test_truncation_count_matches_independent_bound(N, radii, tol):
+    Q, bound = nat.range_truncate(N, 255.0, radii, tol)
+    assert _tail_bound(N, 255.0, radii, Q) <= tol
+    assert bound == pytest.approx(_tail_bound(N, 255.0, radii, Q), rel=1e-6)
+    assert Q == 1 or _tail_bound(N, 255.0, radii, Q - 1) > tol      # fewest pairs
+    assert Q <= len(nat.range_coeffs(N))
+
+
+def test_truncation_bound_holds_against_the_oracle():
+    """The truncated kernel phi_Q = sum_{q<Q} c_q cos(m_q a s), applied by a
+    plain FP64 window sum, stays within the bound of the exact filter (the
+    oracle), and a looser tolerance keeps fewer pairs."""
+    import oracle
+    from paper_1105_4204_amd import synth
+    H, W, sr, radii = 20, 18, 20.0, [2, 2, 3]
+    N = oracle.range_degree(255.0, sr)
+    f = synth.salt(H, W, seed=3).astype(np.float64)
+    ref = oracle.forward(f, sr, N, radii)
+    k = np.array([1.0])
+    for r in radii:
+        k = np.convolve(k, np.ones(2 * r + 1))
+    R = len(k) // 2
+    a = 1.0 / (sr * math.sqrt(N))
+    prev = None
+    for tol in (0.3, 3.0):
+        Q, bound = nat.range_truncate(N, 255.0, radii, tol)
+        ms = [(N % 2) + 2 * q for q in range(Q)]
+        cs = [(math.comb(N, (N - m) // 2) * (1 if m == 0 else 2)) / 2.0 ** N for m in ms]
+        out = np.empty_like(f)
+        for i in range(H):
+            for j in range(W):
+                num = den = 0.0
+                for di in range(-R, R + 1):
+                    for dj in range(-R, R + 1):
+                        y, x = i + di, j + dj
+                        if 0 <= y < H and 0 <= x < W:
+                            s = f[y, x] - f[i, j]
+                            ph = sum(c * math.cos(m * a * s) for c, m in zip(cs, ms))
+                            w = k[di + R] * k[dj + R] * ph
+                            num += w * f[y, x]
+                            den += w
+                out[i, j] = num / den
+        err = np.abs(out - ref).max()
+        assert err <= bound + 1e-9, (tol, Q, err, bound)
+        if prev is not None:
+            assert Q < prev
+        prev = Q
