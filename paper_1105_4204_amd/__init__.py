@@ -13,7 +13,8 @@ without the native library or a GPU.
 import importlib
 
 __all__ = ["bf_trig", "trig_forward", "trig_backward", "direct_forward", "BFTrig",
-           "range_degree", "range_coeffs", "spatial_gaussian", "BatchPlan", "synth"]
+           "range_degree", "range_coeffs", "range_truncate", "spatial_gaussian", "BatchPlan",
+           "trig_forward_channels", "synth"]
 
 _LAZY = {
     "bf_trig": ("ops", "bf_trig"),
@@ -25,6 +26,8 @@ _LAZY = {
     "range_coeffs": ("_native", "range_coeffs"),
     "spatial_gaussian": ("_native", "spatial_gaussian"),
     "BatchPlan": ("batch", "BatchPlan"),
+    "trig_forward_channels": ("batch", "trig_forward_channels"),
+    "range_truncate": ("_native", "range_truncate"),
 }
 
 

@@ -120,3 +120,24 @@ def capture(plan: BatchPlan, warmup: int = 1) -> torch.cuda.CUDAGraph:
     with torch.cuda.graph(g):
         plan.launch()
     return g
+
+
+def trig_forward_channels(img: torch.Tensor, T: float, sigma_r: float, radii, N: int = 0,
+                          trunc_tol: float = 0.0) -> torch.Tensor:
+    """Channel-wise filter of a C x H x W image (e.g. RGB, each channel filtered
+    on its own as in the paper's colour experiments), run as the C items of one
+    batched persistent launch.  Returns a C x H x W tensor; synchronises the
+    current stream before it returns (the plan is released)."""
+    if img.dim() != 3 or not img.is_cuda or img.dtype != torch.float32:
+        raise TypeError("img must be a C x H x W float32 CUDA tensor")
+    img = img.contiguous()
+    C, H, W = img.shape
+    spec = dict(H=H, W=W, T=float(T), sigma_r=float(sigma_r), N=int(N),
+                radii=[int(r) for r in radii], trunc_tol=float(trunc_tol))
+    plan = BatchPlan([spec] * C)
+    out = torch.empty_like(img)
+    plan.bind([img[c] for c in range(C)], out=[out[c] for c in range(C)])
+    plan.launch()
+    torch.cuda.current_stream().synchronize()   # the plan's tables outlive the launch
+    plan.close()
+    return out

@@ -92,6 +92,20 @@ def salt(H: int, W: int, seed: int, frac: float = 0.02) -> np.ndarray:
     return np.clip(img, 0.0, T_GRAY).astype(np.float32)
 
 
+def colour(H: int, W: int, seed: int, noise: float = 12.0) -> np.ndarray:
+    """3 x H x W synthetic colour image: one piecewise-smooth structure (shared
+    shapes) with per-channel intensities and independent noise, clipped to
+    [0, 255]."""
+    base = piecewise_smooth(H, W, seed=seed, noise=0.0)
+    rng = _rng(seed + 1)
+    chans = []
+    for c in range(3):
+        gain, off = rng.uniform(0.5, 1.0), rng.uniform(0.0, 80.0)
+        ch = gain * base.astype(np.float64) + off + rng.normal(0.0, noise, size=(H, W))
+        chans.append(np.clip(ch, 0.0, T_GRAY))
+    return np.stack(chans).astype(np.float32)
+
+
 # --- the five workloads ------------------------------------------------------
 
 def config_image(cfg: int) -> np.ndarray:
