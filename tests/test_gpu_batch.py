@@ -164,3 +164,40 @@ def test_colour_channels_as_batch_items():
         ref = oracle.forward_at(img[c], 25.0, N, [3, 3, 4], idx)
         got = out[c].cpu().numpy().reshape(-1)[idx].astype(np.float64)
         assert np.all(np.abs(got - ref) <= 1e-2 + 1e-4 * np.abs(ref)), c
+
+
+def test_autotuner_picks_valid_tiles_for_a_batch(tmp_path):
+    """The tuner times candidate tiles on a probe image, caches the fastest per
+    (device, mode, radii, N bucket) in a JSON file, and a batch plan built with
+    it runs within tolerance of the oracle; a second tuner instance reads the
+    cache instead of re-timing."""
+    batch, ops = _mods()
+    from paper_1105_4204_amd import autotune
+    cache = str(tmp_path / "tune.json")
+    tuner = autotune.Tuner(cache_path=cache, reps=2, probe_hw=192)
+    specs = [dict(H=140, W=100, sigma_s=4.0, sigma_r=30.0),
+             dict(H=90, W=170, sigma_s=6.0, sigma_r=20.0)]
+    for s in specs:
+        for mode in ("fwd", "bwd"):
+            tile = tuner.tune(s, mode)
+            assert tile[0] >= 1 and tile[1] >= 1, (s, mode, tile)
+    again = autotune.Tuner(cache_path=cache)
+    for s in specs:
+        assert again.tile_for(s, "fwd") == tuner.tile_for(s, "fwd")
+    fs = [_cuda(synth.piecewise_smooth(s["H"], s["W"], seed=70 + i, n_shapes=3))
+          for i, s in enumerate(specs)]
+    ts = [_cuda(synth.piecewise_smooth(s["H"], s["W"], seed=80 + i, n_shapes=3))
+          for i, s in enumerate(specs)]
+    plan = batch.BatchPlan(specs, tuner=again)
+    out, eta, gf, loss = plan.allocate()
+    plan.bind(fs, ts, out, eta, gf, loss)
+    plan.launch()
+    plan.check()
+    torch.cuda.synchronize()
+    from paper_1105_4204_amd import _native as nat
+    for i, s in enumerate(specs):
+        radii = nat.spatial_gaussian(s["sigma_s"], 3)
+        N = oracle.range_degree(255.0, s["sigma_r"])
+        ref = oracle.forward(fs[i].cpu().numpy(), s["sigma_r"], N, radii)
+        err = np.abs(out[i].cpu().numpy().astype(np.float64) - ref)
+        assert np.all(err <= 1e-2 + 1e-4 * np.abs(ref)), (i, err.max())
