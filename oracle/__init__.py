@@ -53,6 +53,9 @@ def _load():
     lib.oracle_grad_at.argtypes = [_dp, ctypes.c_int64, ctypes.c_int64, ctypes.c_double,
                                    ctypes.c_int64, _i32p, ctypes.c_int32, _dp, _i64p,
                                    ctypes.c_int64, _dp]
+    lib.oracle_forward_sv.restype = ctypes.c_int
+    lib.oracle_forward_sv.argtypes = [_dp, ctypes.c_int64, ctypes.c_int64, ctypes.c_double,
+                                      ctypes.c_int64, _i32p, _dp, _dp]
     _lib = lib
     return lib
 
@@ -202,3 +205,23 @@ def ssd_loss_fd(f, target, sigma_r: float, N: int, radii, idx, h: float = 1e-3):
         flat[p] = v0
         res[t] = (lp - lm) / (2.0 * h)
     return res
+
+
+def forward_sv(f, sigma_r: float, N: int, rmap, return_eta: bool = False):
+    """Space-variant filter (Sec. 4): unit box of half-width rmap[i, j] around
+    each pixel, fixed raised-cosine range kernel; direct FP64 window sums."""
+    f = _f64(f)
+    if f.ndim != 2:
+        raise ValueError("f must be 2-D")
+    H, W = f.shape
+    rm = np.ascontiguousarray(rmap, dtype=np.int32)
+    if rm.shape != f.shape:
+        raise ValueError("rmap must match f")
+    out = np.empty_like(f)
+    eta = np.empty_like(f) if return_eta else None
+    rc = _load().oracle_forward_sv(f.ctypes.data_as(_dp), H, W, float(sigma_r), int(N),
+                                   rm.ctypes.data_as(_i32p), out.ctypes.data_as(_dp),
+                                   eta.ctypes.data_as(_dp) if eta is not None else None)
+    if rc != 0:
+        raise ValueError("oracle_forward_sv: bad arguments")
+    return (out, eta) if return_eta else out

@@ -253,3 +253,41 @@ int oracle_grad_at(const double* f, int64_t H, int64_t W, double sigma_r, int64_
     free(k);
     return 0;
 }
+
+/* Space-variant extension (Sec. 4, "Space-variant extension"): the spatial
+ * kernel changes from pixel to pixel while the range kernel stays fixed.
+ * Here the kernel at pixel x is the unit box of half-width rmap[x] in both
+ * directions, so
+ *     out(x) = sum_{|y - x|_inf <= r(x)} phi(f(y) - f(x)) f(y) / eta(x),
+ *     eta(x) = sum_{same y} phi(f(y) - f(x)),
+ * with y restricted to the image (the zero extension of the auxiliary images
+ * leaves only in-image pixels in both sums).  Written out directly, one
+ * window per pixel; rmap is H*W with entries >= 0.  Returns 0, or -1. */
+int oracle_forward_sv(const double* f, int64_t H, int64_t W, double sigma_r, int64_t N,
+                      const int32_t* rmap, double* out, double* eta_out)
+{
+    if (!f || !rmap || !out || H <= 0 || W <= 0 || N < 0) return -1;
+    if (N > 0 && !(sigma_r > 0.0)) return -1;
+    for (int64_t p = 0; p < H * W; ++p) if (rmap[p] < 0) return -1;
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t i = 0; i < H; ++i) {
+        for (int64_t j = 0; j < W; ++j) {
+            int64_t r = rmap[i * W + j];
+            double fx = f[i * W + j];
+            int64_t i0 = i - r < 0 ? 0 : i - r, i1 = i + r > H - 1 ? H - 1 : i + r;
+            int64_t j0 = j - r < 0 ? 0 : j - r, j1 = j + r > W - 1 ? W - 1 : j + r;
+            double num = 0.0, eta = 0.0;
+            for (int64_t y = i0; y <= i1; ++y) {
+                for (int64_t x = j0; x <= j1; ++x) {
+                    double fy = f[y * W + x];
+                    double ph = oracle_phi(fy - fx, N, sigma_r);
+                    num += ph * fy;
+                    eta += ph;
+                }
+            }
+            out[i * W + j] = num / eta;
+            if (eta_out) eta_out[i * W + j] = eta;
+        }
+    }
+    return 0;
+}
