@@ -149,6 +149,20 @@ bf_status bf_trig_backward(const float* f, const float* out, const float* eta,
                            float T, float sigma_r, const bf_spatial_spec* spatial_spec,
                            float* grad_f, const bf_opts* opts);
 
+/* Space-variant spatial kernel (Sec. 4, space-variant extension): the unit
+ * box around pixel (i, j) has half-width radius[i*W + j], clamped to
+ * [0, rmax], in both directions; the range kernel is the fixed raised
+ * cosine.  out(x) = sum_{|y-x|_inf <= r(x)} phi(f(y)-f(x)) f(y) / eta(x) over
+ * in-image y, eta(x) the same sum without f(y), evaluated through eq.
+ * (final-form) with box sums read from summed-area tables, so the cost per
+ * pixel does not depend on the radii.  radius: device int32 H*W (caller-owned,
+ * not modified).  0 <= rmax <= 31 (BF_EUNSUPPORTED above).  opts: stream, N,
+ * eta_out and trunc_tol as for the forward (the truncation bound is taken for
+ * the rmax box); tiles, aux_out and workspace are ignored.  out must not
+ * overlap f, radius or eta_out.  Asynchronous on opts->stream. */
+bf_status bf_sv_forward(const float* f, const int32_t* radius, int64_t H, int64_t W, float T,
+                        float sigma_r, int32_t rmax, float* out, const bf_opts* opts);
+
 /* Direct-window filter: the same eq. (BF)/(normalization) summed pixel by
  * pixel over the whole window, O((2R+1)^2) per pixel (the baseline the paper
  * compares its O(1) method with).  Same arguments as the forward. */

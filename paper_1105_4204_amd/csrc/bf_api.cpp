@@ -132,6 +132,33 @@ bf_status bf_direct_forward(const float* f, int64_t H, int64_t W, float T, float
     return launch_direct(f, out, eta, H, W, c.rp, c.sp, c.stream);
 }
 
+bf_status bf_sv_forward(const float* f, const int32_t* radius, int64_t H, int64_t W, float T,
+                        float sigma_r, int32_t rmax, float* out, const bf_opts* opts) {
+    if (rmax < 0) {
+        set_error("rmax=%d must be >= 0", rmax);
+        return BF_EINVAL;
+    }
+    // the truncation bound (if asked for) is taken for the widest box
+    bf_spatial_spec box = {};
+    box.n_boxes = 1;
+    box.radius[0] = rmax;
+    Common c;
+    bf_status st = prepare(f, H, W, T, sigma_r, &box, opts, &c);
+    if (st != BF_OK) return st;
+    st = check_image(out, H, W, "out");
+    if (st != BF_OK) return st;
+    st = check_image(radius, H, W, "radius");
+    if (st != BF_OK) return st;
+    const int64_t bytes = H * W * (int64_t)sizeof(float);
+    float* eta = opts ? opts->eta_out : nullptr;
+    if (overlaps(f, out, bytes) || overlaps(f, eta, bytes) || overlaps(out, eta, bytes) ||
+        overlaps(radius, out, bytes) || overlaps(radius, eta, bytes)) {
+        set_error("out / eta_out must not overlap f, radius or each other");
+        return BF_EINVAL;
+    }
+    return launch_sv(f, radius, out, eta, H, W, rmax, c.rp, c.stream);
+}
+
 bf_status bf_trig_backward(const float* f, const float* out, const float* eta,
                            const float* aux, const float* grad_out, int64_t H, int64_t W,
                            float T, float sigma_r, const bf_spatial_spec* spatial_spec,

@@ -66,6 +66,9 @@ size_t staged_workspace_bytes(int64_t H, int64_t W);
 bf_status launch_staged(const float* f, float* out, float* eta, int64_t H, int64_t W,
                         const RangeParams& rp, const SpatialParams& sp, void* workspace,
                         hipStream_t stream);
+// Space-variant box kernel through tile-local summed-area tables (bf_sv.hip).
+bf_status launch_sv(const float* f, const int32_t* rmap, float* out, float* eta, int64_t H,
+                    int64_t W, int32_t rmax, const RangeParams& rp, hipStream_t stream);
 bf_status launch_bwd(const float* f, const float* out, const float* eta, const float* aux,
                      const float* gout, float* gf, int64_t H, int64_t W, const RangeParams& rp,
                      const SpatialParams& sp, const TileGeom& g, hipStream_t stream);

@@ -68,6 +68,29 @@ def direct_forward(f: torch.Tensor, T: float, sigma_r: float, radii, N: int = 0,
     return (out, eta) if return_eta else out
 
 
+def sv_forward(f: torch.Tensor, radius: torch.Tensor, T: float, sigma_r: float,
+               rmax: int | None = None, N: int = 0, trunc_tol: float = 0.0,
+               return_eta: bool = False):
+    """Space-variant filter: unit box of half-width radius[i, j] (int32, clamped
+    to [0, rmax]) around each pixel, fixed raised-cosine range kernel.  rmax
+    defaults to radius.max() (one device-to-host read)."""
+    _check_img(f, "f")
+    H, W = f.shape
+    if (not isinstance(radius, torch.Tensor) or not radius.is_cuda
+            or radius.dtype != torch.int32 or tuple(radius.shape) != (H, W)
+            or not radius.is_contiguous()):
+        raise TypeError("radius must be a contiguous H x W int32 CUDA tensor")
+    if rmax is None:
+        rmax = int(radius.max().item())
+    out = torch.empty_like(f)
+    eta = torch.empty_like(f) if return_eta else None
+    opts = nat.make_opts(_stream_ptr(), N, _ptr(eta), trunc_tol=trunc_tol)
+    nat.check(nat.lib().bf_sv_forward(_ptr(f), _ptr(radius), H, W, float(T), float(sigma_r),
+                                      int(rmax), _ptr(out), ctypes.byref(opts)),
+              "bf_sv_forward")
+    return (out, eta) if return_eta else out
+
+
 def trig_backward(f, out, eta, aux, grad_out, T: float, sigma_r: float, radii, N: int = 0,
                   tile=None, trunc_tol: float = 0.0):
     """grad_f = J^T grad_out for the forward that produced (out, eta, aux)."""

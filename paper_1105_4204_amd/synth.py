@@ -106,6 +106,26 @@ def colour(H: int, W: int, seed: int, noise: float = 12.0) -> np.ndarray:
     return np.stack(chans).astype(np.float32)
 
 
+def radius_map(H: int, W: int, seed: int, rmax: int, frac_random: float = 0.1) -> np.ndarray:
+    """H x W int32 half-widths in [0, rmax] for the space-variant kernel: a
+    smooth field (sum of a few wide Gaussian bumps, rescaled to [0, rmax]) with
+    a fraction of pixels set to independent uniform radii, so that neighbouring
+    pixels also differ sharply."""
+    rng = _rng(seed)
+    yy, xx = np.mgrid[0:H, 0:W].astype(np.float64)
+    field = np.zeros((H, W))
+    for _ in range(4):
+        cy, cx = rng.uniform(0, H), rng.uniform(0, W)
+        s = rng.uniform(0.2, 0.6) * max(H, W)
+        field += rng.uniform(0.5, 1.5) * np.exp(-((yy - cy) ** 2 + (xx - cx) ** 2) / (2 * s * s))
+    lo, hi = field.min(), field.max()
+    field = (field - lo) / (hi - lo) if hi > lo else np.zeros_like(field)
+    r = np.rint(field * rmax).astype(np.int32)
+    m = rng.uniform(size=(H, W)) < frac_random
+    r[m] = rng.integers(0, rmax + 1, size=int(m.sum()))
+    return r
+
+
 # --- the five workloads ------------------------------------------------------
 
 def config_image(cfg: int) -> np.ndarray:

@@ -253,3 +253,21 @@ def test_truncation_bound_holds_against_the_oracle():
         if prev is not None:
             assert Q < prev
         prev = Q
+
+
+def test_sv_forward_validates_before_any_launch():
+    """Argument errors of the space-variant entry point are reported on the
+    host (no device is touched, so this runs without a GPU)."""
+    import ctypes
+    L = nat.lib()
+    f, r, o = ctypes.c_void_p(0x100000), ctypes.c_void_p(0x900000), ctypes.c_void_p(0x1100000)
+    opts = nat.make_opts(None, 0, None)
+    call = lambda f_, r_, H, W, rmax, o_: L.bf_sv_forward(f_, r_, H, W, 255.0, 20.0, rmax, o_,
+                                                          ctypes.byref(opts))
+    assert call(None, r, 64, 64, 4, o) == 1          # NULL f
+    assert call(f, None, 64, 64, 4, o) == 1          # NULL radius
+    assert call(f, r, 64, 64, -1, o) == 1            # negative bound
+    assert call(f, r, 0, 64, 4, o) == 1              # empty image
+    assert call(f, r, 64, 64, 32, o) == 6            # beyond the kernel's 31
+    assert call(f, r, 64, 64, 4, f) == 1             # out overlaps f
+    assert call(f, r, 64, 64, 4, ctypes.c_void_p(0x900000 + 64)) == 1   # out overlaps radius
