@@ -56,6 +56,16 @@ def _load():
     lib.oracle_forward_sv.restype = ctypes.c_int
     lib.oracle_forward_sv.argtypes = [_dp, ctypes.c_int64, ctypes.c_int64, ctypes.c_double,
                                       ctypes.c_int64, _i32p, _dp, _dp]
+    lib.oracle_yvv_coeffs.restype = ctypes.c_int
+    lib.oracle_yvv_coeffs.argtypes = [ctypes.c_double, _dp]
+    lib.oracle_yvv_line.restype = ctypes.c_int
+    lib.oracle_yvv_line.argtypes = [_dp, ctypes.c_int64, ctypes.c_double, _dp]
+    lib.oracle_yvv_kernel.restype = ctypes.c_int
+    lib.oracle_yvv_kernel.argtypes = [ctypes.c_double, ctypes.c_int64, _dp]
+    lib.oracle_forward_kernel.restype = ctypes.c_int
+    lib.oracle_forward_kernel.argtypes = [_dp, ctypes.c_int64, ctypes.c_int64, ctypes.c_double,
+                                          ctypes.c_int64, _dp, ctypes.c_int64, _i64p,
+                                          ctypes.c_int64, _dp, _dp]
     _lib = lib
     return lib
 
@@ -224,4 +234,58 @@ def forward_sv(f, sigma_r: float, N: int, rmap, return_eta: bool = False):
                                    eta.ctypes.data_as(_dp) if eta is not None else None)
     if rc != 0:
         raise ValueError("oracle_forward_sv: bad arguments")
+    return (out, eta) if return_eta else out
+
+
+def yvv_coeffs(sigma_s: float):
+    """(B, b1/b0, b2/b0, b3/b0) of the recursive Gaussian of Young and van
+    Vliet (1995) for standard deviation sigma_s >= 0.5."""
+    c = np.empty(4, dtype=np.float64)
+    if _load().oracle_yvv_coeffs(float(sigma_s), c.ctypes.data_as(_dp)) != 0:
+        raise ValueError("sigma_s must be >= 0.5")
+    return tuple(float(x) for x in c)
+
+
+def yvv_line(u, sigma_s: float) -> np.ndarray:
+    """Causal then anticausal pass over a finite line, zero state at both ends."""
+    u = _f64(u).reshape(-1)
+    out = np.empty_like(u)
+    if _load().oracle_yvv_line(u.ctypes.data_as(_dp), u.size, float(sigma_s),
+                               out.ctypes.data_as(_dp)) != 0:
+        raise ValueError("bad arguments")
+    return out
+
+
+def yvv_kernel(sigma_s: float, D: int) -> np.ndarray:
+    """Impulse response of the two passes on an infinite line, taps -D..D."""
+    k = np.empty(2 * int(D) + 1, dtype=np.float64)
+    if _load().oracle_yvv_kernel(float(sigma_s), int(D), k.ctypes.data_as(_dp)) != 0:
+        raise ValueError("bad arguments")
+    return k
+
+
+def forward_kernel(f, sigma_r: float, N: int, k, idx=None, return_eta: bool = False):
+    """Direct FP64 filter with the separable spatial kernel k (x) k, k of odd
+    length 2D+1 centred on tap D; at flat indices idx, or every pixel."""
+    f = _f64(f)
+    H, W = f.shape
+    k = _f64(k).reshape(-1)
+    if k.size % 2 != 1:
+        raise ValueError("kernel length must be odd")
+    D = (k.size - 1) // 2
+    if idx is None:
+        n, ip = H * W, None
+    else:
+        idx = np.ascontiguousarray(idx, dtype=np.int64).reshape(-1)
+        n, ip = idx.size, idx.ctypes.data_as(_i64p)
+    out = np.empty(n, dtype=np.float64)
+    eta = np.empty(n, dtype=np.float64) if return_eta else None
+    rc = _load().oracle_forward_kernel(f.ctypes.data_as(_dp), H, W, float(sigma_r), int(N),
+                                       k.ctypes.data_as(_dp), D, ip, n, out.ctypes.data_as(_dp),
+                                       eta.ctypes.data_as(_dp) if eta is not None else None)
+    if rc != 0:
+        raise ValueError("oracle_forward_kernel: bad arguments")
+    if idx is None:
+        out = out.reshape(H, W)
+        eta = eta.reshape(H, W) if eta is not None else None
     return (out, eta) if return_eta else out

@@ -291,3 +291,101 @@ int oracle_forward_sv(const double* f, int64_t H, int64_t W, double sigma_r, int
     }
     return 0;
 }
+
+/* ---- Recursive Gaussian spatial kernel (Sec. 3: the paper's own code averages
+ * in space with the recursive O(1) Gaussian of its image-processing reference,
+ * i.e. the filter of Young and van Vliet, Signal Processing 44(2), 1995).
+ *
+ * Published recipe, for a target standard deviation s >= 0.5:
+ *   q  = 0.98711 s - 0.96330                      (s >= 2.5)
+ *   q  = 3.97156 - 4.14554 sqrt(1 - 0.26891 s)     (0.5 <= s < 2.5)
+ *   b0 = 1.57825 + 2.44413 q + 1.4281 q^2 + 0.422205 q^3
+ *   b1 = 2.44413 q + 2.85619 q^2 + 1.26661 q^3
+ *   b2 = -(1.4281 q^2 + 1.26661 q^3)
+ *   b3 = 0.422205 q^3
+ *   B  = 1 - (b1 + b2 + b3) / b0
+ * causal pass      w[n] = B u[n] + (b1 w[n-1] + b2 w[n-2] + b3 w[n-3]) / b0,
+ * anticausal pass  v[n] = B w[n] + (b1 v[n+1] + b2 v[n+2] + b3 v[n+3]) / b0.
+ * On an infinite line of zero-extended data the two passes are a linear,
+ * shift-invariant, symmetric filter; the spatial kernel of the bilateral
+ * filter is its impulse response in x times the same in y. */
+
+/* Writes B, b1/b0, b2/b0, b3/b0.  Returns 0, or -1 for s < 0.5. */
+int oracle_yvv_coeffs(double s, double* c_out)
+{
+    if (!(s >= 0.5) || !c_out) return -1;
+    double q = (s >= 2.5) ? 0.98711 * s - 0.96330 : 3.97156 - 4.14554 * sqrt(1.0 - 0.26891 * s);
+    double b0 = 1.57825 + 2.44413 * q + 1.4281 * q * q + 0.422205 * q * q * q;
+    double b1 = 2.44413 * q + 2.85619 * q * q + 1.26661 * q * q * q;
+    double b2 = -(1.4281 * q * q + 1.26661 * q * q * q);
+    double b3 = 0.422205 * q * q * q;
+    c_out[0] = 1.0 - (b1 + b2 + b3) / b0;
+    c_out[1] = b1 / b0;
+    c_out[2] = b2 / b0;
+    c_out[3] = b3 / b0;
+    return 0;
+}
+
+/* The two passes over a finite line u[0..n) with zero state before the
+ * first sample (causal) and after the last (anticausal).  out may equal u. */
+int oracle_yvv_line(const double* u, int64_t n, double s, double* out)
+{
+    double c[4];
+    if (!u || !out || n <= 0 || oracle_yvv_coeffs(s, c)) return -1;
+    double* w = (double*)malloc((size_t)n * sizeof(double));
+    double w1 = 0.0, w2 = 0.0, w3 = 0.0;
+    for (int64_t i = 0; i < n; ++i) {
+        double x = c[0] * u[i] + c[1] * w1 + c[2] * w2 + c[3] * w3;
+        w[i] = x;
+        w3 = w2; w2 = w1; w1 = x;
+    }
+    double v1 = 0.0, v2 = 0.0, v3 = 0.0;
+    for (int64_t i = n - 1; i >= 0; --i) {
+        double x = c[0] * w[i] + c[1] * v1 + c[2] * v2 + c[3] * v3;
+        out[i] = x;
+        v3 = v2; v2 = v1; v1 = x;
+    }
+    free(w);
+    return 0;
+}
+
+/* Impulse response k[d + D], |d| <= D, of the two passes on an infinite
+ * line: the impulse sits in the middle of a zero line long enough (pad on
+ * both sides) that the response has decayed below double precision at its
+ * ends.  Returns 0, or -1. */
+int oracle_yvv_kernel(double s, int64_t D, double* k_out)
+{
+    double c[4];
+    if (D < 0 || !k_out || oracle_yvv_coeffs(s, c)) return -1;
+    int64_t pad = (int64_t)(60.0 * s) + 200;
+    int64_t n = 2 * (D + pad) + 1;
+    double* line = (double*)calloc((size_t)n, sizeof(double));
+    line[D + pad] = 1.0;
+    oracle_yvv_line(line, n, s, line);
+    memcpy(k_out, line + pad, (size_t)(2 * D + 1) * sizeof(double));
+    free(line);
+    return 0;
+}
+
+/* Bilateral filter with an explicit separable spatial kernel
+ * w(dy, dx) = k[dy + D] k[dx + D], |dy|, |dx| <= D: the same direct window
+ * sums as oracle_forward, at the flat pixel indices idx[0..n) (all pixels when
+ * idx is NULL, n = H W). */
+int oracle_forward_kernel(const double* f, int64_t H, int64_t W, double sigma_r, int64_t N,
+                          const double* k, int64_t D, const int64_t* idx, int64_t n,
+                          double* out, double* eta_out)
+{
+    if (!f || !k || !out || H <= 0 || W <= 0 || N < 0 || D < 0) return -1;
+    if (N > 0 && !(sigma_r > 0.0)) return -1;
+    if (!idx && n != H * W) return -1;
+    for (int64_t t = 0; idx && t < n; ++t) if (idx[t] < 0 || idx[t] >= H * W) return -1;
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t t = 0; t < n; ++t) {
+        int64_t p = idx ? idx[t] : t;
+        double num, eta;
+        pixel_sums(f, H, W, p / W, p % W, k, D, N, sigma_r, &num, &eta);
+        out[t] = num / eta;
+        if (eta_out) eta_out[t] = eta;
+    }
+    return 0;
+}
