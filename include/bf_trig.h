@@ -163,6 +163,25 @@ bf_status bf_trig_backward(const float* f, const float* out, const float* eta,
 bf_status bf_sv_forward(const float* f, const int32_t* radius, int64_t H, int64_t W, float T,
                         float sigma_r, int32_t rmax, float* out, const bf_opts* opts);
 
+/* Recursive Gaussian spatial kernel: the filter of Young and van Vliet
+ * (Signal Processing 44(2), 1995), which the paper's experiments use for the
+ * spatial averaging (Sec. 3), in place of the iterated boxes.  Each axis is
+ * filtered by a third-order causal pass and an anticausal pass with the
+ * published coefficients for standard deviation sigma_s in [0.5, 64]
+ * (BF_ERANGE outside), over whole image lines with zero extension at both
+ * ends, so the spatial kernel is the exact two-sided impulse response of the
+ * passes (infinite support).  Evaluated through eq. (final-form) like the
+ * forward; the filtered channels of up to 32 cosine pairs at a time pass
+ * through opts->workspace (required; at least bf_yvv_workspace_bytes bytes,
+ * device memory, not overlapping the images).  opts: stream, N, eta_out and
+ * trunc_tol (the bound of bf_range_truncate with this kernel's centre tap and
+ * mass); tiles and aux_out are ignored.  out must not overlap f or eta_out.
+ * Asynchronous on opts->stream; no adjoint. */
+bf_status bf_yvv_workspace_bytes(int64_t H, int64_t W, float T, float sigma_r, int32_t N,
+                                 int64_t* bytes_out);
+bf_status bf_yvv_forward(const float* f, int64_t H, int64_t W, float T, float sigma_r,
+                         float sigma_s, float* out, const bf_opts* opts);
+
 /* Direct-window filter: the same eq. (BF)/(normalization) summed pixel by
  * pixel over the whole window, O((2R+1)^2) per pixel (the baseline the paper
  * compares its O(1) method with).  Same arguments as the forward. */

@@ -12,7 +12,8 @@ without the native library or a GPU.
 """
 import importlib
 
-__all__ = ["bf_trig", "trig_forward", "trig_backward", "sv_forward", "direct_forward", "BFTrig",
+__all__ = ["bf_trig", "trig_forward", "trig_backward", "sv_forward", "yvv_forward",
+           "direct_forward", "BFTrig",
            "range_degree", "range_coeffs", "range_truncate", "spatial_gaussian", "BatchPlan",
            "trig_forward_channels", "synth"]
 
@@ -22,6 +23,7 @@ _LAZY = {
     "trig_backward": ("ops", "trig_backward"),
     "direct_forward": ("ops", "direct_forward"),
     "sv_forward": ("ops", "sv_forward"),
+    "yvv_forward": ("ops", "yvv_forward"),
     "BFTrig": ("ops", "BFTrig"),
     "range_degree": ("_native", "range_degree"),
     "range_coeffs": ("_native", "range_coeffs"),

@@ -23,7 +23,8 @@ STATUS = {0: "BF_OK", 1: "BF_EINVAL", 2: "BF_ERANGE", 3: "BF_ENOMEM", 4: "BF_EDE
 # exported symbols, in the order include/bf_trig.h declares them
 EXPORTS = ["bf_range_degree", "bf_range_coeffs", "bf_range_truncate", "bf_spatial_gaussian",
            "bf_trig_workspace_bytes", "bf_trig_forward",
-           "bf_trig_forward_ex", "bf_trig_backward", "bf_sv_forward", "bf_direct_forward",
+           "bf_trig_forward_ex", "bf_trig_backward", "bf_sv_forward",
+           "bf_yvv_workspace_bytes", "bf_yvv_forward", "bf_direct_forward",
            "bf_batch_plan_create", "bf_batch_bind", "bf_batch_launch", "bf_batch_check",
            "bf_batch_plan_destroy", "bf_status_string", "bf_last_error"]
 
@@ -93,6 +94,8 @@ def lib():
         "bf_trig_forward_ex": [vp, i64, i64, f32, f32, sp, vp, op],
         "bf_trig_backward": [vp, vp, vp, vp, vp, i64, i64, f32, f32, sp, vp, op],
         "bf_sv_forward": [vp, vp, i64, i64, f32, f32, i32, vp, op],
+        "bf_yvv_workspace_bytes": [i64, i64, f32, f32, i32, ctypes.POINTER(i64)],
+        "bf_yvv_forward": [vp, i64, i64, f32, f32, f32, vp, op],
         "bf_direct_forward": [vp, i64, i64, f32, f32, sp, vp, op],
         "bf_batch_plan_create": [ctypes.POINTER(ImageDesc), i32, ctypes.POINTER(vp)],
         "bf_batch_bind": [vp, ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(vp),
@@ -171,3 +174,10 @@ def workspace_bytes(H: int, W: int, radii) -> int:
     check(lib().bf_trig_workspace_bytes(int(H), int(W), ctypes.byref(spec), ctypes.byref(n)),
           "bf_trig_workspace_bytes")
     return int(n.value)
+
+
+def yvv_workspace_bytes(H: int, W: int, T: float, sigma_r: float, N: int = 0) -> int:
+    b = ctypes.c_int64()
+    check(lib().bf_yvv_workspace_bytes(int(H), int(W), float(T), float(sigma_r), int(N),
+                                       ctypes.byref(b)), "bf_yvv_workspace_bytes")
+    return int(b.value)

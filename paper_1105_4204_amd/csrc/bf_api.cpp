@@ -159,6 +159,58 @@ bf_status bf_sv_forward(const float* f, const int32_t* radius, int64_t H, int64_
     return launch_sv(f, radius, out, eta, H, W, rmax, c.rp, c.stream);
 }
 
+bf_status bf_yvv_workspace_bytes(int64_t H, int64_t W, float T, float sigma_r, int32_t N,
+                                 int64_t* bytes_out) {
+    if (!bytes_out) {
+        set_error("bytes_out is NULL");
+        return BF_EINVAL;
+    }
+    *bytes_out = 0;
+    if (H <= 0 || W <= 0) {
+        set_error("image size %lld x %lld must be positive", (long long)H, (long long)W);
+        return BF_EINVAL;
+    }
+    RangeParams rp;
+    bf_status st = make_range((double)T, (double)sigma_r, N, &rp);
+    if (st != BF_OK) return st;
+    *bytes_out = (int64_t)yvv_workspace_bytes(H, W, rp.npairs);
+    return BF_OK;
+}
+
+bf_status bf_yvv_forward(const float* f, int64_t H, int64_t W, float T, float sigma_r,
+                         float sigma_s, float* out, const bf_opts* opts) {
+    bf_status st = check_image(f, H, W, "f");
+    if (st != BF_OK) return st;
+    st = check_image(out, H, W, "out");
+    if (st != BF_OK) return st;
+    YvvParams yp;
+    st = make_yvv((double)sigma_s, &yp);
+    if (st != BF_OK) return st;
+    RangeParams rp;
+    st = make_range((double)T, (double)sigma_r, opts ? opts->N : 0, &rp);
+    if (st != BF_OK) return st;
+    if (opts && opts->trunc_tol != 0.0f) {
+        st = truncate_pairs_km(&rp, yp.k0, 1.0, (double)T, (double)opts->trunc_tol, nullptr);
+        if (st != BF_OK) return st;
+    }
+    const int64_t bytes = H * W * (int64_t)sizeof(float);
+    float* eta = opts ? opts->eta_out : nullptr;
+    void* ws = opts ? opts->workspace : nullptr;
+    const int64_t wsb = opts ? opts->workspace_bytes : 0;
+    if (!ws) {
+        set_error("the recursive-Gaussian forward needs opts->workspace (bf_yvv_workspace_bytes)");
+        return BF_EINVAL;
+    }
+    if (overlaps(f, out, bytes) || overlaps(f, eta, bytes) || overlaps(out, eta, bytes) ||
+        overlaps(ws, wsb, f, bytes) || overlaps(ws, wsb, out, bytes) ||
+        overlaps(ws, wsb, eta, bytes)) {
+        set_error("out / eta_out / workspace must not overlap f or each other");
+        return BF_EINVAL;
+    }
+    return launch_yvv(f, out, eta, H, W, rp, yp, ws, (size_t)(wsb > 0 ? wsb : 0),
+                      opts ? (hipStream_t)opts->stream : nullptr);
+}
+
 bf_status bf_trig_backward(const float* f, const float* out, const float* eta,
                            const float* aux, const float* grad_out, int64_t H, int64_t W,
                            float T, float sigma_r, const bf_spatial_spec* spatial_spec,

@@ -116,12 +116,18 @@ static void kernel_centre_and_mass(const SpatialParams& sp, double* k0, double* 
 // Keeps the fewest pairs whose bound is <= tol (tol in the units of f).
 bf_status truncate_pairs(RangeParams* rp, const SpatialParams& sp, double T, double tol,
                          double* bound_out) {
+    double k0 = 0.0, mass = 0.0;
+    kernel_centre_and_mass(sp, &k0, &mass);
+    return truncate_pairs_km(rp, k0, mass, T, tol, bound_out);
+}
+
+// The same for any separable kernel given by its 1-D centre tap k0 and mass.
+bf_status truncate_pairs_km(RangeParams* rp, double k0, double mass, double T, double tol,
+                            double* bound_out) {
     if (!(tol > 0.0) || !isfinite(tol)) {
         set_error("truncation tolerance must be positive and finite (%g)", tol);
         return BF_EINVAL;
     }
-    double k0 = 0.0, mass = 0.0;
-    kernel_centre_and_mass(sp, &k0, &mass);
     const double w0 = k0 * k0, sw = mass * mass;
     // exact tail masses in long double, from the same log-binomials as the
     // coefficients
@@ -201,6 +207,92 @@ bool overlaps(const void* a, int64_t abytes, const void* b, int64_t bbytes) {
     const char* pa = (const char*)a;
     const char* pb = (const char*)b;
     return pa < pb + bbytes && pb < pa + abytes;
+}
+
+// Recursive Gaussian of Young and van Vliet (Signal Processing 44(2), 1995),
+// the spatial filter of the paper's own experiments (Sec. 3).  From the
+// requested standard deviation s: q by their fit, then the third-order
+// denominator b0..b3 and the gain B that makes the DC response one; each
+// line is filtered by
+//   causal      w[n] = B u[n] + a1 w[n-1] + a2 w[n-2] + a3 w[n-3]
+//   anticausal  v[n] = B w[n] + a1 v[n+1] + a2 v[n+2] + a3 v[n+3]
+// with a_i = b_i / b0.  Zero-extended data before the first sample leave the
+// causal pass with zero state.  Past the last sample the data are zero too,
+// but the causal output is not: it rings on as w[n] = sum a_i w[n-i], and the
+// anticausal pass must start from where that ringing leaves it.  M maps the
+// causal state at the end of a line, (w[n-1], w[n-2], w[n-3]), to the
+// anticausal start (v[n], v[n+1], v[n+2]); it is found here in FP64 by running
+// the ringing of each unit state until it has died out and filtering it back.
+bf_status make_yvv(double s, YvvParams* yp) {
+    if (!(s >= kYvvMinSigma) || !(s <= kYvvMaxSigma)) {
+        set_error("sigma_s=%g outside [%g, %g]", s, kYvvMinSigma, kYvvMaxSigma);
+        return BF_ERANGE;
+    }
+    const double q = (s >= 2.5) ? 0.98711 * s - 0.96330 : 3.97156 - 4.14554 * sqrt(1.0 - 0.26891 * s);
+    const double b0 = 1.57825 + 2.44413 * q + 1.4281 * q * q + 0.422205 * q * q * q;
+    const double b1 = 2.44413 * q + 2.85619 * q * q + 1.26661 * q * q * q;
+    const double b2 = -(1.4281 * q * q + 1.26661 * q * q * q);
+    const double b3 = 0.422205 * q * q * q;
+    const double a[3] = {b1 / b0, b2 / b0, b3 / b0};
+    const double B = 1.0 - (b1 + b2 + b3) / b0;
+    const int K = 200 * (int)ceil(q) + 2000;   // the ringing decays by e per ~q samples at worst
+    double* w = (double*)malloc((size_t)K * sizeof(double));
+    if (!w) {
+        set_error("host allocation failed");
+        return BF_ENOMEM;
+    }
+    for (int k = 0; k < 3; ++k) {
+        double w1 = k == 0, w2 = k == 1, w3 = k == 2;   // w[n-1], w[n-2], w[n-3]
+        for (int i = 0; i < K; ++i) {
+            const double x = a[0] * w1 + a[1] * w2 + a[2] * w3;
+            w[i] = x;
+            w3 = w2;
+            w2 = w1;
+            w1 = x;
+        }
+        double v1 = 0.0, v2 = 0.0, v3 = 0.0;
+        for (int i = K - 1; i >= 0; --i) {
+            const double x = B * w[i] + a[0] * v1 + a[1] * v2 + a[2] * v3;
+            v3 = v2;
+            v2 = v1;
+            v1 = x;
+            if (i <= 2) yp->M[3 * i + k] = x;   // row i: v[n+i]
+        }
+    }
+    // centre tap of the two-pass impulse response (its mass is one)
+    {
+        const int L = K / 2;
+        double* line = (double*)calloc((size_t)(2 * L + 1), sizeof(double));
+        if (!line) {
+            free(w);
+            set_error("host allocation failed");
+            return BF_ENOMEM;
+        }
+        line[L] = 1.0;
+        double w1 = 0.0, w2 = 0.0, w3 = 0.0;
+        for (int i = 0; i <= 2 * L; ++i) {
+            const double x = B * line[i] + a[0] * w1 + a[1] * w2 + a[2] * w3;
+            line[i] = x;
+            w3 = w2;
+            w2 = w1;
+            w1 = x;
+        }
+        double v1 = 0.0, v2 = 0.0, v3 = 0.0;
+        for (int i = 2 * L; i >= L; --i) {
+            const double x = B * line[i] + a[0] * v1 + a[1] * v2 + a[2] * v3;
+            v3 = v2;
+            v2 = v1;
+            v1 = x;
+        }
+        yp->k0 = v1;
+        free(line);
+    }
+    free(w);
+    yp->B = B;
+    yp->a1 = a[0];
+    yp->a2 = a[1];
+    yp->a3 = a[2];
+    return BF_OK;
 }
 
 }  // namespace bf

@@ -29,13 +29,27 @@ struct SpatialParams {
     int32_t R;        // sum of radii: half-width of the composite kernel
 };
 
+// Recursive Gaussian spatial filter (Young and van Vliet): line-pass
+// coefficients and the map from the causal end state to the anticausal
+// start state (row-major 3 x 3).
+constexpr double kYvvMinSigma = 0.5;
+constexpr double kYvvMaxSigma = 64.0;
+struct YvvParams {
+    double B, a1, a2, a3;
+    double M[9];
+    double k0;       // centre tap of the two-pass impulse response (mass 1)
+};
+
 // Host helpers (bf_host.cpp).
 void set_error(const char* fmt, ...);
 bf_status make_range(double T, double sigma_r, int32_t N_req, RangeParams* rp);
 bf_status make_spatial(const bf_spatial_spec* spec, SpatialParams* sp);
 bf_status truncate_pairs(RangeParams* rp, const SpatialParams& sp, double T, double tol,
                          double* bound_out);
+bf_status truncate_pairs_km(RangeParams* rp, double k0, double mass, double T, double tol,
+                            double* bound_out);
 bf_status check_image(const void* p, int64_t H, int64_t W, const char* name);
+bf_status make_yvv(double sigma_s, YvvParams* yp);
 bool overlaps(const void* a, const void* b, int64_t bytes);   // two ranges of `bytes` each
 bool overlaps(const void* a, int64_t abytes, const void* b, int64_t bbytes);
 
@@ -69,6 +83,11 @@ bf_status launch_staged(const float* f, float* out, float* eta, int64_t H, int64
 // Space-variant box kernel through tile-local summed-area tables (bf_sv.hip).
 bf_status launch_sv(const float* f, const int32_t* rmap, float* out, float* eta, int64_t H,
                     int64_t W, int32_t rmax, const RangeParams& rp, hipStream_t stream);
+// Recursive Gaussian forward over whole image lines (bf_yvv.hip).
+size_t yvv_workspace_bytes(int64_t H, int64_t W, int npairs);
+bf_status launch_yvv(const float* f, float* out, float* eta, int64_t H, int64_t W,
+                     const RangeParams& rp, const YvvParams& yp, void* workspace,
+                     size_t workspace_bytes, hipStream_t stream);
 bf_status launch_bwd(const float* f, const float* out, const float* eta, const float* aux,
                      const float* gout, float* gf, int64_t H, int64_t W, const RangeParams& rp,
                      const SpatialParams& sp, const TileGeom& g, hipStream_t stream);

@@ -52,19 +52,6 @@ struct StageArgs {
     float center;       // T/2
 };
 
-// exp(j m a g) for any phase: quadrant from the FP64 phase, remainder
-// |x| <= pi/4 through cis_small.
-__device__ __forceinline__ void cis_direct(double malpha, float g, float& c, float& s) {
-    const double th = malpha * (double)g;
-    const double n = rint(th * 0.63661977236758134308);        // 2/pi
-    const float x = (float)fma(-n, 1.57079632679489661923, th);  // pi/2
-    float cx, sx;
-    cis_small(x, cx, sx);
-    const int q = ((int)(long long)n) & 3;
-    c = q == 0 ? cx : q == 1 ? -sx : q == 2 ? -cx : sx;
-    s = q == 0 ? sx : q == 1 ? cx : q == 2 ? -sx : -cx;
-}
-
 // Vertical pass.  Workgroup: 64 columns x one segment of nout_v output rows;
 // the 256 extended rows of g are staged in LDS once, then wave w builds
 // channel w (C, gC, S, gS; 1, g for m = 0) down its 64 columns, filters it

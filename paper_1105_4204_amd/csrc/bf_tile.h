@@ -105,6 +105,20 @@ __device__ __forceinline__ void cis_small(float x, float& c, float& s) {
     s = fmaf(ps * x2, x, x);
 }
 
+// exp(j m a g) for any phase: quadrant from the FP64 phase, remainder
+// |x| <= pi/4 through cis_small.  Used where a pass starts the phase of a
+// pair from scratch instead of carrying it from the previous pair.
+__device__ __forceinline__ void cis_direct(double malpha, float g, float& c, float& s) {
+    const double th = malpha * (double)g;
+    const double n = rint(th * 0.63661977236758134308);        // 2/pi
+    const float x = (float)fma(-n, 1.57079632679489661923, th);  // pi/2
+    float cx, sx;
+    cis_small(x, cx, sx);
+    const int q = ((int)(long long)n) & 3;
+    c = q == 0 ? cx : q == 1 ? -sx : q == 2 ? -cx : sx;
+    s = q == 0 ? sx : q == 1 ? cx : q == 2 ? -sx : -cx;
+}
+
 // v[0..kLine) <- src[0..kLine) with 16-byte LDS loads (src 16-byte aligned).
 __device__ __forceinline__ void load_line(float (&v)[kLine], const float* src) {
     const float4* s4 = reinterpret_cast<const float4*>(src);

@@ -91,6 +91,28 @@ def sv_forward(f: torch.Tensor, radius: torch.Tensor, T: float, sigma_r: float,
     return (out, eta) if return_eta else out
 
 
+def yvv_forward(f: torch.Tensor, T: float, sigma_r: float, sigma_s: float, N: int = 0,
+                trunc_tol: float = 0.0, return_eta: bool = False,
+                workspace: torch.Tensor | None = None):
+    """Forward filter with the recursive Gaussian spatial kernel (Young and
+    van Vliet) of standard deviation sigma_s, over whole image lines.  The
+    workspace (bf_yvv_workspace_bytes) is allocated here unless given."""
+    _check_img(f, "f")
+    H, W = f.shape
+    need = nat.yvv_workspace_bytes(H, W, T, sigma_r, N)
+    if workspace is None:
+        workspace = torch.empty((need + 3) // 4, dtype=torch.float32, device=f.device)
+    out = torch.empty_like(f)
+    eta = torch.empty_like(f) if return_eta else None
+    opts = nat.make_opts(_stream_ptr(), N, _ptr(eta), workspace=_ptr(workspace),
+                         workspace_bytes=workspace.numel() * workspace.element_size(),
+                         trunc_tol=trunc_tol)
+    nat.check(nat.lib().bf_yvv_forward(_ptr(f), H, W, float(T), float(sigma_r), float(sigma_s),
+                                       _ptr(out), ctypes.byref(opts)),
+              "bf_yvv_forward")
+    return (out, eta) if return_eta else out
+
+
 def trig_backward(f, out, eta, aux, grad_out, T: float, sigma_r: float, radii, N: int = 0,
                   tile=None, trunc_tol: float = 0.0):
     """grad_f = J^T grad_out for the forward that produced (out, eta, aux)."""

@@ -271,3 +271,25 @@ def test_sv_forward_validates_before_any_launch():
     assert call(f, r, 64, 64, 32, o) == 6            # beyond the kernel's 31
     assert call(f, r, 64, 64, 4, f) == 1             # out overlaps f
     assert call(f, r, 64, 64, 4, ctypes.c_void_p(0x900000 + 64)) == 1   # out overlaps radius
+
+
+def test_yvv_forward_validates_before_any_launch():
+    """Host-side checks of the recursive-Gaussian entry point (no device)."""
+    import ctypes
+    L = nat.lib()
+    H = W = 64
+    need = nat.yvv_workspace_bytes(H, W, 255.0, 20.0)       # N = 66: 34 pairs, chunks of 32
+    assert need == (8 * 4 * 4 + 8 * 4 + 2) * H * W * 4
+    assert nat.yvv_workspace_bytes(H, W, 255.0, 60.0) == (2 * 16 + 2 * 4 + 2) * H * W * 4
+    f, o = ctypes.c_void_p(0x100000), ctypes.c_void_p(0x900000)
+    ws = ctypes.c_void_p(0x10000000)
+
+    def call(ss, ws_ptr, ws_bytes):
+        opts = nat.make_opts(None, 0, None, workspace=ws_ptr, workspace_bytes=ws_bytes)
+        return L.bf_yvv_forward(f, H, W, 255.0, 20.0, ss, o, ctypes.byref(opts))
+
+    assert call(3.0, None, 0) == 1                 # no workspace
+    assert call(0.4, ws, need) == 2                # sigma_s below 0.5
+    assert call(65.0, ws, need) == 2               # above 64
+    assert call(3.0, ws, need - 4) == 1            # workspace too small
+    assert call(3.0, ctypes.c_void_p(0x100000 + 64), need) == 1   # workspace overlaps f
