@@ -197,6 +197,62 @@ def sigma_s_sweep(f, T, sr, sigmas=(2.0, 4.0, 6.0, 10.0, 16.0, 20.0, 30.0),
     return res
 
 
+def yvv_bytes_per_pixel(npairs: int) -> int:
+    """Algorithmic HBM bytes per pixel of the recursive-Gaussian forward.
+
+    Per pair and channel (4 channels): vertical pass writes the causal output
+    and rewrites it anticausally (read + write), horizontal pass reads it,
+    writes and rereads its causal output (7 x 4 B).  Per group of 4 pairs: f
+    read by both passes (8 B), four partial planes written and reduced (32 B).
+    Per launch chunk of up to 32 pairs: den and num read-modify-written (16 B);
+    then the division reads them and writes out (12 B).
+    """
+    groups = (npairs + 3) // 4
+    chunks = (groups + 7) // 8
+    return npairs * 4 * 28 + groups * 40 + chunks * 16 + 12
+
+
+def other_spatial_kernels(f, T, sr, reps=3):
+    """The two other spatial kernels at fixed sigma_r: the recursive Gaussian
+    (whole-line passes, HBM-bound) across sigma_s, and the space-variant box
+    (summed-area tables) across radius bounds."""
+    import torch
+
+    from paper_1105_4204_amd import _native, ops, synth
+    H, W = f.shape
+    mpix = H * W / 1e6
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    N = _native.range_degree(T, sr)
+    npairs = len(_native.range_coeffs(N))
+    ws = torch.empty(_native.yvv_workspace_bytes(H, W, T, sr) // 4 + 1, device=f.device)
+    yv = []
+    for ss in (2.0, 10.0, 30.0):
+        ms = timed(lambda: ops.yvv_forward(f, T, sr, ss, workspace=ws))
+        byts = yvv_bytes_per_pixel(npairs) * H * W
+        yv.append({"sigma_s": ss, "ms": round(ms, 3), "mpix_s": round(mpix / (ms / 1e3), 1),
+                   "algorithmic_GB": round(byts / 1e9, 2),
+                   "achieved_GBs": round(byts / (ms / 1e3) / 1e9, 1),
+                   "hbm_frac": round(byts / (ms / 1e3) / 1e9 / PEAK_HBM_GBS, 4)})
+    del ws
+    sv = []
+    for rmax in (2, 8, 16, 28):
+        rm = torch.from_numpy(synth.radius_map(H, W, seed=2, rmax=rmax)).to(f.device)
+        ms = timed(lambda: ops.sv_forward(f, rm, T, sr, rmax=rmax))
+        sv.append({"rmax": rmax, "ms": round(ms, 3), "mpix_s": round(mpix / (ms / 1e3), 1)})
+    return {"recursive_gaussian": yv, "space_variant_box": sv}
+
+
 def cpu_baseline(f, sigma_r, N, radii, budget_s=12.0, max_rows=1024):
     import numpy as np
     import oracle
@@ -228,6 +284,8 @@ def main():
     ap.add_argument("--fwd-only", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-sweep", action="store_true", help="skip the sigma_s sweep")
+    ap.add_argument("--no-other", action="store_true",
+                    help="skip the recursive-Gaussian and space-variant timings")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a 512 MiB device copy (counter calibration) and exit")
     args = ap.parse_args()
@@ -380,6 +438,10 @@ def main():
     if not args.no_sweep and args.workload == "config2":
         sweep = sigma_s_sweep(f, T, sr)
 
+    other = None
+    if not args.no_other and args.workload == "config2":
+        other = other_spatial_kernels(f, T, sr)
+
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(f_np, sr, N, radii)
@@ -409,6 +471,7 @@ def main():
         "roofline": roofline,
         "batch": batch_res,
         "sigma_s_sweep": sweep,
+        "other_spatial_kernels": other,
         "cpu_baseline": cpu,
         "wall_s_timed": round(wall, 3),
     }

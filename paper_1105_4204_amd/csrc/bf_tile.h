@@ -167,20 +167,35 @@ struct TileCtx {
 };
 
 // Cooperative fill of an extended-tile plane (pitch gaps and pad zero):
-// value(k) for in-image pixels at flat image index k, 0 elsewhere.
+// value(k) for in-image pixels at flat image index k, 0 elsewhere.  Each
+// thread takes kFillBatch elements per round and evaluates value() at a
+// clamped (always in-image) index without branching, so that the round's
+// global loads are all in flight before the first result is used; the
+// selection against the real position happens afterwards.
+constexpr int kFillBatch = 8;
 template <typename F>
 __device__ __forceinline__ void fill_plane(const TileArgs& a, const TileCtx& c, float* dst,
                                            F value) {
     const int n = tile_plane_floats(c.EH, c.EWp);
     const uint32_t magic = (uint32_t)((0x100000000ull + c.EWp - 1) / c.EWp);
-    for (int p = c.t; p < n; p += kTileThreads) {
-        const int ei = (int)__umulhi((uint32_t)p, magic);
-        const int ej = p - ei * c.EWp;
-        const int gi = c.ei0 + ei, gj = c.ej0 + ej;
-        float x = 0.0f;
-        if (ei < c.EH && ej < c.EW && gi >= 0 && gi < a.H && gj >= 0 && gj < a.W)
-            x = value((size_t)gi * a.W + gj);
-        dst[p] = x;
+    for (int p0 = c.t; p0 < n; p0 += kFillBatch * kTileThreads) {
+        float x[kFillBatch];
+        bool in[kFillBatch];
+#pragma unroll
+        for (int u = 0; u < kFillBatch; ++u) {
+            const int p = p0 + u * kTileThreads;
+            const int ei = (int)__umulhi((uint32_t)p, magic);
+            const int ej = p - ei * c.EWp;
+            const int gi = c.ei0 + ei, gj = c.ej0 + ej;
+            in[u] = p < n && ei < c.EH && ej < c.EW && gi >= 0 && gi < a.H && gj >= 0 && gj < a.W;
+            const int ci = min(max(gi, 0), a.H - 1), cj = min(max(gj, 0), a.W - 1);
+            x[u] = value((size_t)ci * a.W + cj);
+        }
+#pragma unroll
+        for (int u = 0; u < kFillBatch; ++u) {
+            const int p = p0 + u * kTileThreads;
+            if (p < n) dst[p] = in[u] ? x[u] : 0.0f;
+        }
     }
 }
 
