@@ -202,14 +202,14 @@ def yvv_bytes_per_pixel(npairs: int) -> int:
 
     Per pair and channel (4 channels): vertical pass writes the causal output
     and rewrites it anticausally (read + write), horizontal pass reads it,
-    writes and rereads its causal output (7 x 4 B).  Per group of 4 pairs: f
-    read by both passes (8 B), four partial planes written and reduced (32 B).
-    Per launch chunk of up to 32 pairs: den and num read-modify-written (16 B);
-    then the division reads them and writes out (12 B).
+    writes and rereads its causal output (7 x 4 B).  Per group of 2 pairs: f
+    read by both passes (8 B), den and num partial planes written and reduced
+    (16 B).  Per launch chunk of up to 32 pairs: den and num read-modify-written
+    (16 B); then the division reads them and writes out (12 B).
     """
-    groups = (npairs + 3) // 4
-    chunks = (groups + 7) // 8
-    return npairs * 4 * 28 + groups * 40 + chunks * 16 + 12
+    groups = (npairs + 1) // 2
+    chunks = (groups + 15) // 16
+    return npairs * 4 * 28 + groups * 24 + chunks * 16 + 12
 
 
 def other_spatial_kernels(f, T, sr, reps=3):

@@ -22,10 +22,13 @@
 //   horizontal pass (bf_yvv_h): lane = image row; 64 x 32 blocks go through
 //     LDS so that global accesses stay coalesced; causal pass left to right
 //     (in place), then the anticausal pass right to left, demodulated on the
-//     fly: each thread sums c_m (C or S) F[channel] over its group's pairs
-//     into one partial plane per channel;
+//     fly: each thread sums c_m (C or S) F[channel] over its group's pairs,
+//     and the C and S waves' sums (gC and gS for num) are added through LDS
+//     into the group's den and num partial planes;
 //   bf_yvv_reduce adds a chunk's partial planes into den and num in a fixed
 //   order; bf_yvv_final divides in FP64 and writes out and eta.
+// The pairs are split into launch chunks of equal size (at most 32 pairs),
+// so that no chunk is a small tail with few workgroups.
 // Unlike the fused box kernel, the filtered channels of a chunk pass through
 // device memory: this path is bound by HBM traffic, about 120 bytes per pixel
 // and pair.
@@ -36,8 +39,8 @@
 namespace bf {
 
 constexpr int kYvThreads = 256;      // four waves, one per channel
-constexpr int kYvPairs = 4;          // pairs per thread (one direct phase, three recurrence steps)
-constexpr int kYvChunkGroups = 8;    // groups per launch chunk (32 pairs)
+constexpr int kYvPairs = 2;          // pairs per thread (one direct phase, one recurrence step)
+constexpr int kYvChunkGroups = 16;   // groups per launch chunk, at most (32 pairs)
 constexpr int kYvBlk = 32;           // horizontal pass: columns per LDS block
 constexpr int kYvBlkP = kYvBlk + 1;
 constexpr int kYvRows = 8;           // vertical pass: rows whose loads are issued together
@@ -45,7 +48,7 @@ constexpr int kYvRows = 8;           // vertical pass: rows whose loads are issu
 struct YvArgs {
     const float* f;
     float* ws;           // channel planes: plane ((g * kYvPairs + p) * 4 + ch), H*W each
-    float* part;         // partial planes: (g * 4 + ch)
+    float* part;         // partial planes: den and num of group g at (2 g) and (2 g + 1)
     float* den;
     float* num;
     float* out;
@@ -98,12 +101,16 @@ __global__ void __launch_bounds__(kYvThreads) bf_yvv_v(const YvArgs a) {
     // rows in blocks of kYvRows: the block's loads are all issued before its
     // dependent recursion steps
     for (int yb = 0; yb < a.H; yb += kYvRows) {
+        // clamped, unconditional loads: all of a block's loads are in flight
+        // before the first is used (a guarded load would wait on its own)
         float gb[kYvRows];
 #pragma unroll
         for (int j = 0; j < kYvRows; ++j) {
-            const int y = yb + j;
-            gb[j] = (col && y < a.H) ? a.f[(size_t)y * a.W + xc] - a.center : 0.0f;
+            const int y = min(yb + j, a.H - 1);
+            gb[j] = a.f[(size_t)y * a.W + xc];
         }
+#pragma unroll
+        for (int j = 0; j < kYvRows; ++j) gb[j] = (col && yb + j < a.H) ? gb[j] - a.center : 0.0f;
 #pragma unroll
         for (int j = 0; j < kYvRows; ++j) {
             if (yb + j < a.H) {
@@ -134,11 +141,12 @@ __global__ void __launch_bounds__(kYvThreads) bf_yvv_v(const YvArgs a) {
         float wb[kYvRows][kYvPairs];
 #pragma unroll
         for (int j = 0; j < kYvRows; ++j) {
-            const int y = yt - j;
+            const int y = max(yt - j, 0);
 #pragma unroll
-            for (int p = 0; p < kYvPairs; ++p)
-                wb[j][p] = (y >= 0 && p < np) ? planes[(size_t)p * 4 * HW + (size_t)y * a.W + x]
-                                              : 0.0f;
+            for (int p = 0; p < kYvPairs; ++p) {
+                const int pc = min(p, np - 1);
+                wb[j][p] = planes[(size_t)pc * 4 * HW + (size_t)y * a.W + x];
+            }
         }
 #pragma unroll
         for (int j = 0; j < kYvRows; ++j) {
@@ -172,20 +180,29 @@ __global__ void __launch_bounds__(kYvThreads) bf_yvv_h(const YvArgs a) {
     const int y0 = blockIdx.x * 64;
     const size_t HW = (size_t)a.H * a.W;
     float* planes = a.ws + (size_t)grp * kYvPairs * 4 * HW + (size_t)ch * HW;
-    float* part = a.part + ((size_t)grp * 4 + ch) * HW;
+    float* part = a.part + (size_t)grp * 2 * HW;
     const int np = min(kYvPairs, a.npairs - qg);
     float cq[kYvPairs];
 #pragma unroll
     for (int p = 0; p < kYvPairs; ++p) cq[p] = p < np ? a.chat[qg + p] : 0.0f;
     // block transfers: lane l moves column l & 31 of rows 2 r + (l >> 5)
     const int bc = lane & 31, br = lane >> 5;
+    // loads at clamped positions, unconditionally, 16 in flight per lane
     auto load_blk = [&](int x0) {
+        const int x = min(x0 + bc, a.W - 1);
         for (int p = 0; p < np; ++p) {
-#pragma unroll 8
-            for (int r = 0; r < 32; ++r) {
-                const int row = 2 * r + br, y = y0 + row, x = x0 + bc;
-                blk[ch][p][row][bc] =
-                    (y < a.H && x < a.W) ? planes[(size_t)p * 4 * HW + (size_t)y * a.W + x] : 0.0f;
+            for (int r0 = 0; r0 < 32; r0 += 16) {
+                float t[16];
+#pragma unroll
+                for (int r = 0; r < 16; ++r) {
+                    const int y = min(y0 + 2 * (r0 + r) + br, a.H - 1);
+                    t[r] = planes[(size_t)p * 4 * HW + (size_t)y * a.W + x];
+                }
+#pragma unroll
+                for (int r = 0; r < 16; ++r) {
+                    const int row = 2 * (r0 + r) + br;
+                    blk[ch][p][row][bc] = (y0 + row < a.H && x0 + bc < a.W) ? t[r] : 0.0f;
+                }
             }
         }
     };
@@ -237,11 +254,19 @@ __global__ void __launch_bounds__(kYvThreads) bf_yvv_h(const YvArgs a) {
         const int x0 = b * kYvBlk;
         load_blk(x0);
         if (ch == 0) {
-#pragma unroll 8
-            for (int r = 0; r < 32; ++r) {
-                const int row = 2 * r + br, y = y0 + row, x = x0 + bc;
-                gblk[row][bc] =
-                    (y < a.H && x < a.W) ? a.f[(size_t)y * a.W + x] - a.center : 0.0f;
+            const int x = min(x0 + bc, a.W - 1);
+            for (int r0 = 0; r0 < 32; r0 += 16) {
+                float t[16];
+#pragma unroll
+                for (int r = 0; r < 16; ++r) {
+                    const int y = min(y0 + 2 * (r0 + r) + br, a.H - 1);
+                    t[r] = a.f[(size_t)y * a.W + x];
+                }
+#pragma unroll
+                for (int r = 0; r < 16; ++r) {
+                    const int row = 2 * (r0 + r) + br;
+                    gblk[row][bc] = (y0 + row < a.H && x0 + bc < a.W) ? t[r] - a.center : 0.0f;
+                }
             }
         }
         __syncthreads();
@@ -265,7 +290,15 @@ __global__ void __launch_bounds__(kYvThreads) bf_yvv_h(const YvArgs a) {
             blk[ch][0][lane][c] = acc;
         }
         __syncthreads();
-        store_blk(x0, part, 1, 0);
+        // den partial = C + S waves, num partial = gC + gS waves
+        if (ch < 2) {
+            for (int r = 0; r < 32; ++r) {
+                const int row = 2 * r + br, y = y0 + row, x = x0 + bc;
+                if (y < a.H && x < a.W)
+                    part[(size_t)ch * HW + (size_t)y * a.W + x] =
+                        blk[ch][0][row][bc] + blk[ch + 2][0][row][bc];
+            }
+        }
         __syncthreads();
     }
 }
@@ -279,9 +312,9 @@ __global__ void bf_yvv_reduce(const YvArgs a, int ngroups, int first) {
         float d = first ? 0.0f : a.den[i];
         float n = first ? 0.0f : a.num[i];
         for (int g = 0; g < ngroups; ++g) {
-            const float* p = a.part + (size_t)g * 4 * HW + i;
-            d += p[0] + p[2 * HW];
-            n += p[HW] + p[3 * HW];
+            const float* p = a.part + (size_t)g * 2 * HW + i;
+            d += p[0];
+            n += p[HW];
         }
         a.den[i] = d;
         a.num[i] = n;
@@ -298,13 +331,17 @@ __global__ void bf_yvv_final(const YvArgs a) {
     }
 }
 
+// Groups per launch chunk: the pairs split into the fewest chunks of at most
+// kYvChunkGroups groups, all of (nearly) the same size.
 static int yvv_chunk_groups(int npairs) {
-    return std::min(kYvChunkGroups, (npairs + kYvPairs - 1) / kYvPairs);
+    const int groups = (npairs + kYvPairs - 1) / kYvPairs;
+    const int chunks = (groups + kYvChunkGroups - 1) / kYvChunkGroups;
+    return (groups + chunks - 1) / chunks;
 }
 
 size_t yvv_workspace_bytes(int64_t H, int64_t W, int npairs) {
     const int G = yvv_chunk_groups(npairs);
-    const size_t planes = (size_t)G * kYvPairs * 4 + (size_t)G * 4 + 2;
+    const size_t planes = (size_t)G * kYvPairs * 4 + (size_t)G * 2 + 2;
     return planes * (size_t)H * (size_t)W * sizeof(float);
 }
 
@@ -323,7 +360,7 @@ bf_status launch_yvv(const float* f, float* out, float* eta, int64_t H, int64_t 
     a.f = f;
     a.ws = ws;
     a.part = ws + (size_t)G * kYvPairs * 4 * HW;
-    a.den = a.part + (size_t)G * 4 * HW;
+    a.den = a.part + (size_t)G * 2 * HW;
     a.num = a.den + HW;
     a.out = out;
     a.eta = eta;

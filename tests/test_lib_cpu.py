@@ -278,9 +278,12 @@ def test_yvv_forward_validates_before_any_launch():
     import ctypes
     L = nat.lib()
     H = W = 64
-    need = nat.yvv_workspace_bytes(H, W, 255.0, 20.0)       # N = 66: 34 pairs, chunks of 32
-    assert need == (8 * 4 * 4 + 8 * 4 + 2) * H * W * 4
-    assert nat.yvv_workspace_bytes(H, W, 255.0, 60.0) == (2 * 16 + 2 * 4 + 2) * H * W * 4
+    # N = 66: 34 pairs in 17 groups of 2, two chunks of 9 groups; 8 planes per
+    # group's channels, 2 partial planes per group, den and num
+    need = nat.yvv_workspace_bytes(H, W, 255.0, 20.0)
+    assert need == (9 * 8 + 9 * 2 + 2) * H * W * 4
+    # N = 8: 5 pairs, 3 groups, one chunk
+    assert nat.yvv_workspace_bytes(H, W, 255.0, 60.0) == (3 * 8 + 3 * 2 + 2) * H * W * 4
     f, o = ctypes.c_void_p(0x100000), ctypes.c_void_p(0x900000)
     ws = ctypes.c_void_p(0x10000000)
 
