@@ -67,11 +67,25 @@ bf_direct_kernel(const DirArgs a) {
     const int i0 = by * kDirTile, j0 = bx * kDirTile;
     const int S = kDirTile + 2 * a.R;
     if (a.staged) {
-        for (int p = t; p < S * S; p += nt) {
-            const int si = p / S, sj = p - si * S;
-            const int gi = i0 - a.R + si, gj = j0 - a.R + sj;
-            tile[p] = (gi >= 0 && gi < a.H && gj >= 0 && gj < a.W) ? a.f[(size_t)gi * a.W + gj]
-                                                                   : 0.0f;
+        // clamped, unconditional loads in batches of 8, then the selection
+        for (int p0 = t; p0 < S * S; p0 += 8 * nt) {
+            float v8[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int p = p0 + u * nt;
+                const int si = p / S, sj = p - si * S;
+                const int gi = min(max(i0 - a.R + si, 0), a.H - 1);
+                const int gj = min(max(j0 - a.R + sj, 0), a.W - 1);
+                v8[u] = a.f[(size_t)gi * a.W + gj];
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int p = p0 + u * nt;
+                const int si = p / S, sj = p - si * S;
+                const int gi = i0 - a.R + si, gj = j0 - a.R + sj;
+                if (p < S * S)
+                    tile[p] = (gi >= 0 && gi < a.H && gj >= 0 && gj < a.W) ? v8[u] : 0.0f;
+            }
         }
     }
     __syncthreads();

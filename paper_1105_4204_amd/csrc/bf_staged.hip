@@ -69,11 +69,25 @@ bf_stage_v(const StageArgs a) {
     const int y0 = blockIdx.y * a.nout_v;
     const int ey0 = y0 - a.R;
     const size_t HW = (size_t)a.H * a.W;
-    for (int p = t; p < kStLine * kStCols; p += kStThreads) {
-        const int yy = p / kStCols, xx = p - yy * kStCols;
-        const int gy = ey0 + yy, gx = x0 + xx;
-        gtile[p] = (gy >= 0 && gy < a.H && gx < a.W) ? a.f[(size_t)gy * a.W + gx] - a.center
-                                                     : 0.0f;
+    // clamped, unconditional loads in batches of 8 per thread, then the
+    // selection against the real position (a guarded load would wait alone)
+    for (int p0 = t; p0 < kStLine * kStCols; p0 += 8 * kStThreads) {
+        float v8[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int p = p0 + u * kStThreads;
+            const int yy = p / kStCols, xx = p - yy * kStCols;
+            const int gy = min(max(ey0 + yy, 0), a.H - 1), gx = min(x0 + xx, a.W - 1);
+            v8[u] = a.f[(size_t)gy * a.W + gx];
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int p = p0 + u * kStThreads;
+            const int yy = p / kStCols, xx = p - yy * kStCols;
+            const int gy = ey0 + yy, gx = x0 + xx;
+            if (p < kStLine * kStCols)
+                gtile[p] = (gy >= 0 && gy < a.H && gx < a.W) ? v8[u] - a.center : 0.0f;
+        }
     }
     __syncthreads();
     const int nch = a.centre ? 2 : 4;
@@ -136,11 +150,23 @@ bf_stage_h(const StageArgs a) {
     const int ex0 = x0 - a.R;
     const int yc = min(y, a.H - 1);
     const size_t HW = (size_t)a.H * a.W;
-    for (int p = t; p < kStRows * kStOutH; p += kStThreads) {
-        const int yy = p / kStOutH, k = p - yy * kStOutH;
-        const int Y = blockIdx.y * kStRows + yy, X = x0 + k;
-        gt[yy][k] = (Y < a.H && X < a.W && k < a.nout_h) ? a.f[(size_t)Y * a.W + X] - a.center
-                                                         : 0.0f;
+    for (int p0 = t; p0 < kStRows * kStOutH; p0 += 8 * kStThreads) {
+        float v8[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int p = p0 + u * kStThreads;
+            const int yy = p / kStOutH, k = p - yy * kStOutH;
+            const int Y = min(blockIdx.y * kStRows + yy, a.H - 1), X = min(x0 + k, a.W - 1);
+            v8[u] = a.f[(size_t)Y * a.W + X];
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int p = p0 + u * kStThreads;
+            const int yy = p / kStOutH, k = p - yy * kStOutH;
+            const int Y = blockIdx.y * kStRows + yy, X = x0 + k;
+            if (p < kStRows * kStOutH)
+                gt[yy][k] = (Y < a.H && X < a.W && k < a.nout_h) ? v8[u] - a.center : 0.0f;
+        }
     }
     __syncthreads();
     const int nch = a.centre ? 2 : 4;

@@ -76,7 +76,10 @@ __global__ void __launch_bounds__(kSvThreads) bf_sv_kernel(const SvArgs a) {
         const int ei = p / E, ej = p - ei * E;
         const int gi = ei0 + ei, gj = ej0 + ej;
         const bool in = p < EE && gi >= 0 && gi < a.H && gj >= 0 && gj < a.W;
-        const float gv = in ? a.f[(size_t)gi * a.W + gj] - a.center : 0.0f;
+        // clamped, unconditional load: the loads of all k are in flight together
+        const int ci = min(max(gi, 0), a.H - 1), cj = min(max(gj, 0), a.W - 1);
+        const float fv = a.f[(size_t)ci * a.W + cj];
+        const float gv = in ? fv - a.center : 0.0f;
         g[k] = gv;
         float c = 1.0f, s = 0.0f;
         if (a.odd) cis_small(a.alpha_f * gv, c, s);
