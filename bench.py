@@ -130,7 +130,7 @@ def batch_bench(reps: int = 3):
     del fs, ts
     # tiles from the autotuner (cached per device, mode, radii and N bucket;
     # tuning happens here, before the timed replays)
-    tuner = autotune.Tuner(reps=3, probe_hw=256)
+    tuner = autotune.Tuner(reps=2, probe_tiles=(8, 32))
     t0 = time.perf_counter()
     for s in specs:
         tuner.tune(s, "fwd")

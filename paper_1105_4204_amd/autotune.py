@@ -1,8 +1,11 @@
 """Tile-shape autotuner for the fused kernels.
 
 For a (spatial radii, degree N, mode) key it times a few candidate output
-tiles of the fused forward / adjoint kernel on a synthetic image (median of
-several launches timed with HIP events) and keeps the fastest.  Results are
+tiles of the fused forward / adjoint kernel and keeps the one with the least
+time per pixel (median of several launches timed with HIP events).  Each
+candidate runs on a probe image of exactly 16 x 32 of its own tiles, so that
+every candidate fills the chip for two rounds of workgroups and none is
+favoured by how its tiles happen to divide a fixed probe size.  Results are
 cached in a JSON file (BF_TUNE_CACHE, default ~/.cache/bftrig/tune.json) keyed
 by device name, so a batch plan reuses them without re-timing.  Candidates
 are odd tile sides (odd LDS pitches) that fit the kernel's limits; invalid
@@ -17,16 +20,16 @@ import statistics
 import torch
 
 from . import _native as nat
-from . import ops, synth
+from . import ops
 
 DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "bftrig", "tune.json")
 
 
 class Tuner:
-    def __init__(self, cache_path: str | None = None, reps: int = 5, probe_hw: int = 384):
+    def __init__(self, cache_path: str | None = None, reps: int = 5, probe_tiles=(16, 32)):
         self.path = cache_path or os.environ.get("BF_TUNE_CACHE", DEFAULT_CACHE)
         self.reps = reps
-        self.probe_hw = probe_hw
+        self.probe_tiles = tuple(probe_tiles)
         self.table = {}
         if os.path.exists(self.path):
             try:
@@ -47,7 +50,7 @@ class Tuner:
         N = int(spec.get("N", 0)) or nat.range_degree(T, float(spec["sigma_r"]))
         nbucket = 1 << max(0, (N - 1).bit_length())          # N rounded up to a power of 2
         dev = torch.cuda.get_device_name(0) if torch.cuda.is_available() else "cpu"
-        return f"{dev}|{mode}|r={','.join(map(str, self._radii(spec)))}|N<={nbucket}"
+        return f"v2|{dev}|{mode}|r={','.join(map(str, self._radii(spec)))}|N<={nbucket}"
 
     def candidates(self, R, mode):
         """Output tiles up to 64 x 64 whose extended sides fit a 128-long
@@ -85,26 +88,27 @@ class Tuner:
         T = float(spec.get("T", 255.0))
         sr = float(spec["sigma_r"])
         N = int(spec.get("N", 0))
-        hw = self.probe_hw
-        f = torch.from_numpy(synth.piecewise_smooth(hw, hw, seed=99)).cuda()
-        out, eta, aux = ops.trig_forward(f, T, sr, radii, N=N, return_aux=True)
-        G = torch.randn_like(f)
+        gen = torch.Generator(device="cuda").manual_seed(99)
         best = None
         for tile in self.candidates(R, mode):
+            H, W = tile[0] * self.probe_tiles[0], tile[1] * self.probe_tiles[1]
+            f = torch.rand(H, W, device="cuda", generator=gen) * T
             try:
                 if mode == "fwd":
                     t = self._time(lambda: ops.trig_forward(f, T, sr, radii, N=N, tile=tile))
                 else:
+                    out, eta, aux = ops.trig_forward(f, T, sr, radii, N=N, return_aux=True)
+                    G = torch.randn(H, W, device="cuda", generator=gen)
                     t = self._time(lambda: ops.trig_backward(f, out, eta, aux, G, T, sr, radii,
                                                              N=N, tile=tile))
             except nat.BFError:
                 continue
-            # cost per output pixel: tiles do not divide the probe exactly
+            t /= H * W                      # time per output pixel
             if best is None or t < best[0]:
                 best = (t, tile)
         if best is None:
             return (0, 0)
-        self.table[k] = {"tile": list(best[1]), "ms": best[0]}
+        self.table[k] = {"tile": list(best[1]), "ns_per_px": best[0] * 1e6}
         self.save()
         return best[1]
 

@@ -428,6 +428,28 @@ __device__ __forceinline__ void col_role(const TileArgs& a, const TileCtx& c, in
 #pragma unroll
         for (int i0c = 0; i0c < kOutMax; i0c += kChunk) {
             if (i0c < TH) {
+                // adjoint: the chunk's inputs, loaded at clamped positions
+                // without branches so that they are all in flight together
+                float fo8[kChunk], G8[kChunk], et8[kChunk], P8[kChunk], Q8[kChunk];
+                if (MODE == kForward && a.loss_part) {   // batch forward: SSD targets
+#pragma unroll
+                    for (int ii = 0; ii < kChunk; ++ii) {
+                        const int gi = min(c.i0 + i0c + ii, a.H - 1), gj = min(c.j0 + j, a.W - 1);
+                        G8[ii] = a.target[(size_t)gi * a.W + gj];
+                    }
+                }
+                if (MODE == kBackward) {
+#pragma unroll
+                    for (int ii = 0; ii < kChunk; ++ii) {
+                        const int gi = min(c.i0 + i0c + ii, a.H - 1), gj = min(c.j0 + j, a.W - 1);
+                        const size_t gidx = (size_t)gi * a.W + gj;
+                        fo8[ii] = a.fout[gidx];
+                        G8[ii] = a.gout ? a.gout[gidx] : a.target[gidx];
+                        et8[ii] = a.feta[gidx];
+                        P8[ii] = a.paux[gidx];
+                        Q8[ii] = a.paux[HW + gidx];
+                    }
+                }
 #pragma unroll
                 for (int ii = 0; ii < kChunk; ++ii) {
                     const int k = i0c + ii;
@@ -443,17 +465,16 @@ __device__ __forceinline__ void col_role(const TileArgs& a, const TileCtx& c, in
                             if (a.eta) a.eta[gidx] = den;
                             if (AUX && a.aux) a.aux[HW + gidx] = A1[kOutMax + k];  // Q
                             if (a.loss_part) {
-                                const double d = (double)y - (double)a.target[gidx];
+                                const double d = (double)y - (double)G8[ii];
                                 sq += d * d;
                             }
                         } else {
-                            const float fo = a.fout[gidx];
-                            const float G = a.gout ? a.gout[gidx] : 2.0f * (fo - a.target[gidx]);
-                            const float Ak = G / a.feta[gidx];
+                            const float fo = fo8[ii];
+                            const float G = a.gout ? G8[ii] : 2.0f * (fo - G8[ii]);
+                            const float Ak = G / et8[ii];
                             const float Bk = Ak * (fo - a.center);
-                            const float P = a.paux[gidx], Q = a.paux[HW + gidx];
                             a.out[gidx] = (A1[kOutMax + k] + other) +
-                                          a.alpha_f * (Ak * P - Bk * Q);
+                                          a.alpha_f * (Ak * P8[ii] - Bk * Q8[ii]);
                         }
                     }
                 }

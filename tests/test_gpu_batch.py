@@ -174,7 +174,7 @@ def test_autotuner_picks_valid_tiles_for_a_batch(tmp_path):
     batch, ops = _mods()
     from paper_1105_4204_amd import autotune
     cache = str(tmp_path / "tune.json")
-    tuner = autotune.Tuner(cache_path=cache, reps=2, probe_hw=192)
+    tuner = autotune.Tuner(cache_path=cache, reps=2, probe_tiles=(2, 4))
     specs = [dict(H=140, W=100, sigma_s=4.0, sigma_r=30.0),
              dict(H=90, W=170, sigma_s=6.0, sigma_r=20.0)]
     for s in specs:
