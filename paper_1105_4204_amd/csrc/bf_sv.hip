@@ -10,8 +10,8 @@
 // the work per pixel and term does not depend on the radii.
 //
 // One workgroup of 256 threads owns a 32 x 32 output tile and the extended
-// tile of side E = 32 + 2 Rm around it (Rm rounded up to even, so rows are
-// 16-byte aligned).  Thread t keeps, in registers, g = f - T/2 and the phase
+// tile of side E = 32 + 2 Rh around it (Rh = Rm rounded up to a multiple of
+// 4, so rows are 16-byte aligned and E is a multiple of 8).  Thread t keeps, in registers, g = f - T/2 and the phase
 // Z = exp(j m a g) of the extended pixels t, t + 256, ... (zero outside the
 // image), plus the phase, radius and FP64 accumulators of the output pixels
 // t, t + 256, t + 512, t + 768.  Per channel of a pair:
@@ -46,7 +46,7 @@ struct SvArgs {
     float* eta;
     int H, W;
     int Rm;          // largest radius accepted (radii are clamped to it)
-    int Rh;          // halo: Rm rounded up to even
+    int Rh;          // halo: Rm rounded up to a multiple of 4
     int E;           // extended side: kSvTile + 2 Rh
     int tiles_x;
     int npairs, odd;
@@ -145,31 +145,37 @@ __global__ void __launch_bounds__(kSvThreads) bf_sv_kernel(const SvArgs a) {
                 }
             }
             __syncthreads();
-            // 2. running row sums (FP64) into rows 1..E of the table
+            // 2. running row sums (FP64) into rows 1..E of the table; E is a
+            // multiple of 8 and every block of 8 samples is loaded before it
+            // is summed, so LDS latency is paid once per block
             if (t < E) {
                 const float4* row = reinterpret_cast<const float4*>(stg + t * E);
                 double* dst = sat + (size_t)(t + 1) * Sp + 1;
                 double s = 0.0;
-                for (int x4 = 0; x4 < E / 4; ++x4) {
-                    const float4 u = row[x4];
-                    s += (double)u.x;
-                    dst[4 * x4] = s;
-                    s += (double)u.y;
-                    dst[4 * x4 + 1] = s;
-                    s += (double)u.z;
-                    dst[4 * x4 + 2] = s;
-                    s += (double)u.w;
-                    dst[4 * x4 + 3] = s;
+                for (int x8 = 0; x8 < E / 8; ++x8) {
+                    const float4 u0 = row[2 * x8], u1 = row[2 * x8 + 1];
+                    const float u[8] = {u0.x, u0.y, u0.z, u0.w, u1.x, u1.y, u1.z, u1.w};
+#pragma unroll
+                    for (int k = 0; k < 8; ++k) {
+                        s += (double)u[k];
+                        dst[8 * x8 + k] = s;
+                    }
                 }
             }
             __syncthreads();
-            // 3. running column sums, in place
+            // 3. running column sums, in place, 8 rows loaded at a time
             if (t < E) {
                 double* col = sat + Sp + 1 + t;
                 double s = 0.0;
-                for (int y = 0; y < E; ++y) {
-                    s += col[(size_t)y * Sp];
-                    col[(size_t)y * Sp] = s;
+                for (int y8 = 0; y8 < E; y8 += 8) {
+                    double c8[8];
+#pragma unroll
+                    for (int k = 0; k < 8; ++k) c8[k] = col[(size_t)(y8 + k) * Sp];
+#pragma unroll
+                    for (int k = 0; k < 8; ++k) {
+                        s += c8[k];
+                        col[(size_t)(y8 + k) * Sp] = s;
+                    }
                 }
             }
             __syncthreads();
@@ -222,7 +228,7 @@ bf_status launch_sv(const float* f, const int32_t* rmap, float* out, float* eta,
     a.H = (int)H;
     a.W = (int)W;
     a.Rm = rmax;
-    a.Rh = (rmax + 1) / 2 * 2;
+    a.Rh = (rmax + 3) / 4 * 4;   // E = 32 + 2 Rh is then a multiple of 8
     a.E = kSvTile + 2 * a.Rh;
     a.tiles_x = (int)((W + kSvTile - 1) / kSvTile);
     const int64_t tiles_y = (H + kSvTile - 1) / kSvTile;
