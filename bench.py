@@ -286,6 +286,9 @@ def main():
     ap.add_argument("--no-sweep", action="store_true", help="skip the sigma_s sweep")
     ap.add_argument("--no-other", action="store_true",
                     help="skip the recursive-Gaussian and space-variant timings")
+    ap.add_argument("--only-other", action="store_true",
+                    help="only time the recursive-Gaussian and space-variant paths (for "
+                         "counter runs); prints their JSON and exits")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a 512 MiB device copy (counter calibration) and exit")
     args = ap.parse_args()
@@ -322,6 +325,10 @@ def main():
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     f = torch.from_numpy(f_np).to(dev)
+    if args.only_other:
+        print(json.dumps({"workload": wl["desc"], "sigma_r": sr,
+                          "other_spatial_kernels": other_spatial_kernels(f, T, sr)}), flush=True)
+        return
     target = torch.from_numpy(t_np).to(dev)
     stream = torch.cuda.current_stream()
     do_bwd = not args.fwd_only

@@ -55,6 +55,8 @@ SMALL = [
     (7, 5, 30.0, 31, [6, 6], "salt"),            # window larger than the image
     (60, 60, 30.0, 0, [0], "smooth"),            # radius 0: identity
     (129, 257, 15.0, 0, [7, 7, 8], "smooth"),    # several tiles and ragged tails
+    (20, 30, 5.1, 1024, [2], "smooth"),          # the largest degree accepted
+    (40, 50, 30.0, 0, [31, 31, 1], "smooth"),    # R = 63: the widest fused kernel
 ]
 
 
