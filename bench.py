@@ -53,9 +53,9 @@ WORKLOADS = {
 # kernel sources they were taken on (hash of TILE_SOURCES).  Record:
 # profiles/bf_tile_kernels_2048x2048_N66_hbm_traffic.md.
 MEASURED_TRAFFIC = {
-    ("bf_tile_kernel<kForward,false>", "config2"): {"bytes": 54997835, "src": "5b5035567f95"},
-    ("bf_tile_kernel<kForward,true>", "config2"): {"bytes": 110853088, "src": "5b5035567f95"},
-    ("bf_tile_kernel<kBackward,false>", "config2"): {"bytes": 328799321, "src": "5b5035567f95"},
+    ("bf_tile_kernel<kForward,false>", "config2"): {"bytes": 55863534, "src": "b937d459346a"},
+    ("bf_tile_kernel<kForward,true>", "config2"): {"bytes": 111075334, "src": "b937d459346a"},
+    ("bf_tile_kernel<kBackward,false>", "config2"): {"bytes": 338494028, "src": "b937d459346a"},
 }
 TILE_SOURCES = ("bf_tile.h", "bf_box.h", "bf_tile.hip")
 
@@ -202,14 +202,14 @@ def yvv_bytes_per_pixel(npairs: int) -> int:
 
     Per pair and channel (4 channels): vertical pass writes the causal output
     and rewrites it anticausally (read + write), horizontal pass reads it,
-    writes and rereads its causal output (7 x 4 B).  Per group of 2 pairs: f
+    writes and rereads its causal output (6 x 4 B).  Per group of 2 pairs: f
     read by both passes (8 B), den and num partial planes written and reduced
     (16 B).  Per launch chunk of up to 32 pairs: den and num read-modify-written
     (16 B); then the division reads them and writes out (12 B).
     """
     groups = (npairs + 1) // 2
     chunks = (groups + 15) // 16
-    return npairs * 4 * 28 + groups * 24 + chunks * 16 + 12
+    return npairs * 4 * 24 + groups * 24 + chunks * 16 + 12
 
 
 def other_spatial_kernels(f, T, sr, reps=3):
