@@ -234,7 +234,7 @@ bf_status bf_trig_backward(const float* f, const float* out, const float* eta,
         }
     }
     TileGeom g;
-    st = plan_bwd_tiles(H, W, c.sp, opts ? opts->tile_h : 0, opts ? opts->tile_w : 0, &g);
+    st = plan_bwd_tiles(H, W, c.sp, opts ? opts->tile_h : 0, opts ? opts->tile_w : 0, &g, f);
     if (st != BF_OK) return st;
     return launch_bwd(f, out, eta, aux, grad_out, grad_f, H, W, c.rp, c.sp, g, c.stream);
 }

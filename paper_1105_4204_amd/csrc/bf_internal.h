@@ -60,6 +60,7 @@ struct TileGeom {
     int EWp, EHp;     // LDS pitches of extended rows and of transposed rows
     int tiles_x, tiles_y;
     size_t lds_bytes;
+    bool gg;          // adjoint: g read from global memory (one LDS plane)
 };
 
 bf_status plan_fwd_tiles(int64_t H, int64_t W, const SpatialParams& sp, int req_h, int req_w,
@@ -70,7 +71,7 @@ bf_status launch_fwd(const float* f, float* out, float* eta, float* aux, int64_t
 bf_status launch_direct(const float* f, float* out, float* eta, int64_t H, int64_t W,
                         const RangeParams& rp, const SpatialParams& sp, hipStream_t stream);
 bf_status plan_bwd_tiles(int64_t H, int64_t W, const SpatialParams& sp, int req_h, int req_w,
-                         TileGeom* g);
+                         TileGeom* g, const float* f);
 // Staged forward for spatial radii beyond the fused kernel (bf_staged.hip).
 bool staged_supported(const SpatialParams& sp);
 struct TileGeom;

@@ -78,10 +78,13 @@ __host__ __device__ inline int tile_t_floats(int TW, int EHp) { return tile_roun
 // Forward only: g at the output pixels, transposed (column j at j * kGtPitch).
 constexpr int kGtPitch = tile_pitch(kOutMax);
 constexpr int kGtFloats = kOutMax * kGtPitch;
-// LDS layout (floats): gplane | hplane (adjoint) | T0 | T1 | gT (forward).
-__host__ __device__ inline size_t tile_lds_floats(int mode, int TH, int TW, int R) {
+// LDS layout (floats): forward gplane | T0 | T1 | gT; adjoint gplane | hplane
+// | T0 | T1, or with GG (g read from global memory, where the tile's rows stay
+// in L2) hplane | T0 | T1, so that a 64 x 64 adjoint tile fits.
+__host__ __device__ inline size_t tile_lds_floats(int mode, int TH, int TW, int R,
+                                                  bool gg = false) {
     const int EH = TH + 2 * R, EW = TW + 2 * R;
-    const int planes = mode == kForward ? 1 : 2;
+    const int planes = (mode == kBackward && !gg) ? 2 : 1;
     return (size_t)planes * tile_plane_floats(EH, tile_pitch(EW)) +
            2 * (size_t)tile_t_floats(TW, tile_pitch(EH)) + (mode == kForward ? kGtFloats : 0);
 }
@@ -132,6 +135,33 @@ __device__ __forceinline__ void load_line(float (&v)[kLine], const float* src) {
     }
 }
 
+// Adjoint with GG: g = f - T/2 along extended row i of the tile, from global
+// memory (the rows are L2-resident while the tile runs), in 16-byte buffer
+// loads: the lane's row start is the vector offset and the chunk's column the
+// scalar offset, so the 32 loads need no per-chunk address registers.  GG
+// requires W, the tile width and R to be multiples of 4, f 16-byte aligned and
+// 4 H W < 2^31, so that every 4-sample chunk of the extended row lies wholly
+// inside or wholly outside the image; chunks outside read a clamped in-image
+// chunk, whose values are never used because the phase there is zero.
+constexpr int kBufferWord3 = 0x00020000;   // raw buffer resource, gfx9 family
+__device__ __forceinline__ void load_g_row(const TileArgs& a, int ei0, int ej0, int i,
+                                           float (&v)[kLine]) {
+    const int W = __builtin_amdgcn_readfirstlane(a.W);
+    const int e0 = __builtin_amdgcn_readfirstlane(ej0);
+    const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+        const_cast<float*>(a.f), 0, a.H * W * (int)sizeof(float), kBufferWord3);
+    const int voff = min(max(ei0 + i, 0), a.H - 1) * W * (int)sizeof(float);
+#pragma unroll
+    for (int k = 0; k < kLine / 4; ++k) {
+        const int soff = min(max(e0 + 4 * k, 0), W - 4) * (int)sizeof(float);   // uniform
+        const auto q = __builtin_amdgcn_raw_buffer_load_b128(rs, voff, soff, 0);
+        v[4 * k] = __uint_as_float(q[0]) - a.center;
+        v[4 * k + 1] = __uint_as_float(q[1]) - a.center;
+        v[4 * k + 2] = __uint_as_float(q[2]) - a.center;
+        v[4 * k + 3] = __uint_as_float(q[3]) - a.center;
+    }
+}
+
 // (zr + j zi)[x] *= exp(j step g[x]) for x < n.
 template <int n, int L>
 __device__ __forceinline__ void phase_step(float (&zr)[L], float (&zi)[L], const float (&g)[kLine],
@@ -160,7 +190,7 @@ struct TileCtx {
     int EH, EW, TH, TW, R, EWp, EHp, tfl;
     int i0, j0, ei0, ej0;     // output and extended tile origins (image coordinates)
     int t, wave, lane;
-    float* gpl;               // g = f - T/2 on the extended tile
+    float* gpl;               // forward: g = f - T/2 on the extended tile
     float* hpl;               // adjoint: A, then h = out - T/2
     float* Tb;                // T0 | T1: row results, transposed
     float* gT;                // forward: g at the output pixels, column-major
@@ -207,13 +237,16 @@ __device__ __forceinline__ int tile_out_barriers(const TileArgs& a, int mode) {
 
 // Row role (waves 0-1): lane i owns extended row i.  State: A0 + j A1 = Z
 // (forward) or Y = A Z (adjoint) at the row's pixels; zero outside the image.
-template <int MODE>
+template <int MODE, bool GG>
 __device__ __forceinline__ void row_role(const TileArgs& a, const TileCtx& c) {
     const int i = c.t;
     const bool act = i < c.EH;
     float A0[kLine], A1[kLine], v[kLine];
     if (act) {
-        load_line(v, c.gpl + i * c.EWp);
+        if (GG)
+            load_g_row(a, c.ei0, c.ej0, i, v);
+        else
+            load_line(v, c.gpl + i * c.EWp);
         const int gi = c.ei0 + i;
         const bool rin = gi >= 0 && gi < a.H;
         const int xlo = c.ej0 < 0 ? -c.ej0 : 0;
@@ -254,7 +287,10 @@ __device__ __forceinline__ void row_role(const TileArgs& a, const TileCtx& c) {
     for (int s = 0; s <= a.nsteps; ++s) {
         if (s < a.nsteps && act) {
             if (ch == 0 && q > 0) {
-                load_line(v, c.gpl + i * c.EWp);
+                if (GG)
+                    load_g_row(a, c.ei0, c.ej0, i, v);
+                else
+                    load_line(v, c.gpl + i * c.EWp);
                 phase_step<kLine>(A0, A1, v, 0, a.two_alpha);
             }
             if (ch & 1) load_line(v, mulpl + i * c.EWp);
@@ -294,7 +330,7 @@ __device__ __forceinline__ void row_role(const TileArgs& a, const TileCtx& c) {
 // j A1[0..64) = Z at the column's outputs; tails: forward den|num (A0) and
 // Q|P (A1) on wave 2|3; adjoint g at the outputs (A0) and the partial sum
 // (A1).  Wave 2 filters the channels with even index, wave 3 the odd ones.
-template <int MODE, bool AUX>
+template <int MODE, bool AUX, bool GG>
 __device__ __forceinline__ void col_role(const TileArgs& a, const TileCtx& c, int tile_id) {
     const int j = c.lane;
     const bool act = j < c.TW;
@@ -311,6 +347,13 @@ __device__ __forceinline__ void col_role(const TileArgs& a, const TileCtx& c, in
                 v[4 * k + 1] = q4.y;
                 v[4 * k + 2] = q4.z;
                 v[4 * k + 3] = q4.w;
+            }
+        } else if (GG) {   // adjoint, g from global memory; rows past TH repeat the last
+            const int gj = min(c.j0 + j, a.W - 1);
+#pragma unroll
+            for (int k = 0; k < kOutMax; ++k) {
+                const int gi = min(c.i0 + min(k, TH - 1), a.H - 1);
+                v[k] = a.f[(size_t)gi * a.W + gj] - a.center;
             }
         } else {
             const float* gcol = c.gpl + c.R * c.EWp + c.R + j;
@@ -497,7 +540,7 @@ __device__ __forceinline__ void col_role(const TileArgs& a, const TileCtx& c, in
 
 // One output tile of one image (tile index tile_id) for descriptor a; all
 // 256 threads of the workgroup call it together.
-template <int MODE, bool AUX>
+template <int MODE, bool AUX, bool GG = false>
 __device__ __forceinline__ void tile_body(const TileArgs& a, int tile_id, float* smem) {
     TileCtx c;
     c.EH = a.EH;
@@ -509,9 +552,9 @@ __device__ __forceinline__ void tile_body(const TileArgs& a, int tile_id, float*
     c.EHp = a.EHp;
     c.tfl = tile_t_floats(a.TW, a.EHp);
     const int pfl = tile_plane_floats(a.EH, a.EWp);
-    c.gpl = smem;
-    c.hpl = c.gpl + pfl;
-    c.Tb = (MODE == kBackward) ? c.hpl + pfl : c.gpl + pfl;
+    c.gpl = GG ? nullptr : smem;
+    c.hpl = (MODE == kBackward) ? (GG ? smem : smem + pfl) : nullptr;
+    c.Tb = (MODE == kBackward && !GG) ? smem + 2 * pfl : smem + pfl;
     c.gT = c.Tb + 2 * c.tfl;
     c.t = threadIdx.x;
     c.wave = __builtin_amdgcn_readfirstlane(c.t >> 6);
@@ -522,7 +565,7 @@ __device__ __forceinline__ void tile_body(const TileArgs& a, int tile_id, float*
     c.ei0 = c.i0 - a.R;
     c.ej0 = c.j0 - a.R;
 
-    fill_plane(a, c, c.gpl, [&](size_t k) { return a.f[k] - a.center; });
+    if (!GG) fill_plane(a, c, c.gpl, [&](size_t k) { return a.f[k] - a.center; });
     if (MODE == kBackward) {
         // A = G / eta, staged where h goes once the row lanes have taken it
         fill_plane(a, c, c.hpl, [&](size_t k) {
@@ -540,21 +583,21 @@ __device__ __forceinline__ void tile_body(const TileArgs& a, int tile_id, float*
         __syncthreads();
     }
     if (c.wave < 2)
-        row_role<MODE>(a, c);
+        row_role<MODE, GG>(a, c);
     else
-        col_role<MODE, AUX>(a, c, tile_id);
+        col_role<MODE, AUX, GG>(a, c, tile_id);
 }
 
-template <int MODE, bool AUX>
+template <int MODE, bool AUX, bool GG = false>
 __global__ void __launch_bounds__(kTileThreads)
 bf_tile_kernel(const TileArgs a) {
     extern __shared__ __align__(16) float smem[];
-    tile_body<MODE, AUX>(a, blockIdx.x, smem);
+    tile_body<MODE, AUX, GG>(a, blockIdx.x, smem);
 }
 
 // Host helpers shared by the single-image and batched launchers (bf_tile.hip).
 bf_status plan_tiles(int mode, int64_t H, int64_t W, const SpatialParams& sp, int req_h,
-                     int req_w, TileGeom* g);
+                     int req_w, TileGeom* g, bool gg = false);
 void fill_tile_args(TileArgs& a, int64_t H, int64_t W, const RangeParams& rp,
                     const SpatialParams& sp, const TileGeom& g, int mode);
 

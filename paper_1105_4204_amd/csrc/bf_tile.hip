@@ -10,7 +10,7 @@ static constexpr size_t kLdsLimit = 160 * 1024 - 256;   // LDS per workgroup on 
                                                           // room for a persistent kernel's statics
 
 bf_status plan_tiles(int mode, int64_t H, int64_t W, const SpatialParams& sp, int req_h,
-                     int req_w, TileGeom* g) {
+                     int req_w, TileGeom* g, bool gg) {
     const int R = sp.R;
     for (int k = 0; k < sp.nb; ++k) {
         if (sp.r[k] > kBoxMaxRadius) {
@@ -26,11 +26,11 @@ bf_status plan_tiles(int mode, int64_t H, int64_t W, const SpatialParams& sp, in
         return BF_EUNSUPPORTED;
     }
     auto lds_of = [&](int th, int tw) {
-        return tile_lds_floats(mode, th, tw, R) * sizeof(float);
+        return tile_lds_floats(mode, th, tw, R, gg) * sizeof(float);
     };
     auto fits = [&](int th, int tw) {
         return th >= 1 && tw >= 1 && th <= side_max && tw <= side_max &&
-               lds_of(th, tw) <= kLdsLimit;
+               lds_of(th, tw) <= kLdsLimit && (!gg || tw % 4 == 0);
     };
     int th = req_h, tw = req_w;
     if (th <= 0 || tw <= 0) {
@@ -71,6 +71,7 @@ bf_status plan_tiles(int mode, int64_t H, int64_t W, const SpatialParams& sp, in
     g->tiles_y = (int)((H + th - 1) / th);
     g->tiles_x = (int)((W + tw - 1) / tw);
     g->lds_bytes = lds_of(th, tw);
+    g->gg = gg;
     return BF_OK;
 }
 
@@ -79,9 +80,18 @@ bf_status plan_fwd_tiles(int64_t H, int64_t W, const SpatialParams& sp, int req_
     return plan_tiles(kForward, H, W, sp, req_h, req_w, g);
 }
 
+// The adjoint reads g from global memory (GG), freeing one LDS plane for
+// larger tiles, when 16-byte row chunks line up with the image: W and R
+// multiples of 4, f 16-byte aligned and the image under 2 GiB (32-bit buffer
+// offsets); the tile width is then kept a multiple of 4 as well.  Otherwise
+// g is staged in LDS.
 bf_status plan_bwd_tiles(int64_t H, int64_t W, const SpatialParams& sp, int req_h, int req_w,
-                         TileGeom* g) {
-    return plan_tiles(kBackward, H, W, sp, req_h, req_w, g);
+                         TileGeom* g, const float* f) {
+    const bool gg_ok = W % 4 == 0 && sp.R % 4 == 0 && H * W * 4 < ((int64_t)1 << 31) &&
+                       (reinterpret_cast<uintptr_t>(f) & 15) == 0 &&
+                       (req_w <= 0 || req_w % 4 == 0);
+    if (gg_ok && plan_tiles(kBackward, H, W, sp, req_h, req_w, g, true) == BF_OK) return BF_OK;
+    return plan_tiles(kBackward, H, W, sp, req_h, req_w, g, false);
 }
 
 void fill_tile_args(TileArgs& a, int64_t H, int64_t W, const RangeParams& rp,
@@ -109,13 +119,13 @@ void fill_tile_args(TileArgs& a, int64_t H, int64_t W, const RangeParams& rp,
     for (int q = 0; q < kMaxPairs; ++q) a.chat[q] = q < rp.npairs ? rp.chat[q] : 0.0f;
 }
 
-template <int MODE, bool AUX>
+template <int MODE, bool AUX, bool GG = false>
 static bf_status launch_tile(const TileArgs& a, const TileGeom& g, hipStream_t stream,
                              const char* what) {
     const dim3 grid((unsigned)(g.tiles_x * g.tiles_y)), block(kTileThreads);
-    (void)hipFuncSetAttribute((const void*)bf_tile_kernel<MODE, AUX>,
+    (void)hipFuncSetAttribute((const void*)bf_tile_kernel<MODE, AUX, GG>,
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)g.lds_bytes);
-    hipLaunchKernelGGL((bf_tile_kernel<MODE, AUX>), grid, block, g.lds_bytes, stream, a);
+    hipLaunchKernelGGL((bf_tile_kernel<MODE, AUX, GG>), grid, block, g.lds_bytes, stream, a);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) {
         set_error("%s launch failed: %s", what, hipGetErrorString(e));
@@ -148,6 +158,7 @@ bf_status launch_bwd(const float* f, const float* out, const float* eta, const f
     a.paux = aux;
     a.gout = gout;
     fill_tile_args(a, H, W, rp, sp, g, kBackward);
+    if (g.gg) return launch_tile<kBackward, false, true>(a, g, stream, "backward");
     return launch_tile<kBackward, false>(a, g, stream, "backward");
 }
 

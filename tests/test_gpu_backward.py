@@ -121,3 +121,62 @@ def test_backward_deterministic():
     b = ops.trig_backward(f, out, eta, aux, G, 255.0, 20.0, [9, 9, 10])
     torch.cuda.synchronize()
     assert torch.equal(a, b)
+
+
+# The adjoint reads g from global memory (one LDS plane, larger tiles) when W
+# and R are multiples of 4 and f is 16-byte aligned; these cases take that path.
+GG_CASES = [
+    (36, 48, 25.0, 0, [1, 1, 2]),
+    (33, 68, 30.0, 0, [4]),
+    (20, 8, 20.0, 0, [2, 2]),
+]
+
+
+@pytest.mark.parametrize("case", GG_CASES, ids=[f"{c[0]}x{c[1]}-r{c[4]}" for c in GG_CASES])
+def test_backward_global_g_full_parity(case):
+    H, W, sr, N, radii = case
+    assert W % 4 == 0 and sum(radii) % 4 == 0
+    print(f"case {case}", flush=True)
+    f = synth.piecewise_smooth(H, W, seed=H + 11 * W, n_shapes=3)
+    G = np.random.default_rng(H + W).normal(size=(H, W))
+    Nuse = N or oracle.range_degree(255.0, sr)
+    ref = oracle.grad(f, sr, Nuse, radii, G)
+    ops = _ops()
+    fg = _cuda(f)
+    out, eta, aux = ops.trig_forward(fg, 255.0, sr, radii, N=N, return_aux=True)
+    gf = ops.trig_backward(fg, out, eta, aux, _cuda(G), 255.0, sr, radii, N=N)
+    torch.cuda.synchronize()
+    _check(gf.cpu().numpy(), ref, f"grad gg {case}")
+
+
+def test_backward_both_g_paths_agree_and_match_oracle():
+    """The same 130 x 200 image (R = 8) through both adjoint variants: an
+    aligned tensor takes the global-g kernel (64 x 64 tiles), a view shifted
+    by one float (not 16-byte aligned) the LDS-g kernel (smaller tiles).  Both
+    must match the oracle on sampled pixels, borders included, and each other
+    to rounding."""
+    H, W, sr, radii = 130, 200, 20.0, [2, 3, 3]
+    f = synth.piecewise_smooth(H, W, seed=91, n_shapes=4)
+    G = np.random.default_rng(92).normal(size=(H, W))
+    ops = _ops()
+    fa = _cuda(f)
+    big = torch.empty(H * W + 1, device="cuda")
+    fm = big[1:].view(H, W)
+    fm.copy_(fa)
+    assert fa.data_ptr() % 16 == 0 and fm.data_ptr() % 16 != 0
+    grads = []
+    for fx in (fa, fm):
+        out, eta, aux = ops.trig_forward(fx, 255.0, sr, radii, return_aux=True)
+        grads.append(ops.trig_backward(fx, out, eta, aux, _cuda(G), 255.0, sr, radii))
+    torch.cuda.synchronize()
+    g0, g1 = grads[0].cpu().numpy(), grads[1].cpu().numpy()
+    scale = np.abs(g0).max()
+    assert np.max(np.abs(g0 - g1)) <= 1e-4 * scale
+    N = oracle.range_degree(255.0, sr)
+    rng = np.random.default_rng(93)
+    idx = list(rng.integers(0, H * W, 24)) + [0, W - 1, (H - 1) * W, H * W - 1, 64 * W + 64,
+                                              63 * W + 127, 100 * W + 196]
+    idx = np.array(idx, dtype=np.int64)
+    ref = oracle.grad_at(f, sr, N, radii, G, idx)
+    _check(g0.reshape(-1)[idx], ref, "global-g sampled")
+    _check(g1.reshape(-1)[idx], ref, "LDS-g sampled")
