@@ -204,11 +204,11 @@ def yvv_bytes_per_pixel(npairs: int) -> int:
     and rewrites it anticausally (read + write), horizontal pass reads it,
     writes and rereads its causal output (6 x 4 B).  Per group of 2 pairs: f
     read by both passes (8 B), den and num partial planes written and reduced
-    (16 B).  Per launch chunk of up to 32 pairs: den and num read-modify-written
+    (16 B).  Per launch chunk of up to 40 pairs: den and num read-modify-written
     (16 B); then the division reads them and writes out (12 B).
     """
     groups = (npairs + 1) // 2
-    chunks = (groups + 15) // 16
+    chunks = (groups + 19) // 20
     return npairs * 4 * 24 + groups * 24 + chunks * 16 + 12
 
 

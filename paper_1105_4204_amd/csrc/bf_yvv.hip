@@ -27,8 +27,9 @@
 //     into the group's den and num partial planes;
 //   bf_yvv_reduce adds a chunk's partial planes into den and num in a fixed
 //   order; bf_yvv_final divides in FP64 and writes out and eta.
-// The pairs are split into launch chunks of equal size (at most 32 pairs),
-// so that no chunk is a small tail with few workgroups.
+// The pairs are split into launch chunks of equal size (at most 40 pairs, so
+// the 66-degree workload runs as one chunk), so that no chunk is a small tail
+// with few workgroups.
 // Unlike the fused box kernel, the filtered channels of a chunk pass through
 // device memory: this path is bound by HBM traffic, about 120 bytes per pixel
 // and pair.
@@ -40,10 +41,10 @@ namespace bf {
 
 constexpr int kYvThreads = 256;      // four waves, one per channel
 constexpr int kYvPairs = 2;          // pairs per thread (one direct phase, one recurrence step)
-constexpr int kYvChunkGroups = 16;   // groups per launch chunk, at most (32 pairs)
+constexpr int kYvChunkGroups = 20;   // groups per launch chunk, at most (40 pairs)
 constexpr int kYvBlk = 32;           // horizontal pass: columns per LDS block
 constexpr int kYvBlkP = kYvBlk + 1;
-constexpr int kYvRows = 8;           // vertical pass: rows whose loads are issued together
+constexpr int kYvRows = 16;          // vertical pass: rows whose loads are issued together
 
 struct YvArgs {
     const float* f;
@@ -185,33 +186,58 @@ __global__ void __launch_bounds__(kYvThreads) bf_yvv_h(const YvArgs a) {
     float cq[kYvPairs];
 #pragma unroll
     for (int p = 0; p < kYvPairs; ++p) cq[p] = p < np ? a.chat[qg + p] : 0.0f;
-    // block transfers: lane l moves column l & 31 of rows 2 r + (l >> 5)
+    // block transfers: lane l moves column l & 31 of rows 2 r + (l >> 5).
+    // Double buffering: while a block is filtered from LDS, the next block's
+    // values are already on their way into registers (t, tg), from clamped
+    // positions without branches; they are masked when written to LDS.
     const int bc = lane & 31, br = lane >> 5;
-    // loads at clamped positions, unconditionally, 16 in flight per lane
-    auto load_blk = [&](int x0) {
+    float t[kYvPairs][32];
+    float tg[8];
+    auto fetch_blk = [&](int x0) {
         const int x = min(x0 + bc, a.W - 1);
-        for (int p = 0; p < np; ++p) {
-            for (int r0 = 0; r0 < 32; r0 += 16) {
-                float t[16];
 #pragma unroll
-                for (int r = 0; r < 16; ++r) {
-                    const int y = min(y0 + 2 * (r0 + r) + br, a.H - 1);
-                    t[r] = planes[(size_t)p * 4 * HW + (size_t)y * a.W + x];
-                }
+        for (int p = 0; p < kYvPairs; ++p) {
+            const int pc = min(p, np - 1);
 #pragma unroll
-                for (int r = 0; r < 16; ++r) {
-                    const int row = 2 * (r0 + r) + br;
-                    blk[ch][p][row][bc] = (y0 + row < a.H && x0 + bc < a.W) ? t[r] : 0.0f;
-                }
+            for (int r = 0; r < 32; ++r) {
+                const int y = min(y0 + 2 * r + br, a.H - 1);
+                t[p][r] = planes[(size_t)pc * 4 * HW + (size_t)y * a.W + x];
             }
         }
     };
-    auto store_blk = [&](int x0, float* base, int nplanes, size_t pstride) {
-        for (int p = 0; p < nplanes; ++p) {
+    auto put_blk = [&](int x0) {
+#pragma unroll
+        for (int p = 0; p < kYvPairs; ++p) {
+#pragma unroll
+            for (int r = 0; r < 32; ++r) {
+                const int row = 2 * r + br;
+                blk[ch][p][row][bc] = (y0 + row < a.H && x0 + bc < a.W) ? t[p][r] : 0.0f;
+            }
+        }
+    };
+    // g of a block: wave w moves rows 2 r + (l >> 5) for r in [8 w, 8 w + 8)
+    auto fetch_g = [&](int x0) {
+        const int x = min(x0 + bc, a.W - 1);
+#pragma unroll
+        for (int r = 0; r < 8; ++r) {
+            const int y = min(y0 + 2 * (8 * ch + r) + br, a.H - 1);
+            tg[r] = a.f[(size_t)y * a.W + x];
+        }
+    };
+    auto put_g = [&](int x0) {
+#pragma unroll
+        for (int r = 0; r < 8; ++r) {
+            const int row = 2 * (8 * ch + r) + br;
+            gblk[row][bc] = (y0 + row < a.H && x0 + bc < a.W) ? tg[r] - a.center : 0.0f;
+        }
+    };
+    auto store_blk = [&](int x0) {
+        for (int p = 0; p < np; ++p) {
 #pragma unroll 8
             for (int r = 0; r < 32; ++r) {
                 const int row = 2 * r + br, y = y0 + row, x = x0 + bc;
-                if (y < a.H && x < a.W) base[(size_t)p * pstride + (size_t)y * a.W + x] = blk[ch][p][row][bc];
+                if (y < a.H && x < a.W)
+                    planes[(size_t)p * 4 * HW + (size_t)y * a.W + x] = blk[ch][p][row][bc];
             }
         }
     };
@@ -220,9 +246,11 @@ __global__ void __launch_bounds__(kYvThreads) bf_yvv_h(const YvArgs a) {
     for (int p = 0; p < kYvPairs; ++p) s1[p] = s2[p] = s3[p] = 0.0;
     const int nblk = (a.W + kYvBlk - 1) / kYvBlk;
     // causal, left to right
+    fetch_blk(0);
     for (int b = 0; b < nblk; ++b) {
         const int x0 = b * kYvBlk;
-        load_blk(x0);
+        put_blk(x0);
+        if (b + 1 < nblk) fetch_blk(x0 + kYvBlk);
         __syncthreads();
         const int ncol = min(kYvBlk, a.W - x0);
         for (int c = 0; c < ncol; ++c) {
@@ -239,7 +267,7 @@ __global__ void __launch_bounds__(kYvThreads) bf_yvv_h(const YvArgs a) {
             }
         }
         __syncthreads();
-        store_blk(x0, planes, np, 4 * HW);
+        store_blk(x0);
         __syncthreads();
     }
     double v1[kYvPairs], v2[kYvPairs], v3[kYvPairs];
@@ -249,25 +277,18 @@ __global__ void __launch_bounds__(kYvThreads) bf_yvv_h(const YvArgs a) {
         v2[p] = a.M[3] * s1[p] + a.M[4] * s2[p] + a.M[5] * s3[p];
         v3[p] = a.M[6] * s1[p] + a.M[7] * s2[p] + a.M[8] * s3[p];
     }
-    // anticausal, right to left, demodulated into the partial plane
+    // anticausal, right to left, demodulated into the partial plane (the
+    // causal stores above are complete: the loads below are issued after the
+    // last barrier, and each lane's loads follow its own stores)
+    fetch_blk((nblk - 1) * kYvBlk);
+    fetch_g((nblk - 1) * kYvBlk);
     for (int b = nblk - 1; b >= 0; --b) {
         const int x0 = b * kYvBlk;
-        load_blk(x0);
-        if (ch == 0) {
-            const int x = min(x0 + bc, a.W - 1);
-            for (int r0 = 0; r0 < 32; r0 += 16) {
-                float t[16];
-#pragma unroll
-                for (int r = 0; r < 16; ++r) {
-                    const int y = min(y0 + 2 * (r0 + r) + br, a.H - 1);
-                    t[r] = a.f[(size_t)y * a.W + x];
-                }
-#pragma unroll
-                for (int r = 0; r < 16; ++r) {
-                    const int row = 2 * (r0 + r) + br;
-                    gblk[row][bc] = (y0 + row < a.H && x0 + bc < a.W) ? t[r] - a.center : 0.0f;
-                }
-            }
+        put_blk(x0);
+        put_g(x0);
+        if (b > 0) {
+            fetch_blk(x0 - kYvBlk);
+            fetch_g(x0 - kYvBlk);
         }
         __syncthreads();
         const int ncol = min(kYvBlk, a.W - x0);
@@ -339,8 +360,11 @@ static int yvv_chunk_groups(int npairs) {
     return (groups + chunks - 1) / chunks;
 }
 
+// Sized for the largest chunk any pair count up to npairs can produce (term
+// truncation may lower the count, and a balanced split of fewer groups can
+// have larger chunks).
 size_t yvv_workspace_bytes(int64_t H, int64_t W, int npairs) {
-    const int G = yvv_chunk_groups(npairs);
+    const int G = std::min(kYvChunkGroups, (npairs + kYvPairs - 1) / kYvPairs);
     const size_t planes = (size_t)G * kYvPairs * 4 + (size_t)G * 2 + 2;
     return planes * (size_t)H * (size_t)W * sizeof(float);
 }

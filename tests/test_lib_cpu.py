@@ -278,10 +278,13 @@ def test_yvv_forward_validates_before_any_launch():
     import ctypes
     L = nat.lib()
     H = W = 64
-    # N = 66: 34 pairs in 17 groups of 2, two chunks of 9 groups; 8 planes per
-    # group's channels, 2 partial planes per group, den and num
+    # N = 66: 34 pairs in 17 groups of 2, one chunk; 8 planes per group's
+    # channels, 2 partial planes per group, den and num
     need = nat.yvv_workspace_bytes(H, W, 255.0, 20.0)
-    assert need == (9 * 8 + 9 * 2 + 2) * H * W * 4
+    assert need == (17 * 8 + 17 * 2 + 2) * H * W * 4
+    # N = 264: the 108 pairs with a nonzero float coefficient, 54 groups; sized
+    # for the largest chunk (20 groups) any truncated pair count may need
+    assert nat.yvv_workspace_bytes(H, W, 255.0, 10.0) == (20 * 8 + 20 * 2 + 2) * H * W * 4
     # N = 8: 5 pairs, 3 groups, one chunk
     assert nat.yvv_workspace_bytes(H, W, 255.0, 60.0) == (3 * 8 + 3 * 2 + 2) * H * W * 4
     f, o = ctypes.c_void_p(0x100000), ctypes.c_void_p(0x900000)
