@@ -50,7 +50,7 @@ class Tuner:
         N = int(spec.get("N", 0)) or nat.range_degree(T, float(spec["sigma_r"]))
         nbucket = 1 << max(0, (N - 1).bit_length())          # N rounded up to a power of 2
         dev = torch.cuda.get_device_name(0) if torch.cuda.is_available() else "cpu"
-        return f"v2|{dev}|{mode}|r={','.join(map(str, self._radii(spec)))}|N<={nbucket}"
+        return f"v3|{dev}|{mode}|r={','.join(map(str, self._radii(spec)))}|N<={nbucket}"
 
     def candidates(self, R, mode):
         """Output tiles up to 64 x 64 whose extended sides fit a 128-long
@@ -92,7 +92,10 @@ class Tuner:
         best = None
         for tile in self.candidates(R, mode):
             H, W = tile[0] * self.probe_tiles[0], tile[1] * self.probe_tiles[1]
-            f = torch.rand(H, W, device="cuda", generator=gen) * T
+            # a view one float into its buffer: not 16-byte aligned, so the
+            # single-image adjoint stages g in LDS like the batch kernel does
+            # (the global-g variant fits larger tiles than the batch can use)
+            f = (torch.rand(H * W + 1, device="cuda", generator=gen) * T)[1:].view(H, W)
             try:
                 if mode == "fwd":
                     t = self._time(lambda: ops.trig_forward(f, T, sr, radii, N=N, tile=tile))
