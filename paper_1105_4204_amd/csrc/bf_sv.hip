@@ -11,10 +11,11 @@
 //
 // One workgroup of 256 threads owns a 32 x 32 output tile and the extended
 // tile of side E = 32 + 2 Rh around it (Rh = Rm rounded up to a multiple of
-// 4, so rows are 16-byte aligned and E is a multiple of 8).  Thread t keeps, in registers, g = f - T/2 and the phase
-// Z = exp(j m a g) of the extended pixels t, t + 256, ... (zero outside the
-// image), plus the phase, radius and FP64 accumulators of the output pixels
-// t, t + 256, t + 512, t + 768.  Per channel of a pair:
+// 4, so rows are 16-byte aligned and E is a multiple of 8).  Thread t keeps,
+// in registers, g = f - T/2 and the phase Z = exp(j m a g) of the extended
+// pixels t, t + 256, ... (zero outside the image), plus the phase, radius and
+// FP64 accumulators of the output pixels t, t + 256, t + 512, t + 768.  Per
+// channel of a pair:
 //   1. every thread writes the channel (C, gC, S, gS; 1, g for m = 0) of its
 //      extended pixels to an FP32 staging plane in LDS;
 //   2. one thread per extended row forms the running row sums in FP64 into
