@@ -143,7 +143,11 @@ bf_status bf_trig_forward_ex(const float* f, int64_t H, int64_t W, float T, floa
  * Q = sum_m c_m m (C_m F[S_m] - S_m F[C_m]) (g = f - T/2, C_m + j S_m =
  * exp(j m alpha g)), which the forward writes to opts->aux_out.  f, out, eta,
  * grad_out and grad_f are H*W, aux 2*H*W; grad_f must not overlap the
- * inputs.  opts->aux_out is ignored. */
+ * inputs.  opts->aux_out is ignored.  When W and the kernel half-width R are
+ * multiples of 4, f is 16-byte aligned and 4 H W < 2^31, the adjoint reads g
+ * from global memory and fits tiles up to 64 x 64 (widths a multiple of 4);
+ * otherwise it stages g in LDS and fits smaller tiles.  An explicit
+ * opts->tile_h x tile_w that fits neither returns BF_EINVAL. */
 bf_status bf_trig_backward(const float* f, const float* out, const float* eta,
                            const float* aux, const float* grad_out, int64_t H, int64_t W,
                            float T, float sigma_r, const bf_spatial_spec* spatial_spec,
