@@ -4,7 +4,7 @@
 // applies the box stages of the separable spatial kernel in place.  The box
 // radius is a template parameter, so every index is a compile-time constant
 // and the line stays in VGPRs; box_dispatch() selects the instantiation for a
-// run-time radius with a wave-uniform switch.
+// run-time radius with a chain of wave-uniform tests.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -54,44 +54,30 @@ __device__ __forceinline__ void box_stage(float (&v)[L]) {
     }
 }
 
-// Applies box_stage<L, r> for a wave-uniform run-time r (held in an SGPR).
-//
-// box_tree: binary search over the instantiations, five uniform two-way
-// branches per call.  Its joins merge the line from both sides, which costs
-// register copies where a caller keeps much other state live.
-template <int L, int LO, int HI, bool COMP>
-__device__ __forceinline__ void box_tree(float (&v)[L], int r) {
-    if constexpr (LO == HI) {
-        if constexpr (2 * LO < L) box_stage<L, LO, COMP>(v);
-    } else {
-        constexpr int MID = (LO + HI) / 2;
-        if (r <= MID)
-            box_tree<L, LO, MID, COMP>(v, r);
-        else
-            box_tree<L, MID + 1, HI, COMP>(v, r);
-    }
-}
-
-// box_chain: the candidates one after another, each in its own block; the
-// empty asm makes r opaque between blocks, so the compiler cannot fold the
-// chain into one multi-way branch, and every join is two-way with the line
-// in place.  Costs a taken branch per candidate below r.
+// Applies box_stage<L, r> for a wave-uniform run-time r (held in an SGPR):
+// the candidates one after another, each in its own block.  The empty asm
+// makes r opaque between blocks, so the compiler cannot fold the chain into
+// one multi-way branch (whose join would merge the line from 32 paths, with
+// register copies and spills where the caller keeps much other state live),
+// and every join is two-way with the line in place.  Each stage body is
+// marked unlikely, so it is laid out away from the chain of tests: a
+// candidate below r costs a test and a branch not taken, not a jump over the
+// whole stage.  (A binary search over the candidates, measured against this,
+// spilled heavily in the tile kernels; the chain with the bodies in line cost
+// about 1100 cycles per dispatch at r = 9, this layout about 650.)
 template <int L, int R, int RE, bool COMP>
 __device__ __forceinline__ void box_chain(float (&v)[L], int r) {
     if constexpr (R <= RE && 2 * R < L) {
-        if (r == R) box_stage<L, R, COMP>(v);
+        if (__builtin_expect(r == R, 0)) box_stage<L, R, COMP>(v);
         asm volatile("" : "+s"(r));
         box_chain<L, R + 1, RE, COMP>(v, r);
     }
 }
 
-template <int L, bool TREE, bool COMP = false>
+template <int L, bool COMP = false>
 __device__ __forceinline__ void box_dispatch(float (&v)[L], int r) {
     r = __builtin_amdgcn_readfirstlane(r);
-    if constexpr (TREE)
-        box_tree<L, 0, kBoxMaxRadius, COMP>(v, r);
-    else
-        box_chain<L, 0, kBoxMaxRadius, COMP>(v, r);
+    box_chain<L, 0, kBoxMaxRadius, COMP>(v, r);
 }
 
 }  // namespace bf

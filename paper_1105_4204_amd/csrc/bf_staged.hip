@@ -112,7 +112,7 @@ bf_stage_v(const StageArgs a) {
             }
             v[y] = in ? val : 0.0f;
         }
-        for (int b = 0; b < a.nb; ++b) box_dispatch<kStLine, false, true>(v, a.r[b]);
+        for (int b = 0; b < a.nb; ++b) box_dispatch<kStLine, true>(v, a.r[b]);
 #pragma unroll
         for (int y0c = 0; y0c < kStOutV; y0c += kChunk) {
             if (y0c < a.nout_v) {
@@ -186,7 +186,7 @@ bf_stage_h(const StageArgs a) {
                 v[x] = in ? val : 0.0f;
             }
         }
-        for (int b = 0; b < a.nb; ++b) box_dispatch<kStLine, false, true>(v, a.r[b]);
+        for (int b = 0; b < a.nb; ++b) box_dispatch<kStLine, true>(v, a.r[b]);
 #pragma unroll
         for (int k = 0; k < kStOutH; ++k) {
             float w = a.c * v[k];

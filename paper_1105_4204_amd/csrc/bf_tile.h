@@ -307,7 +307,7 @@ __device__ __forceinline__ void row_role(const TileArgs& a, const TileCtx& c) {
 #pragma unroll
                 for (int x = 0; x < kLine; ++x) v[x] *= A1[x];
             }
-            for (int b = 0; b < a.nb; ++b) box_dispatch<kLine, MODE == kForward>(v, a.r[b]);
+            for (int b = 0; b < a.nb; ++b) box_dispatch<kLine>(v, a.r[b]);
             float* dst = c.Tb + (s & 1) * c.tfl + i;
 #pragma unroll
             for (int j0c = 0; j0c < kOutMax; j0c += kChunk) {
@@ -396,7 +396,7 @@ __device__ __forceinline__ void col_role(const TileArgs& a, const TileCtx& c, in
                 }
             }
             load_line(v, c.Tb + ((s - 1) & 1) * c.tfl + j * c.EHp);
-            for (int b = 0; b < a.nb; ++b) box_dispatch<kLine, MODE == kForward>(v, a.r[b]);
+            for (int b = 0; b < a.nb; ++b) box_dispatch<kLine>(v, a.r[b]);
             const float cq = a.chat[q];
             const float m = (float)(a.odd + 2 * q);
             // accumulate over the output rows k < TH; the channel picks the
