@@ -286,24 +286,37 @@ __device__ __forceinline__ void row_role(const TileArgs& a, const TileCtx& c) {
     int q = 0, ch = 0;    // pair and channel of step s
     for (int s = 0; s <= a.nsteps; ++s) {
         if (s < a.nsteps && act) {
-            if (ch == 0 && q > 0) {
+            // The blocks that a step may or may not run are marked unlikely
+            // and separated by opaque copies of ch, so each is laid out out of
+            // line and a step that skips it pays a branch not taken (as in
+            // the radius dispatch, bf_box.h).
+            int cs = ch;
+            if (__builtin_expect(cs == 0 && q > 0, 0)) {
                 if (GG)
                     load_g_row(a, c.ei0, c.ej0, i, v);
                 else
                     load_line(v, c.gpl + i * c.EWp);
                 phase_step<kLine>(A0, A1, v, 0, a.two_alpha);
             }
-            if (ch & 1) load_line(v, mulpl + i * c.EWp);
-            if (ch == 0) {
+            asm volatile("" : "+s"(cs));
+            if (__builtin_expect(cs == 0, 0)) {
 #pragma unroll
                 for (int x = 0; x < kLine; ++x) v[x] = A0[x];
-            } else if (ch == 1) {
+            }
+            asm volatile("" : "+s"(cs));
+            if (__builtin_expect(cs == 1, 0)) {
+                load_line(v, mulpl + i * c.EWp);
 #pragma unroll
                 for (int x = 0; x < kLine; ++x) v[x] *= A0[x];
-            } else if (ch == 2) {
+            }
+            asm volatile("" : "+s"(cs));
+            if (__builtin_expect(cs == 2, 0)) {
 #pragma unroll
                 for (int x = 0; x < kLine; ++x) v[x] = A1[x];
-            } else {
+            }
+            asm volatile("" : "+s"(cs));
+            if (__builtin_expect(cs == 3, 0)) {
+                load_line(v, mulpl + i * c.EWp);
 #pragma unroll
                 for (int x = 0; x < kLine; ++x) v[x] *= A1[x];
             }
@@ -387,7 +400,7 @@ __device__ __forceinline__ void col_role(const TileArgs& a, const TileCtx& c, in
     int q = 0, ch = 0;    // pair and channel of step s - 1
     for (int s = 0; s <= a.nsteps; ++s) {
         if (s > 0 && (ch & 1) == (c.wave - 2) && act) {
-            if ((ch >> 1) == 0 && q > 0) {
+            if (__builtin_expect((ch >> 1) == 0 && q > 0, 0)) {   // out of line
                 if (MODE == kBackward) {          // g kept in the A0 tail
                     phase_step<kOutMax>(A0, A1, A0, kOutMax, a.two_alpha);
                 } else {
@@ -413,28 +426,35 @@ __device__ __forceinline__ void col_role(const TileArgs& a, const TileCtx& c, in
                     }
                 }
             };
+            // one out-of-line block per channel, as in the row role
+            int cs = ch;
             if (MODE == kForward) {
                 const float cm = cq * m;
-                if (ch < 2) {   // C F[.] into den|num; -m S F[.] into Q|P
+                if (__builtin_expect(cs < 2, 0)) {   // C F[.] into den|num; -m S F[.] into Q|P
                     accumulate([&](int k) { return cq * A0[k]; }, A0);
                     if (AUX) accumulate([&](int k) { return -cm * A1[k]; }, A1);
-                } else {        // S F[.] into den|num; m C F[.] into Q|P
+                }
+                asm volatile("" : "+s"(cs));
+                if (__builtin_expect(cs >= 2, 0)) {  // S F[.] into den|num; m C F[.] into Q|P
                     accumulate([&](int k) { return cq * A1[k]; }, A0);
                     if (AUX) accumulate([&](int k) { return cm * A0[k]; }, A1);
                 }
             } else {
                 const float cma = cq * m * a.alpha_f;
-                if (ch == 0)        // A C: c (C - ma g S)
+                if (__builtin_expect(cs == 0, 0))   // A C: c (C - ma g S)
                     accumulate(
                         [&](int k) { return fmaf(-cma * A0[kOutMax + k], A1[k], cq * A0[k]); },
                         A1);
-                else if (ch == 2)   // A S: c (S + ma g C)
+                asm volatile("" : "+s"(cs));
+                if (__builtin_expect(cs == 2, 0))   // A S: c (S + ma g C)
                     accumulate(
                         [&](int k) { return fmaf(cma * A0[kOutMax + k], A0[k], cq * A1[k]); },
                         A1);
-                else if (ch == 1)   // B C: c ma S
+                asm volatile("" : "+s"(cs));
+                if (__builtin_expect(cs == 1, 0))   // B C: c ma S
                     accumulate([&](int k) { return cma * A1[k]; }, A1);
-                else                // B S: -c ma C
+                asm volatile("" : "+s"(cs));
+                if (__builtin_expect(cs == 3, 0))   // B S: -c ma C
                     accumulate([&](int k) { return -cma * A0[k]; }, A1);
             }
         }
