@@ -162,12 +162,12 @@ __device__ __forceinline__ void load_g_row(const TileArgs& a, int ei0, int ej0, 
     }
 }
 
-// (zr + j zi)[x] *= exp(j step g[x]) for x < n.
-template <int n, int L>
+// (zr + j zi)[x] *= exp(j step g[goff + x]) for x0 <= x < x1.
+template <int x0, int x1, int L>
 __device__ __forceinline__ void phase_step(float (&zr)[L], float (&zi)[L], const float (&g)[kLine],
                                            int goff, float step) {
 #pragma unroll
-    for (int x = 0; x < n; ++x) {
+    for (int x = x0; x < x1; ++x) {
         float cu, su;
         cis_small(step * g[goff + x], cu, su);
         const float nr = zr[x] * cu - zi[x] * su;
@@ -291,12 +291,12 @@ __device__ __forceinline__ void row_role(const TileArgs& a, const TileCtx& c) {
             // line and a step that skips it pays a branch not taken (as in
             // the radius dispatch, bf_box.h).
             int cs = ch;
-            if (__builtin_expect(cs == 0 && q > 0, 0)) {
+            if (__builtin_expect(cs == 0 && q > 0, 0)) {   // second half of the phase step
                 if (GG)
                     load_g_row(a, c.ei0, c.ej0, i, v);
                 else
                     load_line(v, c.gpl + i * c.EWp);
-                phase_step<kLine>(A0, A1, v, 0, a.two_alpha);
+                phase_step<kLine / 2, kLine>(A0, A1, v, 0, a.two_alpha);
             }
             asm volatile("" : "+s"(cs));
             if (__builtin_expect(cs == 0, 0)) {
@@ -328,6 +328,19 @@ __device__ __forceinline__ void row_role(const TileArgs& a, const TileCtx& c) {
 #pragma unroll
                     for (int jj = 0; jj < kChunk; ++jj) dst[(j0c + jj) * c.EHp] = v[j0c + jj];
                 }
+            }
+            // After the last channel of a pair Z is free: the first half of
+            // the next pair's phase step goes here, the second half into the
+            // next step, so that no single step carries all of it.
+            asm volatile("" : "+s"(cs));
+            if (__builtin_expect(cs == pair_channels<MODE>(q == 0 && !a.odd) - 1 &&
+                                     q + 1 < a.npairs,
+                                 0)) {
+                if (GG)
+                    load_g_row(a, c.ei0, c.ej0, i, v);
+                else
+                    load_line(v, c.gpl + i * c.EWp);
+                phase_step<0, kLine / 2>(A0, A1, v, 0, a.two_alpha);
             }
         }
         __syncthreads();
@@ -399,15 +412,21 @@ __device__ __forceinline__ void col_role(const TileArgs& a, const TileCtx& c, in
     }
     int q = 0, ch = 0;    // pair and channel of step s - 1
     for (int s = 0; s <= a.nsteps; ++s) {
-        if (s > 0 && (ch & 1) == (c.wave - 2) && act) {
-            if (__builtin_expect((ch >> 1) == 0 && q > 0, 0)) {   // out of line
-                if (MODE == kBackward) {          // g kept in the A0 tail
-                    phase_step<kOutMax>(A0, A1, A0, kOutMax, a.two_alpha);
-                } else {
-                    load_gcol();
-                    phase_step<kOutMax>(A0, A1, v, 0, a.two_alpha);
-                }
+        // The phase step of a column wave falls into a step in which the
+        // other wave filters: wave 3 advances to pair q during channel 0 of
+        // pair q, wave 2 to pair q + 1 at the end of the last channel of
+        // pair q (an idle step for it, except in the one-channel centre pair
+        // of the adjoint, where it follows the wave's own accumulation).
+        auto col_phase = [&]() {
+            if (MODE == kBackward) {          // g kept in the A0 tail
+                phase_step<0, kOutMax>(A0, A1, A0, kOutMax, a.two_alpha);
+            } else {
+                load_gcol();
+                phase_step<0, kOutMax>(A0, A1, v, 0, a.two_alpha);
             }
+        };
+        if (__builtin_expect(s > 0 && c.wave == 3 && ch == 0 && q > 0 && act, 0)) col_phase();
+        if (s > 0 && (ch & 1) == (c.wave - 2) && act) {
             load_line(v, c.Tb + ((s - 1) & 1) * c.tfl + j * c.EHp);
             for (int b = 0; b < a.nb; ++b) box_dispatch<kLine>(v, a.r[b]);
             const float cq = a.chat[q];
@@ -458,6 +477,10 @@ __device__ __forceinline__ void col_role(const TileArgs& a, const TileCtx& c, in
                     accumulate([&](int k) { return -cma * A0[k]; }, A1);
             }
         }
+        if (__builtin_expect(s > 0 && c.wave == 2 && act && q + 1 < a.npairs &&
+                                 ch == pair_channels<MODE>(q == 0 && !a.odd) - 1,
+                             0))
+            col_phase();
         __syncthreads();
         if (s > 0 && ++ch == pair_channels<MODE>(q == 0 && !a.odd)) {
             ch = 0;
