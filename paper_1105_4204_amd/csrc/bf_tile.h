@@ -75,18 +75,19 @@ __host__ __device__ constexpr int tile_pitch(int n) { return ((n + 3) / 8) * 8 +
 __host__ __device__ inline int tile_round(int n) { return (n + kChunk - 1) / kChunk * kChunk; }
 __host__ __device__ inline int tile_plane_floats(int EH, int EWp) { return EH * EWp + kPad; }
 __host__ __device__ inline int tile_t_floats(int TW, int EHp) { return tile_round(TW) * EHp + kPad; }
-// Forward only: g at the output pixels, transposed (column j at j * kGtPitch).
+// Forward and GG adjoint: g at the output pixels, transposed (column j at j * kGtPitch).
 constexpr int kGtPitch = tile_pitch(kOutMax);
 constexpr int kGtFloats = kOutMax * kGtPitch;
 // LDS layout (floats): forward gplane | T0 | T1 | gT; adjoint gplane | hplane
 // | T0 | T1, or with GG (g read from global memory, where the tile's rows stay
-// in L2) hplane | T0 | T1, so that a 64 x 64 adjoint tile fits.
+// in L2) hplane | T0 | T1 | gT, so that a 64 x 64 adjoint tile fits.
 __host__ __device__ inline size_t tile_lds_floats(int mode, int TH, int TW, int R,
                                                   bool gg = false) {
     const int EH = TH + 2 * R, EW = TW + 2 * R;
     const int planes = (mode == kBackward && !gg) ? 2 : 1;
     return (size_t)planes * tile_plane_floats(EH, tile_pitch(EW)) +
-           2 * (size_t)tile_t_floats(TW, tile_pitch(EH)) + (mode == kForward ? kGtFloats : 0);
+           2 * (size_t)tile_t_floats(TW, tile_pitch(EH)) +
+           ((mode == kForward || gg) ? kGtFloats : 0);
 }
 
 // exp(j x) for |x| <= pi/2: cos x = 1 + x^2 P(x^2), sin x = x + x^3 Q(x^2)
@@ -193,7 +194,7 @@ struct TileCtx {
     float* gpl;               // forward: g = f - T/2 on the extended tile
     float* hpl;               // adjoint: A, then h = out - T/2
     float* Tb;                // T0 | T1: row results, transposed
-    float* gT;                // forward: g at the output pixels, column-major
+    float* gT;                // forward, GG adjoint: g at the output pixels, column-major
 };
 
 // Cooperative fill of an extended-tile plane (pitch gaps and pad zero):
@@ -354,41 +355,35 @@ __device__ __forceinline__ void row_role(const TileArgs& a, const TileCtx& c) {
 
 // Column role (waves 2-3): lane j owns output column j.  State: A0[0..64) +
 // j A1[0..64) = Z at the column's outputs; tails: forward den|num (A0) and
-// Q|P (A1) on wave 2|3; adjoint g at the outputs (A0) and the partial sum
-// (A1).  Wave 2 filters the channels with even index, wave 3 the odd ones.
+// Q|P (A1) on wave 2|3; adjoint the partial sum (A1).  g at the outputs is
+// read from LDS where it is needed.  Wave 2 filters the channels with even
+// index, wave 3 the odd ones.
 template <int MODE, bool AUX, bool GG>
 __device__ __forceinline__ void col_role(const TileArgs& a, const TileCtx& c, int tile_id) {
     const int j = c.lane;
     const bool act = j < c.TW;
     const int TH = c.TH;
     float A0[kLine], A1[kLine], v[kLine];
-    // v[0..kOutMax) <- g at the output pixels of column j (rows past TH: 0 or a repeat)
-    auto load_gcol = [&]() {
-        if (MODE == kForward) {
+    // dst[0..kOutMax) <- g at the output pixels of column j (rows past TH: 0 or a repeat)
+    auto load_gcol = [&](auto& dst) {
+        if (MODE == kForward || GG) {
             const float4* s4 = reinterpret_cast<const float4*>(c.gT + j * kGtPitch);
 #pragma unroll
             for (int k = 0; k < kOutMax / 4; ++k) {
                 const float4 q4 = s4[k];
-                v[4 * k] = q4.x;
-                v[4 * k + 1] = q4.y;
-                v[4 * k + 2] = q4.z;
-                v[4 * k + 3] = q4.w;
-            }
-        } else if (GG) {   // adjoint, g from global memory; rows past TH repeat the last
-            const int gj = min(c.j0 + j, a.W - 1);
-#pragma unroll
-            for (int k = 0; k < kOutMax; ++k) {
-                const int gi = min(c.i0 + min(k, TH - 1), a.H - 1);
-                v[k] = a.f[(size_t)gi * a.W + gj] - a.center;
+                dst[4 * k] = q4.x;
+                dst[4 * k + 1] = q4.y;
+                dst[4 * k + 2] = q4.z;
+                dst[4 * k + 3] = q4.w;
             }
         } else {
             const float* gcol = c.gpl + c.R * c.EWp + c.R + j;
 #pragma unroll
-            for (int k = 0; k < kOutMax; ++k) v[k] = gcol[min(k, TH - 1) * c.EWp];
+            for (int k = 0; k < kOutMax; ++k) dst[k] = gcol[min(k, TH - 1) * c.EWp];
         }
     };
     if (act) {
-        load_gcol();
+        load_gcol(v);
         if (a.odd) {
 #pragma unroll
             for (int k = 0; k < kOutMax; ++k) cis_small(a.alpha_f * v[k], A0[k], A1[k]);
@@ -401,7 +396,7 @@ __device__ __forceinline__ void col_role(const TileArgs& a, const TileCtx& c, in
         }
 #pragma unroll
         for (int k = 0; k < kOutMax; ++k) {
-            A0[kOutMax + k] = (MODE == kBackward) ? v[k] : 0.0f;
+            A0[kOutMax + k] = 0.0f;
             A1[kOutMax + k] = 0.0f;
         }
     }
@@ -418,14 +413,9 @@ __device__ __forceinline__ void col_role(const TileArgs& a, const TileCtx& c, in
         // pair q (an idle step for it, except in the one-channel centre pair
         // of the adjoint, where it follows the wave's own accumulation).
         auto col_phase = [&]() {
-            if (MODE == kBackward) {          // g kept in the A0 tail
-                phase_step<0, kOutMax>(A0, A1, A0, kOutMax, a.two_alpha);
-            } else {
-                load_gcol();
-                phase_step<0, kOutMax>(A0, A1, v, 0, a.two_alpha);
-            }
+            load_gcol(v);
+            phase_step<0, kOutMax>(A0, A1, v, 0, a.two_alpha);
         };
-        if (__builtin_expect(s > 0 && c.wave == 3 && ch == 0 && q > 0 && act, 0)) col_phase();
         if (s > 0 && (ch & 1) == (c.wave - 2) && act) {
             load_line(v, c.Tb + ((s - 1) & 1) * c.tfl + j * c.EHp);
             for (int b = 0; b < a.nb; ++b) box_dispatch<kLine>(v, a.r[b]);
@@ -460,15 +450,16 @@ __device__ __forceinline__ void col_role(const TileArgs& a, const TileCtx& c, in
                 }
             } else {
                 const float cma = cq * m * a.alpha_f;
-                if (__builtin_expect(cs == 0, 0))   // A C: c (C - ma g S)
-                    accumulate(
-                        [&](int k) { return fmaf(-cma * A0[kOutMax + k], A1[k], cq * A0[k]); },
-                        A1);
+                float gk[kOutMax];
+                if (__builtin_expect(cs == 0, 0)) {   // A C: c (C - ma g S)
+                    load_gcol(gk);
+                    accumulate([&](int k) { return fmaf(-cma * gk[k], A1[k], cq * A0[k]); }, A1);
+                }
                 asm volatile("" : "+s"(cs));
-                if (__builtin_expect(cs == 2, 0))   // A S: c (S + ma g C)
-                    accumulate(
-                        [&](int k) { return fmaf(cma * A0[kOutMax + k], A0[k], cq * A1[k]); },
-                        A1);
+                if (__builtin_expect(cs == 2, 0)) {   // A S: c (S + ma g C)
+                    load_gcol(gk);
+                    accumulate([&](int k) { return fmaf(cma * gk[k], A0[k], cq * A1[k]); }, A1);
+                }
                 asm volatile("" : "+s"(cs));
                 if (__builtin_expect(cs == 1, 0))   // B C: c ma S
                     accumulate([&](int k) { return cma * A1[k]; }, A1);
@@ -477,10 +468,11 @@ __device__ __forceinline__ void col_role(const TileArgs& a, const TileCtx& c, in
                     accumulate([&](int k) { return -cma * A0[k]; }, A1);
             }
         }
-        if (__builtin_expect(s > 0 && c.wave == 2 && act && q + 1 < a.npairs &&
-                                 ch == pair_channels<MODE>(q == 0 && !a.odd) - 1,
-                             0))
-            col_phase();
+        // one call site for both waves (wave 3 is idle in this step either way)
+        const bool adv3 = c.wave == 3 && ch == 0 && q > 0;
+        const bool adv2 = c.wave == 2 && q + 1 < a.npairs &&
+                          ch == pair_channels<MODE>(q == 0 && !a.odd) - 1;
+        if (__builtin_expect(s > 0 && act && (adv2 || adv3), 0)) col_phase();
         __syncthreads();
         if (s > 0 && ++ch == pair_channels<MODE>(q == 0 && !a.odd)) {
             ch = 0;
@@ -617,11 +609,18 @@ __device__ __forceinline__ void tile_body(const TileArgs& a, int tile_id, float*
         });
     }
     __syncthreads();
-    if (MODE == kForward) {
+    if (MODE == kForward || GG) {
         // output columns, contiguous, for the column lanes' 16-byte loads
         for (int p = c.t; p < kGtFloats; p += kTileThreads) {
             const int jj = p / kGtPitch, k = p - jj * kGtPitch;
-            c.gT[p] = (jj < a.TW && k < a.TH) ? c.gpl[(k + a.R) * a.EWp + a.R + jj] : 0.0f;
+            const bool in = jj < a.TW && k < a.TH;
+            if (GG) {   // from global memory: clamped load, zero outside the image
+                const int gi = c.i0 + k, gj = c.j0 + jj;
+                const float fv = a.f[(size_t)min(gi, a.H - 1) * a.W + min(gj, a.W - 1)];
+                c.gT[p] = (in && gi < a.H && gj < a.W) ? fv - a.center : 0.0f;
+            } else {
+                c.gT[p] = in ? c.gpl[(k + a.R) * a.EWp + a.R + jj] : 0.0f;
+            }
         }
         __syncthreads();
     }
