@@ -292,13 +292,10 @@ __device__ __forceinline__ void row_role(const TileArgs& a, const TileCtx& c) {
             // line and a step that skips it pays a branch not taken (as in
             // the radius dispatch, bf_box.h).
             int cs = ch;
-            if (__builtin_expect(cs == 0 && q > 0, 0)) {   // second half of the phase step
-                if (GG)
-                    load_g_row(a, c.ei0, c.ej0, i, v);
-                else
-                    load_line(v, c.gpl + i * c.EWp);
+            // second half of the phase step: the previous step (the last
+            // channel of pair q - 1) left g in v, below
+            if (__builtin_expect(cs == 0 && q > 0, 0))
                 phase_step<kLine / 2, kLine>(A0, A1, v, 0, a.two_alpha);
-            }
             asm volatile("" : "+s"(cs));
             if (__builtin_expect(cs == 0, 0)) {
 #pragma unroll
@@ -332,7 +329,8 @@ __device__ __forceinline__ void row_role(const TileArgs& a, const TileCtx& c) {
             }
             // After the last channel of a pair Z is free: the first half of
             // the next pair's phase step goes here, the second half into the
-            // next step, so that no single step carries all of it.
+            // next step, so that no single step carries all of it; g stays in
+            // v for that second half.
             asm volatile("" : "+s"(cs));
             if (__builtin_expect(cs == pair_channels<MODE>(q == 0 && !a.odd) - 1 &&
                                      q + 1 < a.npairs,
