@@ -34,6 +34,7 @@ constexpr int kStOutV = 88;       // vertical pass: outputs per line, at most
 constexpr int kStRows = 64;       // horizontal pass: rows per workgroup
 constexpr int kStOutH = 64;       // horizontal pass: outputs per line, at most
 constexpr int kStPitch = kStCols + 1;
+static_assert(kStOutH % 4 == 0, "the four waves share the output columns");
 
 struct StageArgs {
     const float* f;
@@ -173,18 +174,28 @@ bf_stage_h(const StageArgs a) {
     const int ch = wave;
     if (ch < nch) {
         float v[kStLine];
-        const float* src = a.vt + (size_t)ch * HW;
+        // 4-byte buffer loads: the lane's row is the vector offset, the
+        // (wave-uniform) column the scalar offset, from a resource based at
+        // the first in-image column of the line and sized to the line's
+        // columns, so that every offset stays far below 2^31 and no load
+        // needs address registers.  Columns outside the image read a clamped
+        // column and are zeroed by a uniform select; rows past H read row
+        // H - 1, and their results are never stored.
+        const int Hs = __builtin_amdgcn_readfirstlane(a.H);
+        const int Ws = __builtin_amdgcn_readfirstlane(a.W);
+        const int e0 = __builtin_amdgcn_readfirstlane(ex0);
+        const int xlo = max(e0, 0), xhi = min(e0 + kStLine, Ws);   // in-image columns [xlo, xhi)
+        const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+            const_cast<float*>(a.vt + (size_t)ch * HW + (size_t)xlo * Hs), 0,
+            (xhi - xlo) * Hs * (int)sizeof(float), kBufferWord3);
+        const int voff = yc * (int)sizeof(float);
 #pragma unroll
-        for (int x0c = 0; x0c < kStLine; x0c += 4 * kChunk) {
-            asm volatile("" ::: "memory");
-#pragma unroll
-            for (int x = x0c; x < x0c + 4 * kChunk; ++x) {
-                const int gx = ex0 + x;
-                const bool in = y < a.H && gx >= 0 && gx < a.W;
-                const int gxc = min(max(gx, 0), a.W - 1);
-                const float val = src[(unsigned)(gxc * a.H + yc)];
-                v[x] = in ? val : 0.0f;
-            }
+        for (int x = 0; x < kStLine; ++x) {
+            const int gx = e0 + x;
+            const int col = min(max(gx, xlo), xhi - 1) - xlo;
+            const float val = __uint_as_float(
+                __builtin_amdgcn_raw_buffer_load_b32(rs, voff, col * Hs * (int)sizeof(float), 0));
+            v[x] = (gx >= 0 && gx < Ws) ? val : 0.0f;
         }
         for (int b = 0; b < a.nb; ++b) box_dispatch<kStLine, true>(v, a.r[b]);
 #pragma unroll
@@ -199,16 +210,28 @@ bf_stage_h(const StageArgs a) {
         }
     }
     __syncthreads();
-    // fixed-order sums: den = (C F[C] + S F[S]), num = (C F[gC] + S F[gS])
-    if (wave == 0 && y < a.H) {
-#pragma unroll 8
-        for (int k = 0; k < kStOutH; ++k) {
+    // fixed-order sums: den = (C F[C] + S F[S]), num = (C F[gC] + S F[gS]);
+    // wave w updates the output columns 16 w .. 16 w + 15 of its rows, the
+    // loads of all 16 first (clamped, unconditional), then the stores
+    if (y < a.H) {
+        constexpr int kPer = kStOutH / 4;
+        float d16[kPer], n16[kPer];
+#pragma unroll
+        for (int u = 0; u < kPer; ++u) {
+            const int k = wave * kPer + u;
+            const size_t idx = (size_t)min(x0 + k, a.W - 1) * a.H + y;
+            d16[u] = a.den_t[idx];
+            n16[u] = a.num_t[idx];
+        }
+#pragma unroll
+        for (int u = 0; u < kPer; ++u) {
+            const int k = wave * kPer + u;
             const int X = x0 + k;
             if (k < a.nout_h && X < a.W) {
                 const float d = a.centre ? red[0][k][lane] : red[0][k][lane] + red[2][k][lane];
                 const float n = a.centre ? red[1][k][lane] : red[1][k][lane] + red[3][k][lane];
-                a.den_t[(size_t)X * a.H + y] += d;
-                a.num_t[(size_t)X * a.H + y] += n;
+                a.den_t[(size_t)X * a.H + y] = d16[u] + d;
+                a.num_t[(size_t)X * a.H + y] = n16[u] + n;
             }
         }
     }
