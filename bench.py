@@ -197,6 +197,42 @@ def sigma_s_sweep(f, T, sr, sigmas=(2.0, 4.0, 6.0, 10.0, 16.0, 20.0, 30.0),
     return res
 
 
+def wide_config_bench(reps=2):
+    """The wide-kernel, many-term workload: 4096x4096 (same generator, seed
+    3), sigma_s = 30 as boxes (29, 29, 30), sigma_r = 10 (N = 264), forward
+    only, through the staged path; in full and with term truncation at 1e-2
+    gray (pairs kept and the error bound reported)."""
+    import torch
+
+    from paper_1105_4204_amd import _native, ops, synth
+    f = torch.from_numpy(synth.config_image(3)).to("cuda:0")
+    H, W = f.shape
+    radii = _native.spatial_gaussian(30.0, 3)
+    sr, T = 10.0, 255.0
+    N = _native.range_degree(T, sr)
+    res = {"workload": "4096x4096 f32 piecewise-smooth, sigma_s=30 as 3 boxes "
+                       f"{tuple(radii)}, T=255, sigma_r=10, N={N}, forward",
+           "path": "staged" if _native.workspace_bytes(H, W, radii) else "fused",
+           "pairs": len(_native.range_coeffs(N)),
+           "nonzero_pairs": sum(1 for c in _native.range_coeffs(N) if c != 0.0)}
+    for key, tol in (("full", 0.0), ("trunc_1e-2", 1e-2)):
+        ops.trig_forward(f, T, sr, radii, trunc_tol=tol)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            ops.trig_forward(f, T, sr, radii, trunc_tol=tol)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        row = {"fwd_ms": round(ms, 2), "fwd_mpix_s": round(H * W / 1e6 / (ms / 1e3), 1)}
+        if tol > 0:
+            q, bound = _native.range_truncate(N, T, radii, tol)
+            row.update({"pairs_kept": q, "error_bound_gray": bound})
+        res[key] = row
+    return res
+
+
 def yvv_bytes_per_pixel(npairs: int) -> int:
     """Algorithmic HBM bytes per pixel of the recursive-Gaussian forward.
 
@@ -283,9 +319,12 @@ def main():
     ap.add_argument("--no-direct", action="store_true")
     ap.add_argument("--fwd-only", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
-    ap.add_argument("--no-sweep", action="store_true", help="skip the sigma_s sweep")
+    ap.add_argument("--no-sweep", action="store_true",
+                    help="skip the sigma_s sweep (and the wide-kernel configuration)")
     ap.add_argument("--no-other", action="store_true",
                     help="skip the recursive-Gaussian and space-variant timings")
+    ap.add_argument("--no-wide", action="store_true",
+                    help="skip the 4096x4096, sigma_s=30, N=264 forward")
     ap.add_argument("--only-other", action="store_true",
                     help="only time the recursive-Gaussian and space-variant paths (for "
                          "counter runs); prints their JSON and exits")
@@ -449,6 +488,10 @@ def main():
     if not args.no_other and args.workload == "config2":
         other = other_spatial_kernels(f, T, sr)
 
+    wide = None
+    if not args.no_wide and not args.no_sweep and args.workload == "config2":
+        wide = wide_config_bench()
+
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(f_np, sr, N, radii)
@@ -479,6 +522,7 @@ def main():
         "batch": batch_res,
         "sigma_s_sweep": sweep,
         "other_spatial_kernels": other,
+        "wide_kernel_config": wide,
         "cpu_baseline": cpu,
         "wall_s_timed": round(wall, 3),
     }

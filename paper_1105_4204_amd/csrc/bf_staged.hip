@@ -97,21 +97,28 @@ bf_stage_v(const StageArgs a) {
     if (ch < nch) {
         const int x = x0 + lane;
         float v[kStLine];
+        // two loops rather than a test of the (uniform) centre flag per
+        // sample, so that the LDS reads of g are not each followed by a
+        // branch and a wait of their own
+        if (a.centre) {
 #pragma unroll
-        for (int y = 0; y < kStLine; ++y) {
-            const int gy = ey0 + y;
-            const bool in = x < a.W && gy >= 0 && gy < a.H;
-            const float g = gtile[y * kStCols + lane];
-            float val;
-            if (a.centre) {
-                val = (ch == 0) ? 1.0f : g;
-            } else {
+            for (int y = 0; y < kStLine; ++y) {
+                const int gy = ey0 + y;
+                const bool in = x < a.W && gy >= 0 && gy < a.H;
+                const float g = gtile[y * kStCols + lane];
+                v[y] = in ? ((ch == 0) ? 1.0f : g) : 0.0f;
+            }
+        } else {
+#pragma unroll
+            for (int y = 0; y < kStLine; ++y) {
+                const int gy = ey0 + y;
+                const bool in = x < a.W && gy >= 0 && gy < a.H;
+                const float g = gtile[y * kStCols + lane];
                 float cc, ss;
                 cis_direct(a.malpha, g, cc, ss);
                 const float base = (ch >= 2) ? ss : cc;
-                val = (ch & 1) ? g * base : base;
+                v[y] = in ? ((ch & 1) ? g * base : base) : 0.0f;
             }
-            v[y] = in ? val : 0.0f;
         }
         for (int b = 0; b < a.nb; ++b) box_dispatch<kStLine, true>(v, a.r[b]);
 #pragma unroll
@@ -124,14 +131,17 @@ bf_stage_v(const StageArgs a) {
         }
     }
     __syncthreads();
-    // transposed, coalesced writes: consecutive threads, consecutive rows of one column
+    // transposed, coalesced writes: wave w writes columns w, w + 4, ..., its
+    // lanes consecutive rows of one column
     for (int c2 = 0; c2 < nch; ++c2) {
         const float* src = tr + (size_t)c2 * a.nout_v * kStPitch;
         float* dst = a.vt + (size_t)c2 * HW;
-        for (int p = t; p < kStCols * a.nout_v; p += kStThreads) {
-            const int xl = p / a.nout_v, yl = p - xl * a.nout_v;
-            const int X = x0 + xl, Y = y0 + yl;
-            if (X < a.W && Y < a.H) dst[(size_t)X * a.H + Y] = src[yl * kStPitch + xl];
+        for (int xl = wave; xl < kStCols; xl += kStThreads / 64) {
+            const int X = x0 + xl;
+            for (int yl = lane; yl < a.nout_v; yl += 64) {
+                const int Y = y0 + yl;
+                if (X < a.W && Y < a.H) dst[(size_t)X * a.H + Y] = src[yl * kStPitch + xl];
+            }
         }
     }
 }
@@ -198,15 +208,16 @@ bf_stage_h(const StageArgs a) {
             v[x] = (gx >= 0 && gx < Ws) ? val : 0.0f;
         }
         for (int b = 0; b < a.nb; ++b) box_dispatch<kStLine, true>(v, a.r[b]);
+        if (a.centre) {
 #pragma unroll
-        for (int k = 0; k < kStOutH; ++k) {
-            float w = a.c * v[k];
-            if (!a.centre) {
+            for (int k = 0; k < kStOutH; ++k) red[ch][k][lane] = a.c * v[k];
+        } else {
+#pragma unroll
+            for (int k = 0; k < kStOutH; ++k) {
                 float cc, ss;
                 cis_direct(a.malpha, gt[lane][k], cc, ss);
-                w *= (ch >= 2) ? ss : cc;
+                red[ch][k][lane] = a.c * v[k] * ((ch >= 2) ? ss : cc);
             }
-            red[ch][k][lane] = w;
         }
     }
     __syncthreads();

@@ -118,7 +118,7 @@ __device__ __forceinline__ void cis_direct(double malpha, float g, float& c, flo
     const float x = (float)fma(-n, 1.57079632679489661923, th);  // pi/2
     float cx, sx;
     cis_small(x, cx, sx);
-    const int q = ((int)(long long)n) & 3;
+    const int q = ((int)n) & 3;   // |n| stays far below 2^31 for any phase used here
     c = q == 0 ? cx : q == 1 ? -sx : q == 2 ? -cx : sx;
     s = q == 0 ? sx : q == 1 ? cx : q == 2 ? -sx : -cx;
 }
