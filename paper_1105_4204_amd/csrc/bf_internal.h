@@ -61,6 +61,7 @@ struct TileGeom {
     int tiles_x, tiles_y;
     size_t lds_bytes;
     bool gg;          // adjoint: g read from global memory (one LDS plane)
+    int line;         // register line length of the single-image kernels (120 or 128)
 };
 
 bf_status plan_fwd_tiles(int64_t H, int64_t W, const SpatialParams& sp, int req_h, int req_w,

@@ -43,7 +43,9 @@ enum TileMode { kForward = 0, kBackward = 1 };
 
 constexpr int kTileThreads = 256;   // waves 0-1: row lanes, waves 2-3: column lanes
 constexpr int kLine = 128;          // register line length (extended rows and columns)
+constexpr int kLineShort = 120;     // the shorter line, for extended tiles of at most 120
 constexpr int kOutMax = 64;         // output tile side limit (column-lane state)
+constexpr int kColState = 2 * kOutMax;   // column lane: Z at the outputs, then the sums
 constexpr int kPad = kLine;         // LDS slack after each buffer
 constexpr int kChunk = 8;           // outputs stored per uniform guard
 
@@ -123,11 +125,13 @@ __device__ __forceinline__ void cis_direct(double malpha, float g, float& c, flo
     s = q == 0 ? sx : q == 1 ? cx : q == 2 ? -sx : -cx;
 }
 
-// v[0..kLine) <- src[0..kLine) with 16-byte LDS loads (src 16-byte aligned).
-__device__ __forceinline__ void load_line(float (&v)[kLine], const float* src) {
+// v[0..L) <- src[0..L) with 16-byte LDS loads (src 16-byte aligned).
+template <int L>
+__device__ __forceinline__ void load_line(float (&v)[L], const float* src) {
+    static_assert(L % 4 == 0, "line of whole 16-byte chunks");
     const float4* s4 = reinterpret_cast<const float4*>(src);
 #pragma unroll
-    for (int k = 0; k < kLine / 4; ++k) {
+    for (int k = 0; k < L / 4; ++k) {
         const float4 q = s4[k];
         v[4 * k] = q.x;
         v[4 * k + 1] = q.y;
@@ -145,15 +149,16 @@ __device__ __forceinline__ void load_line(float (&v)[kLine], const float* src) {
 // inside or wholly outside the image; chunks outside read a clamped in-image
 // chunk, whose values are never used because the phase there is zero.
 constexpr int kBufferWord3 = 0x00020000;   // raw buffer resource, gfx9 family
+template <int L>
 __device__ __forceinline__ void load_g_row(const TileArgs& a, int ei0, int ej0, int i,
-                                           float (&v)[kLine]) {
+                                           float (&v)[L]) {
     const int W = __builtin_amdgcn_readfirstlane(a.W);
     const int e0 = __builtin_amdgcn_readfirstlane(ej0);
     const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
         const_cast<float*>(a.f), 0, a.H * W * (int)sizeof(float), kBufferWord3);
     const int voff = min(max(ei0 + i, 0), a.H - 1) * W * (int)sizeof(float);
 #pragma unroll
-    for (int k = 0; k < kLine / 4; ++k) {
+    for (int k = 0; k < L / 4; ++k) {
         const int soff = min(max(e0 + 4 * k, 0), W - 4) * (int)sizeof(float);   // uniform
         const auto q = __builtin_amdgcn_raw_buffer_load_b128(rs, voff, soff, 0);
         v[4 * k] = __uint_as_float(q[0]) - a.center;
@@ -164,8 +169,8 @@ __device__ __forceinline__ void load_g_row(const TileArgs& a, int ei0, int ej0, 
 }
 
 // (zr + j zi)[x] *= exp(j step g[goff + x]) for x0 <= x < x1.
-template <int x0, int x1, int L>
-__device__ __forceinline__ void phase_step(float (&zr)[L], float (&zi)[L], const float (&g)[kLine],
+template <int x0, int x1, int L, int LG>
+__device__ __forceinline__ void phase_step(float (&zr)[L], float (&zi)[L], const float (&g)[LG],
                                            int goff, float step) {
 #pragma unroll
     for (int x = x0; x < x1; ++x) {
@@ -238,11 +243,11 @@ __device__ __forceinline__ int tile_out_barriers(const TileArgs& a, int mode) {
 
 // Row role (waves 0-1): lane i owns extended row i.  State: A0 + j A1 = Z
 // (forward) or Y = A Z (adjoint) at the row's pixels; zero outside the image.
-template <int MODE, bool GG>
+template <int MODE, bool GG, int L>
 __device__ __forceinline__ void row_role(const TileArgs& a, const TileCtx& c) {
     const int i = c.t;
     const bool act = i < c.EH;
-    float A0[kLine], A1[kLine], v[kLine];
+    float A0[L], A1[L], v[L];
     if (act) {
         if (GG)
             load_g_row(a, c.ei0, c.ej0, i, v);
@@ -254,7 +259,7 @@ __device__ __forceinline__ void row_role(const TileArgs& a, const TileCtx& c) {
         const int xhi = min(c.EW, a.W - c.ej0);
         if (a.odd) {
 #pragma unroll
-            for (int x = 0; x < kLine; ++x) {
+            for (int x = 0; x < L; ++x) {
                 float cc, ss;
                 cis_small(a.alpha_f * v[x], cc, ss);
                 const bool in = rin && x >= xlo && x < xhi;
@@ -263,7 +268,7 @@ __device__ __forceinline__ void row_role(const TileArgs& a, const TileCtx& c) {
             }
         } else {
 #pragma unroll
-            for (int x = 0; x < kLine; ++x) {
+            for (int x = 0; x < L; ++x) {
                 const bool in = rin && x >= xlo && x < xhi;
                 A0[x] = in ? 1.0f : 0.0f;
                 A1[x] = 0.0f;
@@ -272,7 +277,7 @@ __device__ __forceinline__ void row_role(const TileArgs& a, const TileCtx& c) {
         if (MODE == kBackward) {
             load_line(v, c.hpl + i * c.EWp);   // A
 #pragma unroll
-            for (int x = 0; x < kLine; ++x) {
+            for (int x = 0; x < L; ++x) {
                 A0[x] *= v[x];
                 A1[x] *= v[x];
             }
@@ -295,30 +300,30 @@ __device__ __forceinline__ void row_role(const TileArgs& a, const TileCtx& c) {
             // second half of the phase step: the previous step (the last
             // channel of pair q - 1) left g in v, below
             if (__builtin_expect(cs == 0 && q > 0, 0))
-                phase_step<kLine / 2, kLine>(A0, A1, v, 0, a.two_alpha);
+                phase_step<L / 2, L>(A0, A1, v, 0, a.two_alpha);
             asm volatile("" : "+s"(cs));
             if (__builtin_expect(cs == 0, 0)) {
 #pragma unroll
-                for (int x = 0; x < kLine; ++x) v[x] = A0[x];
+                for (int x = 0; x < L; ++x) v[x] = A0[x];
             }
             asm volatile("" : "+s"(cs));
             if (__builtin_expect(cs == 1, 0)) {
                 load_line(v, mulpl + i * c.EWp);
 #pragma unroll
-                for (int x = 0; x < kLine; ++x) v[x] *= A0[x];
+                for (int x = 0; x < L; ++x) v[x] *= A0[x];
             }
             asm volatile("" : "+s"(cs));
             if (__builtin_expect(cs == 2, 0)) {
 #pragma unroll
-                for (int x = 0; x < kLine; ++x) v[x] = A1[x];
+                for (int x = 0; x < L; ++x) v[x] = A1[x];
             }
             asm volatile("" : "+s"(cs));
             if (__builtin_expect(cs == 3, 0)) {
                 load_line(v, mulpl + i * c.EWp);
 #pragma unroll
-                for (int x = 0; x < kLine; ++x) v[x] *= A1[x];
+                for (int x = 0; x < L; ++x) v[x] *= A1[x];
             }
-            for (int b = 0; b < a.nb; ++b) box_dispatch<kLine>(v, a.r[b]);
+            for (int b = 0; b < a.nb; ++b) box_dispatch<L>(v, a.r[b]);
             float* dst = c.Tb + (s & 1) * c.tfl + i;
 #pragma unroll
             for (int j0c = 0; j0c < kOutMax; j0c += kChunk) {
@@ -339,7 +344,7 @@ __device__ __forceinline__ void row_role(const TileArgs& a, const TileCtx& c) {
                     load_g_row(a, c.ei0, c.ej0, i, v);
                 else
                     load_line(v, c.gpl + i * c.EWp);
-                phase_step<0, kLine / 2>(A0, A1, v, 0, a.two_alpha);
+                phase_step<0, L / 2>(A0, A1, v, 0, a.two_alpha);
             }
         }
         __syncthreads();
@@ -356,12 +361,13 @@ __device__ __forceinline__ void row_role(const TileArgs& a, const TileCtx& c) {
 // Q|P (A1) on wave 2|3; adjoint the partial sum (A1).  g at the outputs is
 // read from LDS where it is needed.  Wave 2 filters the channels with even
 // index, wave 3 the odd ones.
-template <int MODE, bool AUX, bool GG>
+template <int MODE, bool AUX, bool GG, int L>
 __device__ __forceinline__ void col_role(const TileArgs& a, const TileCtx& c, int tile_id) {
+    static_assert(L >= kOutMax, "the line holds the column's outputs");
     const int j = c.lane;
     const bool act = j < c.TW;
     const int TH = c.TH;
-    float A0[kLine], A1[kLine], v[kLine];
+    float A0[kColState], A1[kColState], v[L];
     // dst[0..kOutMax) <- g at the output pixels of column j (rows past TH: 0 or a repeat)
     auto load_gcol = [&](auto& dst) {
         if (MODE == kForward || GG) {
@@ -416,12 +422,12 @@ __device__ __forceinline__ void col_role(const TileArgs& a, const TileCtx& c, in
         };
         if (s > 0 && (ch & 1) == (c.wave - 2) && act) {
             load_line(v, c.Tb + ((s - 1) & 1) * c.tfl + j * c.EHp);
-            for (int b = 0; b < a.nb; ++b) box_dispatch<kLine>(v, a.r[b]);
+            for (int b = 0; b < a.nb; ++b) box_dispatch<L>(v, a.r[b]);
             const float cq = a.chat[q];
             const float m = (float)(a.odd + 2 * q);
             // accumulate over the output rows k < TH; the channel picks the
             // coefficient (uniform), every index is a compile-time constant
-            auto accumulate = [&](auto coef_of, float (&acc)[kLine]) {
+            auto accumulate = [&](auto coef_of, float (&acc)[kColState]) {
 #pragma unroll
                 for (int i0c = 0; i0c < kOutMax; i0c += kChunk) {
                     if (i0c < TH) {
@@ -573,7 +579,7 @@ __device__ __forceinline__ void col_role(const TileArgs& a, const TileCtx& c, in
 
 // One output tile of one image (tile index tile_id) for descriptor a; all
 // 256 threads of the workgroup call it together.
-template <int MODE, bool AUX, bool GG = false>
+template <int MODE, bool AUX, bool GG = false, int L = kLine>
 __device__ __forceinline__ void tile_body(const TileArgs& a, int tile_id, float* smem) {
     TileCtx c;
     c.EH = a.EH;
@@ -623,16 +629,16 @@ __device__ __forceinline__ void tile_body(const TileArgs& a, int tile_id, float*
         __syncthreads();
     }
     if (c.wave < 2)
-        row_role<MODE, GG>(a, c);
+        row_role<MODE, GG, L>(a, c);
     else
-        col_role<MODE, AUX, GG>(a, c, tile_id);
+        col_role<MODE, AUX, GG, L>(a, c, tile_id);
 }
 
-template <int MODE, bool AUX, bool GG = false>
+template <int MODE, bool AUX, bool GG = false, int L = kLine>
 __global__ void __launch_bounds__(kTileThreads)
 bf_tile_kernel(const TileArgs a) {
     extern __shared__ __align__(16) float smem[];
-    tile_body<MODE, AUX, GG>(a, blockIdx.x, smem);
+    tile_body<MODE, AUX, GG, L>(a, blockIdx.x, smem);
 }
 
 // Host helpers shared by the single-image and batched launchers (bf_tile.hip).

@@ -72,6 +72,10 @@ bf_status plan_tiles(int mode, int64_t H, int64_t W, const SpatialParams& sp, in
     g->tiles_x = (int)((W + tw - 1) / tw);
     g->lds_bytes = lds_of(th, tw);
     g->gg = gg;
+    // every lane of the single-image kernels runs its whole register line,
+    // whatever part of it the tile uses, so extended tiles of at most 120
+    // take the shorter line (about 6 % less work for R <= 28 at 64 x 64)
+    g->line = (g->EH <= kLineShort && g->EW <= kLineShort) ? kLineShort : kLine;
     return BF_OK;
 }
 
@@ -123,9 +127,16 @@ template <int MODE, bool AUX, bool GG = false>
 static bf_status launch_tile(const TileArgs& a, const TileGeom& g, hipStream_t stream,
                              const char* what) {
     const dim3 grid((unsigned)(g.tiles_x * g.tiles_y)), block(kTileThreads);
-    (void)hipFuncSetAttribute((const void*)bf_tile_kernel<MODE, AUX, GG>,
-                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)g.lds_bytes);
-    hipLaunchKernelGGL((bf_tile_kernel<MODE, AUX, GG>), grid, block, g.lds_bytes, stream, a);
+    if (g.line == kLineShort) {
+        (void)hipFuncSetAttribute((const void*)bf_tile_kernel<MODE, AUX, GG, kLineShort>,
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)g.lds_bytes);
+        hipLaunchKernelGGL((bf_tile_kernel<MODE, AUX, GG, kLineShort>), grid, block,
+                           g.lds_bytes, stream, a);
+    } else {
+        (void)hipFuncSetAttribute((const void*)bf_tile_kernel<MODE, AUX, GG>,
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)g.lds_bytes);
+        hipLaunchKernelGGL((bf_tile_kernel<MODE, AUX, GG>), grid, block, g.lds_bytes, stream, a);
+    }
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) {
         set_error("%s launch failed: %s", what, hipGetErrorString(e));

@@ -43,6 +43,10 @@ CASES = [
     (16, 40, 60.0, 9, [3]),
     (1, 50, 30.0, 0, [3]),
     (18, 18, 12.0, 0, [1, 1, 1]),       # N = 181
+    # extended tiles wider than 120 samples: the 128-sample line variants,
+    # g from global memory (W, R multiples of 4) and g staged in LDS
+    (24, 28, 25.0, 0, [16, 18, 18]),    # R = 52, extended tile 128 x 128
+    (30, 30, 30.0, 0, [15, 17, 18]),    # R = 50, extended tile 128 x 124
 ]
 
 
