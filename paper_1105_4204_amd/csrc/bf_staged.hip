@@ -35,6 +35,8 @@ constexpr int kStRows = 64;       // horizontal pass: rows per workgroup
 constexpr int kStOutH = 64;       // horizontal pass: outputs per line, at most
 constexpr int kStPitch = kStCols + 1;
 static_assert(kStOutH % 4 == 0, "the four waves share the output columns");
+static_assert(kStThreads == 256 && kStCols == 64 && kStLine % 64 == 0,
+              "the phase hand-over: four waves, 16 rows each per block of 64");
 
 struct StageArgs {
     const float* f;
@@ -94,13 +96,10 @@ bf_stage_v(const StageArgs a) {
     const int nch = a.centre ? 2 : 4;
     const int ch = wave;
     float* trw = tr + (size_t)wave * a.nout_v * kStPitch;
-    if (ch < nch) {
-        const int x = x0 + lane;
-        float v[kStLine];
-        // two loops rather than a test of the (uniform) centre flag per
-        // sample, so that the LDS reads of g are not each followed by a
-        // branch and a wait of their own
-        if (a.centre) {
+    const int x = x0 + lane;
+    float v[kStLine];
+    if (a.centre) {   // channels 1 and g: no phase
+        if (ch < nch) {
 #pragma unroll
             for (int y = 0; y < kStLine; ++y) {
                 const int gy = ey0 + y;
@@ -108,18 +107,40 @@ bf_stage_v(const StageArgs a) {
                 const float g = gtile[y * kStCols + lane];
                 v[y] = in ? ((ch == 0) ? 1.0f : g) : 0.0f;
             }
-        } else {
+        }
+    } else {
+        // Every channel needs the phase of every sample: per block of 64
+        // rows each wave evaluates it for 16 of them and hands the four
+        // channel values (C, gC, S, gS; zero outside the image) over
+        // through the transpose area, which is free until the box stages
+        // are done.  The channel is uniform here, so all four waves pass
+        // the barriers.
+        float* stg = tr;   // [4][64][kStCols]
 #pragma unroll
-            for (int y = 0; y < kStLine; ++y) {
+        for (int blk = 0; blk < kStLine / 64; ++blk) {
+#pragma unroll
+            for (int u = 0; u < 16; ++u) {
+                const int yl = wave * 16 + u;
+                const int y = blk * 64 + yl;
                 const int gy = ey0 + y;
                 const bool in = x < a.W && gy >= 0 && gy < a.H;
                 const float g = gtile[y * kStCols + lane];
                 float cc, ss;
                 cis_direct(a.malpha, g, cc, ss);
-                const float base = (ch >= 2) ? ss : cc;
-                v[y] = in ? ((ch & 1) ? g * base : base) : 0.0f;
+                cc = in ? cc : 0.0f;
+                ss = in ? ss : 0.0f;
+                stg[(0 * 64 + yl) * kStCols + lane] = cc;
+                stg[(1 * 64 + yl) * kStCols + lane] = g * cc;
+                stg[(2 * 64 + yl) * kStCols + lane] = ss;
+                stg[(3 * 64 + yl) * kStCols + lane] = g * ss;
             }
+            __syncthreads();
+#pragma unroll
+            for (int yl = 0; yl < 64; ++yl) v[blk * 64 + yl] = stg[(ch * 64 + yl) * kStCols + lane];
+            __syncthreads();
         }
+    }
+    if (ch < nch) {
         for (int b = 0; b < a.nb; ++b) box_dispatch<kStLine, true>(v, a.r[b]);
 #pragma unroll
         for (int y0c = 0; y0c < kStOutV; y0c += kChunk) {
@@ -153,6 +174,7 @@ __global__ void __launch_bounds__(kStThreads) __attribute__((amdgpu_waves_per_eu
 bf_stage_h(const StageArgs a) {
     __shared__ float gt[kStRows][kStOutH + 1];
     __shared__ float red[4][kStOutH][kStRows + 1];
+    __shared__ float csm[2][kStOutH][kStRows + 1];   // C and S at the outputs
     const int t = threadIdx.x;
     const int wave = __builtin_amdgcn_readfirstlane(t >> 6);
     const int lane = t & 63;
@@ -180,6 +202,19 @@ bf_stage_h(const StageArgs a) {
         }
     }
     __syncthreads();
+    if (!a.centre) {
+        // the phase at the outputs, once per pixel: wave w evaluates the
+        // output columns 16 w .. 16 w + 15 of every row (the flag is uniform)
+#pragma unroll
+        for (int u = 0; u < kStOutH / 4; ++u) {
+            const int k = wave * (kStOutH / 4) + u;
+            float cc, ss;
+            cis_direct(a.malpha, gt[lane][k], cc, ss);
+            csm[0][k][lane] = cc;
+            csm[1][k][lane] = ss;
+        }
+        __syncthreads();
+    }
     const int nch = a.centre ? 2 : 4;
     const int ch = wave;
     if (ch < nch) {
@@ -212,12 +247,9 @@ bf_stage_h(const StageArgs a) {
 #pragma unroll
             for (int k = 0; k < kStOutH; ++k) red[ch][k][lane] = a.c * v[k];
         } else {
+            const int cs = ch >= 2 ? 1 : 0;
 #pragma unroll
-            for (int k = 0; k < kStOutH; ++k) {
-                float cc, ss;
-                cis_direct(a.malpha, gt[lane][k], cc, ss);
-                red[ch][k][lane] = a.c * v[k] * ((ch >= 2) ? ss : cc);
-            }
+            for (int k = 0; k < kStOutH; ++k) red[ch][k][lane] = a.c * v[k] * csm[cs][k][lane];
         }
     }
     __syncthreads();
@@ -340,7 +372,9 @@ bf_status launch_staged(const float* f, float* out, float* eta, int64_t H, int64
     a.nout_v = std::min(kStLine - 2 * sp.R, kStOutV);
     a.nout_h = std::min(kStLine - 2 * sp.R, kStOutH);
     a.center = rp.center;
-    const size_t lds_v = ((size_t)kStLine * kStCols + 4 * (size_t)a.nout_v * kStPitch) *
+    // g tile, then the transposed outputs or (before them) the phase hand-over
+    const size_t lds_v = ((size_t)kStLine * kStCols +
+                          std::max(4 * (size_t)a.nout_v * kStPitch, (size_t)4 * 64 * kStCols)) *
                          sizeof(float);
     (void)hipFuncSetAttribute((const void*)bf_stage_v, hipFuncAttributeMaxDynamicSharedMemorySize,
                               (int)lds_v);
