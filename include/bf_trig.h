@@ -113,11 +113,14 @@ bf_status bf_range_truncate(int32_t N, double T, const bf_spatial_spec* spatial_
 bf_status bf_spatial_gaussian(double sigma_s, int32_t n_boxes, bf_spatial_spec* out);
 
 /* Device workspace the forward wants for image size H x W and this spatial
- * kernel.  0: the fused single-pass kernel is used.  24*H*W bytes: the staged
- * path, which filters the channels of each cosine pair in two separable
- * passes through this workspace (Sec. 2.1, eq. (final-form)), is required
- * (sum of radii 63 < R <= 127) or faster (the fused tiles shrink as R grows;
- * from R of about 50 on a 2048^2 image).  Every radius must be <= 31;
+ * kernel.  0: the fused single-pass kernel is used.  Otherwise
+ * 4 * (4 H Wp + 2 H W) bytes, Wp = W rounded up to a multiple of 4, plus
+ * 256 (four channel planes with zero margins, then den and num; the
+ * workspace must be 16-byte aligned): the staged path, which filters the
+ * channels of each cosine pair in two separable passes through this
+ * workspace (Sec. 2.1, eq. (final-form)), is required (sum of radii
+ * 63 < R <= 124) or faster (the fused tiles shrink as R grows; from R of
+ * about 53 on a 2048^2 image).  Every radius must be <= 31;
  * BF_EUNSUPPORTED when neither path handles the kernel.  The staged path is
  * forward only: with aux_out set the forward uses the fused kernel, which
  * exists for R <= 63; without the workspace it also falls back to the fused

@@ -80,6 +80,10 @@ bf_status bf_trig_forward_ex(const float* f, int64_t H, int64_t W, float T, floa
             set_error("workspace must not overlap the images");
             return BF_EINVAL;
         }
+        if ((reinterpret_cast<uintptr_t>(ws) & 15) != 0) {
+            set_error("the staged path's workspace must be 16-byte aligned");
+            return BF_EINVAL;
+        }
         return launch_staged(f, out, eta, H, W, c.rp, c.sp, ws, c.stream);
     }
     if (st != BF_OK) return st;

@@ -8,16 +8,20 @@
 // the |x| <= pi/4 polynomial):
 //   vertical pass   (bf_stage_v): lane = image column; a 256-sample register
 //     line down the column holds a channel (C, gC, S, gS; 1, g for m = 0)
-//     on the extended rows, the box stages run along it, and the 256 - 2R
-//     outputs are written, transposed, to a column-major plane V_ch;
+//     on the extended rows, the box stages run along it, and the up to 88
+//     outputs are written to a row-major plane V_ch (consecutive lanes,
+//     consecutive columns);
 //   horizontal pass (bf_stage_h): lane = image row; a 256-sample line along
-//     the row is read from V_ch (coalesced thanks to the transposed layout),
-//     the box stages run along it, and the 64 outputs are demodulated and
-//     accumulated into den and num (column-major, read-modify-write).
-// A final pass divides in FP64 and writes out (and eta) row-major.  The
-// planes live in a caller-provided workspace of 24 bytes per pixel: unlike
-// the fused kernel, this path keeps the filtered channels of one pair in
-// device memory between its two passes.  Wide kernels have a large mass
+//     the row is read from V_ch in 16-byte loads, the box stages run along
+//     it, and the up to 64 outputs are demodulated and accumulated into den
+//     and num (column-major, read-modify-write).
+// A V_ch row carries 128 zero columns on each side (the zero extension of
+// the horizontal pass, R <= 124) and is padded to a multiple of 4 columns;
+// the horizontal blocks are placed so that every line starts on a 16-byte
+// boundary.  A final pass divides in FP64 and writes out (and eta)
+// row-major.  The planes live in a caller-provided workspace: unlike the
+// fused kernel, this path keeps the filtered channels of one pair in device
+// memory between its two passes.  Wide kernels have a large mass
 // (the sum of w) against w(0), so where a pixel has few similar neighbours
 // the pair terms cancel heavily; both passes use compensated running sums.
 #include <algorithm>
@@ -33,22 +37,24 @@ constexpr int kStCols = 64;       // vertical pass: columns per workgroup
 constexpr int kStOutV = 88;       // vertical pass: outputs per line, at most
 constexpr int kStRows = 64;       // horizontal pass: rows per workgroup
 constexpr int kStOutH = 64;       // horizontal pass: outputs per line, at most
-constexpr int kStPitch = kStCols + 1;
+constexpr int kStMargin = 128;    // zero columns on each side of a V row (>= R)
 static_assert(kStOutH % 4 == 0, "the four waves share the output columns");
 static_assert(kStThreads == 256 && kStCols == 64 && kStLine % 64 == 0,
               "the phase hand-over: four waves, 16 rows each per block of 64");
 
 struct StageArgs {
     const float* f;
-    float* vt;          // 4 column-major H x W planes: V_ch[x * H + y]
+    float* vp;          // 4 row-major planes of H rows: V_ch[y * Wp + kStMargin + x]
     float* den_t;       // column-major accumulators
     float* num_t;
     float* out;
     float* eta;
     int H, W, R, nb;
     int r[BF_MAX_BOXES];
+    int Wp;             // V row pitch: W rounded up to a multiple of 4, plus two margins
     int nout_v;         // outputs per vertical line: min(256 - 2R, kStOutV)
-    int nout_h;         // outputs per horizontal line: min(256 - 2R, kStOutH)
+    int nout_h;         // outputs per horizontal line: min(256 - 2R, kStOutH), multiple of 4
+    int xshift;         // horizontal block b starts at column b nout_h - xshift
     int centre;         // this pair is m = 0 (channels 1, g)
     float c;            // c_m
     double malpha;      // m a
@@ -58,20 +64,19 @@ struct StageArgs {
 // Vertical pass.  Workgroup: 64 columns x one segment of nout_v output rows;
 // the 256 extended rows of g are staged in LDS once, then wave w builds
 // channel w (C, gC, S, gS; 1, g for m = 0) down its 64 columns, filters it
-// and writes it transposed through LDS.
+// and writes its outputs row by row into V_ch.
 // One wave per SIMD: the 256-sample line needs the whole register file.
 __global__ void __launch_bounds__(kStThreads) __attribute__((amdgpu_waves_per_eu(1, 1)))
 bf_stage_v(const StageArgs a) {
     extern __shared__ __align__(16) float lds[];
     float* gtile = lds;                                   // [256][kStCols]
-    float* tr = lds + kStLine * kStCols;                  // [4][nout_v][kStPitch]
+    float* stg = lds + kStLine * kStCols;                 // [4][64][kStCols]
     const int t = threadIdx.x;
     const int wave = __builtin_amdgcn_readfirstlane(t >> 6);
     const int lane = t & 63;
     const int x0 = blockIdx.x * kStCols;
     const int y0 = blockIdx.y * a.nout_v;
     const int ey0 = y0 - a.R;
-    const size_t HW = (size_t)a.H * a.W;
     // clamped, unconditional loads in batches of 8 per thread, then the
     // selection against the real position (a guarded load would wait alone)
     for (int p0 = t; p0 < kStLine * kStCols; p0 += 8 * kStThreads) {
@@ -95,7 +100,6 @@ bf_stage_v(const StageArgs a) {
     __syncthreads();
     const int nch = a.centre ? 2 : 4;
     const int ch = wave;
-    float* trw = tr + (size_t)wave * a.nout_v * kStPitch;
     const int x = x0 + lane;
     float v[kStLine];
     if (a.centre) {   // channels 1 and g: no phase
@@ -112,10 +116,8 @@ bf_stage_v(const StageArgs a) {
         // Every channel needs the phase of every sample: per block of 64
         // rows each wave evaluates it for 16 of them and hands the four
         // channel values (C, gC, S, gS; zero outside the image) over
-        // through the transpose area, which is free until the box stages
-        // are done.  The channel is uniform here, so all four waves pass
-        // the barriers.
-        float* stg = tr;   // [4][64][kStCols]
+        // through LDS.  The flag is uniform, so all four waves pass the
+        // barriers.
 #pragma unroll
         for (int blk = 0; blk < kStLine / 64; ++blk) {
 #pragma unroll
@@ -140,28 +142,17 @@ bf_stage_v(const StageArgs a) {
             __syncthreads();
         }
     }
-    if (ch < nch) {
+    if (ch < nch && x < a.W) {   // columns past W stay zero: they are the margin
         for (int b = 0; b < a.nb; ++b) box_dispatch<kStLine, true>(v, a.r[b]);
+        float* dst = a.vp + (size_t)ch * a.H * a.Wp + kStMargin + x;
 #pragma unroll
         for (int y0c = 0; y0c < kStOutV; y0c += kChunk) {
-            if (y0c < a.nout_v) {
+            if (y0c < a.nout_v) {   // uniform
 #pragma unroll
-                for (int yy = 0; yy < kChunk; ++yy)
-                    if (y0c + yy < a.nout_v) trw[(y0c + yy) * kStPitch + lane] = v[y0c + yy];
-            }
-        }
-    }
-    __syncthreads();
-    // transposed, coalesced writes: wave w writes columns w, w + 4, ..., its
-    // lanes consecutive rows of one column
-    for (int c2 = 0; c2 < nch; ++c2) {
-        const float* src = tr + (size_t)c2 * a.nout_v * kStPitch;
-        float* dst = a.vt + (size_t)c2 * HW;
-        for (int xl = wave; xl < kStCols; xl += kStThreads / 64) {
-            const int X = x0 + xl;
-            for (int yl = lane; yl < a.nout_v; yl += 64) {
-                const int Y = y0 + yl;
-                if (X < a.W && Y < a.H) dst[(size_t)X * a.H + Y] = src[yl * kStPitch + xl];
+                for (int yy = 0; yy < kChunk; ++yy) {
+                    const int Y = y0 + y0c + yy;
+                    if (y0c + yy < a.nout_v && Y < a.H) dst[(size_t)Y * a.Wp] = v[y0c + yy];
+                }
             }
         }
     }
@@ -178,27 +169,28 @@ bf_stage_h(const StageArgs a) {
     const int t = threadIdx.x;
     const int wave = __builtin_amdgcn_readfirstlane(t >> 6);
     const int lane = t & 63;
-    const int y = blockIdx.y * kStRows + lane;
-    const int x0 = blockIdx.x * a.nout_h;
-    const int ex0 = x0 - a.R;
+    const int yb = blockIdx.y * kStRows;
+    const int y = yb + lane;
+    const int x0 = blockIdx.x * a.nout_h - a.xshift;   // may be negative in the first block
+    const int ex0 = x0 - a.R;                           // a multiple of 4
     const int yc = min(y, a.H - 1);
-    const size_t HW = (size_t)a.H * a.W;
     for (int p0 = t; p0 < kStRows * kStOutH; p0 += 8 * kStThreads) {
         float v8[8];
 #pragma unroll
         for (int u = 0; u < 8; ++u) {
             const int p = p0 + u * kStThreads;
             const int yy = p / kStOutH, k = p - yy * kStOutH;
-            const int Y = min(blockIdx.y * kStRows + yy, a.H - 1), X = min(x0 + k, a.W - 1);
+            const int Y = min(yb + yy, a.H - 1), X = min(max(x0 + k, 0), a.W - 1);
             v8[u] = a.f[(size_t)Y * a.W + X];
         }
 #pragma unroll
         for (int u = 0; u < 8; ++u) {
             const int p = p0 + u * kStThreads;
             const int yy = p / kStOutH, k = p - yy * kStOutH;
-            const int Y = blockIdx.y * kStRows + yy, X = x0 + k;
+            const int Y = yb + yy, X = x0 + k;
             if (p < kStRows * kStOutH)
-                gt[yy][k] = (Y < a.H && X < a.W && k < a.nout_h) ? v8[u] - a.center : 0.0f;
+                gt[yy][k] = (Y < a.H && X >= 0 && X < a.W && k < a.nout_h) ? v8[u] - a.center
+                                                                            : 0.0f;
         }
     }
     __syncthreads();
@@ -219,28 +211,30 @@ bf_stage_h(const StageArgs a) {
     const int ch = wave;
     if (ch < nch) {
         float v[kStLine];
-        // 4-byte buffer loads: the lane's row is the vector offset, the
-        // (wave-uniform) column the scalar offset, from a resource based at
-        // the first in-image column of the line and sized to the line's
-        // columns, so that every offset stays far below 2^31 and no load
-        // needs address registers.  Columns outside the image read a clamped
-        // column and are zeroed by a uniform select; rows past H read row
-        // H - 1, and their results are never stored.
+        // 16-byte buffer loads along the lane's row of V_ch: the row (from
+        // the workgroup's first) is the vector offset, the wave-uniform
+        // column the scalar offset; the resource spans the workgroup's rows.
+        // The line starts on a 16-byte boundary and at column ex0 >= -R,
+        // inside the left margin; samples past the row's end belong to
+        // positions no kept output reads (or come back as zero past the
+        // resource).  Rows past H read row H - 1 and are never stored.
         const int Hs = __builtin_amdgcn_readfirstlane(a.H);
-        const int Ws = __builtin_amdgcn_readfirstlane(a.W);
+        const int Wps = __builtin_amdgcn_readfirstlane(a.Wp);
         const int e0 = __builtin_amdgcn_readfirstlane(ex0);
-        const int xlo = max(e0, 0), xhi = min(e0 + kStLine, Ws);   // in-image columns [xlo, xhi)
+        const int ybs = __builtin_amdgcn_readfirstlane(yb);
+        const int nrows = min(Hs - ybs, kStRows);
         const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
-            const_cast<float*>(a.vt + (size_t)ch * HW + (size_t)xlo * Hs), 0,
-            (xhi - xlo) * Hs * (int)sizeof(float), kBufferWord3);
-        const int voff = yc * (int)sizeof(float);
+            a.vp + (size_t)ch * Hs * Wps + (size_t)ybs * Wps, 0,
+            nrows * Wps * (int)sizeof(float), kBufferWord3);
+        const int voff = (yc - yb) * Wps * (int)sizeof(float);
 #pragma unroll
-        for (int x = 0; x < kStLine; ++x) {
-            const int gx = e0 + x;
-            const int col = min(max(gx, xlo), xhi - 1) - xlo;
-            const float val = __uint_as_float(
-                __builtin_amdgcn_raw_buffer_load_b32(rs, voff, col * Hs * (int)sizeof(float), 0));
-            v[x] = (gx >= 0 && gx < Ws) ? val : 0.0f;
+        for (int k = 0; k < kStLine / 4; ++k) {
+            const int soff = (kStMargin + e0 + 4 * k) * (int)sizeof(float);   // uniform
+            const auto q = __builtin_amdgcn_raw_buffer_load_b128(rs, voff, soff, 0);
+            v[4 * k] = __uint_as_float(q[0]);
+            v[4 * k + 1] = __uint_as_float(q[1]);
+            v[4 * k + 2] = __uint_as_float(q[2]);
+            v[4 * k + 3] = __uint_as_float(q[3]);
         }
         for (int b = 0; b < a.nb; ++b) box_dispatch<kStLine, true>(v, a.r[b]);
         if (a.centre) {
@@ -262,7 +256,7 @@ bf_stage_h(const StageArgs a) {
 #pragma unroll
         for (int u = 0; u < kPer; ++u) {
             const int k = wave * kPer + u;
-            const size_t idx = (size_t)min(x0 + k, a.W - 1) * a.H + y;
+            const size_t idx = (size_t)min(max(x0 + k, 0), a.W - 1) * a.H + y;
             d16[u] = a.den_t[idx];
             n16[u] = a.num_t[idx];
         }
@@ -270,7 +264,7 @@ bf_stage_h(const StageArgs a) {
         for (int u = 0; u < kPer; ++u) {
             const int k = wave * kPer + u;
             const int X = x0 + k;
-            if (k < a.nout_h && X < a.W) {
+            if (k < a.nout_h && X >= 0 && X < a.W) {
                 const float d = a.centre ? red[0][k][lane] : red[0][k][lane] + red[2][k][lane];
                 const float n = a.centre ? red[1][k][lane] : red[1][k][lane] + red[3][k][lane];
                 a.den_t[(size_t)X * a.H + y] = d16[u] + d;
@@ -284,6 +278,21 @@ __global__ void bf_stage_zero(float* p, size_t n) {
     for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
          i += (size_t)gridDim.x * blockDim.x)
         p[i] = 0.0f;
+}
+
+// Zeroes the columns of the V planes that the vertical pass never writes:
+// kStMargin on the left, and the padding and kStMargin on the right of
+// every row (Wp - W per row, 4 H rows).
+__global__ void bf_stage_margins(float* vp, int H, int W, int Wp) {
+    const size_t per_row = (size_t)(Wp - W);
+    const size_t n = (size_t)4 * H * per_row;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (size_t)gridDim.x * blockDim.x) {
+        const size_t row = i / per_row;
+        const int j = (int)(i - row * per_row);
+        const int col = j < kStMargin ? j : W + j;
+        vp[row * Wp + col] = 0.0f;
+    }
 }
 
 // out = T/2 + num/den (FP64), eta = den; column-major in, row-major out
@@ -314,14 +323,20 @@ bf_stage_final(const StageArgs a) {
     }
 }
 
+static int staged_pitch(int64_t W) { return (int)((W + 3) / 4 * 4 + 2 * kStMargin); }
+
+// nout_h for the sum of radii R: at most 256 - 2R (every kept output sees its
+// whole box in the line) and a multiple of 4 (16-byte aligned lines).
+static int staged_nout_h(int R) { return std::min(kStLine - 2 * R, kStOutH) / 4 * 4; }
+
 size_t staged_workspace_bytes(int64_t H, int64_t W) {
-    return (size_t)6 * (size_t)H * (size_t)W * sizeof(float);
+    return ((size_t)4 * (size_t)H * (size_t)staged_pitch(W) + (size_t)2 * H * W) * sizeof(float);
 }
 
 bool staged_supported(const SpatialParams& sp) {
     for (int k = 0; k < sp.nb; ++k)
         if (sp.r[k] > kBoxMaxRadius) return false;
-    return 2 * sp.R < kStLine;
+    return sp.R <= kStMargin && staged_nout_h(sp.R) >= 4;
 }
 
 // Cost model, per cosine pair, calibrated on MI355X (2048^2, N = 66): a round
@@ -344,9 +359,9 @@ bool prefer_staged(int64_t H, int64_t W, const SpatialParams& sp, bf_status fuse
     }
     auto rounds = [&](double blocks) { return std::ceil(blocks / cus); };
     const int nout_v = std::min(kStLine - 2 * sp.R, kStOutV);
-    const int nout_h = std::min(kStLine - 2 * sp.R, kStOutH);
+    const int nout_h = staged_nout_h(sp.R);
     const double bv = std::ceil((double)W / kStCols) * std::ceil((double)H / nout_v);
-    const double bh = std::ceil((double)W / nout_h) * std::ceil((double)H / kStRows);
+    const double bh = std::ceil((double)(W + 3) / nout_h) * std::ceil((double)H / kStRows);
     const double fused_us = rounds((double)g.tiles_x * g.tiles_y) * 17.0;
     const double staged_us = (rounds(bv) + rounds(bh)) * 83.0;
     return staged_us < fused_us;
@@ -358,10 +373,12 @@ bf_status launch_staged(const float* f, float* out, float* eta, int64_t H, int64
     StageArgs a = {};
     const size_t HW = (size_t)H * (size_t)W;
     float* ws = static_cast<float*>(workspace);
+    a.Wp = staged_pitch(W);
+    const size_t vplanes = (size_t)4 * (size_t)H * (size_t)a.Wp;
     a.f = f;
-    a.vt = ws;
-    a.den_t = ws + 4 * HW;
-    a.num_t = ws + 5 * HW;
+    a.vp = ws;
+    a.den_t = ws + vplanes;
+    a.num_t = ws + vplanes + HW;
     a.out = out;
     a.eta = eta;
     a.H = (int)H;
@@ -370,18 +387,18 @@ bf_status launch_staged(const float* f, float* out, float* eta, int64_t H, int64
     a.nb = sp.nb;
     for (int k = 0; k < BF_MAX_BOXES; ++k) a.r[k] = sp.r[k];
     a.nout_v = std::min(kStLine - 2 * sp.R, kStOutV);
-    a.nout_h = std::min(kStLine - 2 * sp.R, kStOutH);
+    a.nout_h = staged_nout_h(sp.R);
+    a.xshift = (4 - sp.R % 4) % 4;   // block 0 starts at -xshift: x0 - R is a multiple of 4
     a.center = rp.center;
-    // g tile, then the transposed outputs or (before them) the phase hand-over
-    const size_t lds_v = ((size_t)kStLine * kStCols +
-                          std::max(4 * (size_t)a.nout_v * kStPitch, (size_t)4 * 64 * kStCols)) *
-                         sizeof(float);
+    // g tile, then the phase hand-over
+    const size_t lds_v = ((size_t)kStLine * kStCols + (size_t)4 * 64 * kStCols) * sizeof(float);
     (void)hipFuncSetAttribute((const void*)bf_stage_v, hipFuncAttributeMaxDynamicSharedMemorySize,
                               (int)lds_v);
     hipLaunchKernelGGL(bf_stage_zero, dim3(1024), dim3(256), 0, stream, a.den_t, 2 * HW);
+    hipLaunchKernelGGL(bf_stage_margins, dim3(1024), dim3(256), 0, stream, a.vp, a.H, a.W, a.Wp);
     const dim3 gv((unsigned)((W + kStCols - 1) / kStCols),
                   (unsigned)((H + a.nout_v - 1) / a.nout_v));
-    const dim3 gh((unsigned)((W + a.nout_h - 1) / a.nout_h),
+    const dim3 gh((unsigned)((W + a.xshift + a.nout_h - 1) / a.nout_h),
                   (unsigned)((H + kStRows - 1) / kStRows));
     for (int q = 0; q < rp.npairs; ++q) {
         const int m = rp.odd + 2 * q;

@@ -159,13 +159,15 @@ def test_phase_polynomial_constants_and_accuracy():
 
 def test_workspace_query_and_staged_validation():
     """R <= 63 (every radius <= 31) runs fused and needs no workspace; up to
-    R = 127 the staged path needs 24 bytes per pixel; wider kernels are
-    unsupported.  The forward rejects a staged request without workspace
+    R = 124 (four boxes of 31) the staged path needs its channel planes with
+    zero margins plus den and num; wider kernels are unsupported.  The forward rejects a staged request without workspace
     (BF_EINVAL) and a request for the adjoint's sums (BF_EUNSUPPORTED)."""
     assert nat.workspace_bytes(64, 80, [9, 9, 10]) == 0
     assert nat.workspace_bytes(64, 80, [31, 31, 1]) == 0            # R = 63
-    assert nat.workspace_bytes(64, 80, [29, 29, 30]) == 24 * 64 * 80
-    assert nat.workspace_bytes(10, 10, [31, 31, 31, 31]) == 24 * 100   # R = 124
+    def staged(H, W):   # four channel planes with 128-column zero margins, den, num
+        return 4 * (4 * H * ((W + 3) // 4 * 4 + 256) + 2 * H * W)
+    assert nat.workspace_bytes(64, 80, [29, 29, 30]) == staged(64, 80)
+    assert nat.workspace_bytes(10, 10, [31, 31, 31, 31]) == staged(10, 10)   # R = 124
     with pytest.raises(nat.BFError) as e:
         nat.workspace_bytes(64, 80, [40])
     assert e.value.code == 6
