@@ -340,10 +340,10 @@ bool staged_supported(const SpatialParams& sp) {
 }
 
 // Cost model, per cosine pair, calibrated on MI355X (2048^2, N = 66): a round
-// of fused tiles (one workgroup per CU) takes about 17 us whatever the tile
-// size, a round of staged workgroups about 83 us per pass.  The fused tiles
-// shrink as R grows (the extended line is at most 128 samples), so past R of
-// about 53 the staged passes are cheaper.
+// of fused tiles (one workgroup per CU) takes about 16 us whatever the tile
+// size, a round of staged workgroups about 27 us in either pass.  The fused
+// tiles shrink as R grows (the extended line is at most 128 samples), so
+// past R of about 50 the staged passes are faster.
 bool prefer_staged(int64_t H, int64_t W, const SpatialParams& sp, bf_status fused_status,
                    const TileGeom& g) {
     if (!staged_supported(sp)) return false;
@@ -362,8 +362,8 @@ bool prefer_staged(int64_t H, int64_t W, const SpatialParams& sp, bf_status fuse
     const int nout_h = staged_nout_h(sp.R);
     const double bv = std::ceil((double)W / kStCols) * std::ceil((double)H / nout_v);
     const double bh = std::ceil((double)(W + 3) / nout_h) * std::ceil((double)H / kStRows);
-    const double fused_us = rounds((double)g.tiles_x * g.tiles_y) * 17.0;
-    const double staged_us = (rounds(bv) + rounds(bh)) * 83.0;
+    const double fused_us = rounds((double)g.tiles_x * g.tiles_y) * 16.0;
+    const double staged_us = (rounds(bv) + rounds(bh)) * 27.0;
     return staged_us < fused_us;
 }
 

@@ -102,6 +102,21 @@ def test_forward_tile_override_consistent():
     assert torch.max(torch.abs(a - b)).item() < 2e-2
 
 
+def test_forward_fused_wide_kernel_tile_override():
+    """R = 46 forced through the fused kernel (a tile shape is given, so the
+    staged path is not taken): 36 x 36 tiles on the 128-sample line, against
+    the oracle, and against the staged path the library picks unforced."""
+    H, W, radii, sr = 90, 100, [15, 15, 16], 30.0
+    f_np = synth.piecewise_smooth(H, W, seed=46, n_shapes=4)
+    f = _cuda(f_np)
+    a = _ops().trig_forward(f, 255.0, sr, radii, tile=(36, 36))
+    b = _ops().trig_forward(f, 255.0, sr, radii)
+    torch.cuda.synchronize()
+    ref = oracle.forward(f_np, sr, oracle.range_degree(255.0, sr), radii)
+    _check(a.cpu().numpy(), ref, "fused R=46 tile 36x36")
+    _check(b.cpu().numpy(), ref, "default path R=46")
+
+
 def test_config1_full_image():
     f = synth.config_image(1)
     N = oracle.range_degree(255.0, 30.0)
