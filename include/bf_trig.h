@@ -114,8 +114,8 @@ bf_status bf_spatial_gaussian(double sigma_s, int32_t n_boxes, bf_spatial_spec* 
 
 /* Device workspace the forward wants for image size H x W and this spatial
  * kernel.  0: the fused single-pass kernel is used.  Otherwise
- * 4 * (4 H Wp + 2 H W) bytes, Wp = W rounded up to a multiple of 4, plus
- * 256 (four channel planes with zero margins, then den and num; the
+ * 4 * (4 H Wp + 2 H W) bytes, Wp = W + 260 rounded up to a multiple of 64
+ * (four channel planes with zero margins, then den and num; the
  * workspace must be 16-byte aligned): the staged path, which filters the
  * channels of each cosine pair in two separable passes through this
  * workspace (Sec. 2.1, eq. (final-form)), is required (sum of radii

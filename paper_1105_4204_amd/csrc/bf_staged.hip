@@ -15,10 +15,10 @@
 //     the row is read from V_ch in 16-byte loads, the box stages run along
 //     it, and the up to 64 outputs are demodulated and accumulated into den
 //     and num (column-major, read-modify-write).
-// A V_ch row carries 128 zero columns on each side (the zero extension of
-// the horizontal pass, R <= 124) and is padded to a multiple of 4 columns;
-// the horizontal blocks are placed so that every line starts on a 16-byte
-// boundary.  A final pass divides in FP64 and writes out (and eta)
+// A V_ch row carries at least 128 zero columns on each side (the zero
+// extension of the horizontal pass, R <= 124); the left margin is
+// 128 + (R mod 4) columns and the pitch a multiple of 4, so that every
+// horizontal line starts on a 16-byte boundary.  A final pass divides in FP64 and writes out (and eta)
 // row-major.  The planes live in a caller-provided workspace: unlike the
 // fused kernel, this path keeps the filtered channels of one pair in device
 // memory between its two passes.  Wide kernels have a large mass
@@ -37,24 +37,24 @@ constexpr int kStCols = 64;       // vertical pass: columns per workgroup
 constexpr int kStOutV = 88;       // vertical pass: outputs per line, at most
 constexpr int kStRows = 64;       // horizontal pass: rows per workgroup
 constexpr int kStOutH = 64;       // horizontal pass: outputs per line, at most
-constexpr int kStMargin = 128;    // zero columns on each side of a V row (>= R)
+constexpr int kStMargin = 128;    // zero columns at least on each side of a V row (>= R)
 static_assert(kStOutH % 4 == 0, "the four waves share the output columns");
 static_assert(kStThreads == 256 && kStCols == 64 && kStLine % 64 == 0,
               "the phase hand-over: four waves, 16 rows each per block of 64");
 
 struct StageArgs {
     const float* f;
-    float* vp;          // 4 row-major planes of H rows: V_ch[y * Wp + kStMargin + x]
+    float* vp;          // 4 row-major planes of H rows: V_ch[y * Wp + margin + x]
     float* den_t;       // column-major accumulators
     float* num_t;
     float* out;
     float* eta;
     int H, W, R, nb;
     int r[BF_MAX_BOXES];
-    int Wp;             // V row pitch: W rounded up to a multiple of 4, plus two margins
+    int Wp;             // V row pitch: W + 260 rounded up to a multiple of 64
+    int margin;         // left margin: kStMargin + R mod 4, so margin - R is a multiple of 4
     int nout_v;         // outputs per vertical line: min(256 - 2R, kStOutV)
     int nout_h;         // outputs per horizontal line: min(256 - 2R, kStOutH), multiple of 4
-    int xshift;         // horizontal block b starts at column b nout_h - xshift
     int centre;         // this pair is m = 0 (channels 1, g)
     float c;            // c_m
     double malpha;      // m a
@@ -144,7 +144,7 @@ bf_stage_v(const StageArgs a) {
     }
     if (ch < nch && x < a.W) {   // columns past W stay zero: they are the margin
         for (int b = 0; b < a.nb; ++b) box_dispatch<kStLine, true>(v, a.r[b]);
-        float* dst = a.vp + (size_t)ch * a.H * a.Wp + kStMargin + x;
+        float* dst = a.vp + (size_t)ch * a.H * a.Wp + a.margin + x;
 #pragma unroll
         for (int y0c = 0; y0c < kStOutV; y0c += kChunk) {
             if (y0c < a.nout_v) {   // uniform
@@ -171,8 +171,8 @@ bf_stage_h(const StageArgs a) {
     const int lane = t & 63;
     const int yb = blockIdx.y * kStRows;
     const int y = yb + lane;
-    const int x0 = blockIdx.x * a.nout_h - a.xshift;   // may be negative in the first block
-    const int ex0 = x0 - a.R;                           // a multiple of 4
+    const int x0 = blockIdx.x * a.nout_h;
+    const int ex0 = x0 - a.R;   // margin + ex0 is a multiple of 4
     const int yc = min(y, a.H - 1);
     for (int p0 = t; p0 < kStRows * kStOutH; p0 += 8 * kStThreads) {
         float v8[8];
@@ -218,6 +218,7 @@ bf_stage_h(const StageArgs a) {
         // inside the left margin; samples past the row's end belong to
         // positions no kept output reads (or come back as zero past the
         // resource).  Rows past H read row H - 1 and are never stored.
+        const int ms = __builtin_amdgcn_readfirstlane(a.margin);
         const int Hs = __builtin_amdgcn_readfirstlane(a.H);
         const int Wps = __builtin_amdgcn_readfirstlane(a.Wp);
         const int e0 = __builtin_amdgcn_readfirstlane(ex0);
@@ -229,7 +230,7 @@ bf_stage_h(const StageArgs a) {
         const int voff = (yc - yb) * Wps * (int)sizeof(float);
 #pragma unroll
         for (int k = 0; k < kStLine / 4; ++k) {
-            const int soff = (kStMargin + e0 + 4 * k) * (int)sizeof(float);   // uniform
+            const int soff = (ms + e0 + 4 * k) * (int)sizeof(float);   // uniform
             const auto q = __builtin_amdgcn_raw_buffer_load_b128(rs, voff, soff, 0);
             v[4 * k] = __uint_as_float(q[0]);
             v[4 * k + 1] = __uint_as_float(q[1]);
@@ -281,16 +282,15 @@ __global__ void bf_stage_zero(float* p, size_t n) {
 }
 
 // Zeroes the columns of the V planes that the vertical pass never writes:
-// kStMargin on the left, and the padding and kStMargin on the right of
-// every row (Wp - W per row, 4 H rows).
-__global__ void bf_stage_margins(float* vp, int H, int W, int Wp) {
+// [0, margin) and [margin + W, Wp) of every row (Wp - W per row, 4 H rows).
+__global__ void bf_stage_margins(float* vp, int H, int W, int Wp, int margin) {
     const size_t per_row = (size_t)(Wp - W);
     const size_t n = (size_t)4 * H * per_row;
     for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
          i += (size_t)gridDim.x * blockDim.x) {
         const size_t row = i / per_row;
         const int j = (int)(i - row * per_row);
-        const int col = j < kStMargin ? j : W + j;
+        const int col = j < margin ? j : W + j;
         vp[row * Wp + col] = 0.0f;
     }
 }
@@ -323,7 +323,10 @@ bf_stage_final(const StageArgs a) {
     }
 }
 
-static int staged_pitch(int64_t W) { return (int)((W + 3) / 4 * 4 + 2 * kStMargin); }
+// margin <= kStMargin + 3 columns on the left, at least kStMargin on the
+// right, rows starting on 256-byte boundaries (a pitch off those boundaries
+// measured 14 % slower on the 4096^2 workload)
+static int staged_pitch(int64_t W) { return (int)((W + 2 * kStMargin + 4 + 63) / 64 * 64); }
 
 // nout_h for the sum of radii R: at most 256 - 2R (every kept output sees its
 // whole box in the line) and a multiple of 4 (16-byte aligned lines).
@@ -341,7 +344,7 @@ bool staged_supported(const SpatialParams& sp) {
 
 // Cost model, per cosine pair, calibrated on MI355X (2048^2, N = 66): a round
 // of fused tiles (one workgroup per CU) takes about 16 us whatever the tile
-// size, a round of staged workgroups about 27 us in either pass.  The fused
+// size, a round of staged workgroups about 30 us in either pass.  The fused
 // tiles shrink as R grows (the extended line is at most 128 samples), so
 // past R of about 50 the staged passes are faster.
 bool prefer_staged(int64_t H, int64_t W, const SpatialParams& sp, bf_status fused_status,
@@ -361,9 +364,9 @@ bool prefer_staged(int64_t H, int64_t W, const SpatialParams& sp, bf_status fuse
     const int nout_v = std::min(kStLine - 2 * sp.R, kStOutV);
     const int nout_h = staged_nout_h(sp.R);
     const double bv = std::ceil((double)W / kStCols) * std::ceil((double)H / nout_v);
-    const double bh = std::ceil((double)(W + 3) / nout_h) * std::ceil((double)H / kStRows);
+    const double bh = std::ceil((double)W / nout_h) * std::ceil((double)H / kStRows);
     const double fused_us = rounds((double)g.tiles_x * g.tiles_y) * 16.0;
-    const double staged_us = (rounds(bv) + rounds(bh)) * 27.0;
+    const double staged_us = (rounds(bv) + rounds(bh)) * 30.0;
     return staged_us < fused_us;
 }
 
@@ -388,17 +391,18 @@ bf_status launch_staged(const float* f, float* out, float* eta, int64_t H, int64
     for (int k = 0; k < BF_MAX_BOXES; ++k) a.r[k] = sp.r[k];
     a.nout_v = std::min(kStLine - 2 * sp.R, kStOutV);
     a.nout_h = staged_nout_h(sp.R);
-    a.xshift = (4 - sp.R % 4) % 4;   // block 0 starts at -xshift: x0 - R is a multiple of 4
+    a.margin = kStMargin + sp.R % 4;   // margin + x0 - R is a multiple of 4 for x0 = b nout_h
     a.center = rp.center;
     // g tile, then the phase hand-over
     const size_t lds_v = ((size_t)kStLine * kStCols + (size_t)4 * 64 * kStCols) * sizeof(float);
     (void)hipFuncSetAttribute((const void*)bf_stage_v, hipFuncAttributeMaxDynamicSharedMemorySize,
                               (int)lds_v);
     hipLaunchKernelGGL(bf_stage_zero, dim3(1024), dim3(256), 0, stream, a.den_t, 2 * HW);
-    hipLaunchKernelGGL(bf_stage_margins, dim3(1024), dim3(256), 0, stream, a.vp, a.H, a.W, a.Wp);
+    hipLaunchKernelGGL(bf_stage_margins, dim3(1024), dim3(256), 0, stream, a.vp, a.H, a.W, a.Wp,
+                       a.margin);
     const dim3 gv((unsigned)((W + kStCols - 1) / kStCols),
                   (unsigned)((H + a.nout_v - 1) / a.nout_v));
-    const dim3 gh((unsigned)((W + a.xshift + a.nout_h - 1) / a.nout_h),
+    const dim3 gh((unsigned)((W + a.nout_h - 1) / a.nout_h),
                   (unsigned)((H + kStRows - 1) / kStRows));
     for (int q = 0; q < rp.npairs; ++q) {
         const int m = rp.odd + 2 * q;

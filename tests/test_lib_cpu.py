@@ -164,7 +164,7 @@ def test_workspace_query_and_staged_validation():
     (BF_EINVAL) and a request for the adjoint's sums (BF_EUNSUPPORTED)."""
     assert nat.workspace_bytes(64, 80, [9, 9, 10]) == 0
     def staged(H, W):   # four channel planes with 128-column zero margins, den, num
-        return 4 * (4 * H * ((W + 3) // 4 * 4 + 256) + 2 * H * W)
+        return 4 * (4 * H * ((W + 260 + 63) // 64 * 64) + 2 * H * W)
     # R = 63 still fits the fused kernel, but its tiles are 2 x 2 there: the
     # cost model may ask for the staged workspace (the forward falls back to
     # the fused kernel without it)
