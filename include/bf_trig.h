@@ -196,6 +196,16 @@ bf_status bf_direct_forward(const float* f, int64_t H, int64_t W, float T, float
                             const bf_spatial_spec* spatial_spec, float* out,
                             const bf_opts* opts);
 
+/* Debug helper for the precondition of Sec. 2.1 (intensities in [0, T], which
+ * keeps the raised-cosine kernel non-negative; the filters do not test it).
+ * Writes to *count_dev (device memory, one uint32, caller-owned) the number
+ * of pixels of the H x W device image f that lie outside [0, T] or are NaN.
+ * Asynchronous on stream (a hipStream_t; NULL = the null stream): the count
+ * is valid once the stream has reached this call.  BF_EINVAL for a NULL
+ * pointer, a non-positive size or T not positive and finite. */
+bf_status bf_check_range(const float* f, int64_t H, int64_t W, float T, uint32_t* count_dev,
+                         void* stream);
+
 /* ---- batches of images of different sizes and parameters ------------------
  * For callers that filter many images (e.g. the colour channels of Fig. 4 or
  * a training batch) in one launch.  A plan fixes the images' sizes and

@@ -13,7 +13,7 @@ without the native library or a GPU.
 import importlib
 
 __all__ = ["bf_trig", "trig_forward", "trig_backward", "sv_forward", "yvv_forward",
-           "direct_forward", "BFTrig",
+           "direct_forward", "check_range", "BFTrig",
            "range_degree", "range_coeffs", "range_truncate", "spatial_gaussian", "BatchPlan",
            "trig_forward_channels", "synth"]
 
@@ -22,6 +22,7 @@ _LAZY = {
     "trig_forward": ("ops", "trig_forward"),
     "trig_backward": ("ops", "trig_backward"),
     "direct_forward": ("ops", "direct_forward"),
+    "check_range": ("ops", "check_range"),
     "sv_forward": ("ops", "sv_forward"),
     "yvv_forward": ("ops", "yvv_forward"),
     "BFTrig": ("ops", "BFTrig"),

@@ -24,7 +24,7 @@ STATUS = {0: "BF_OK", 1: "BF_EINVAL", 2: "BF_ERANGE", 3: "BF_ENOMEM", 4: "BF_EDE
 EXPORTS = ["bf_range_degree", "bf_range_coeffs", "bf_range_truncate", "bf_spatial_gaussian",
            "bf_trig_workspace_bytes", "bf_trig_forward",
            "bf_trig_forward_ex", "bf_trig_backward", "bf_sv_forward",
-           "bf_yvv_workspace_bytes", "bf_yvv_forward", "bf_direct_forward",
+           "bf_yvv_workspace_bytes", "bf_yvv_forward", "bf_direct_forward", "bf_check_range",
            "bf_batch_plan_create", "bf_batch_bind", "bf_batch_launch", "bf_batch_check",
            "bf_batch_plan_destroy", "bf_status_string", "bf_last_error"]
 
@@ -97,6 +97,7 @@ def lib():
         "bf_yvv_workspace_bytes": [i64, i64, f32, f32, i32, ctypes.POINTER(i64)],
         "bf_yvv_forward": [vp, i64, i64, f32, f32, f32, vp, op],
         "bf_direct_forward": [vp, i64, i64, f32, f32, sp, vp, op],
+        "bf_check_range": [vp, i64, i64, f32, vp, vp],
         "bf_batch_plan_create": [ctypes.POINTER(ImageDesc), i32, ctypes.POINTER(vp)],
         "bf_batch_bind": [vp, ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(vp),
                           ctypes.POINTER(vp), ctypes.POINTER(vp), vp],

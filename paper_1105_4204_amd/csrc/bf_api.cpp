@@ -1,6 +1,8 @@
 // extern "C" entry points of libbftrig: argument validation, parameter
 // derivation and dispatch to the HIP kernels.  Nothing here allocates on the
 // single-image paths, so they may be captured into a hipGraph.
+#include <cmath>
+
 #include "bf_internal.h"
 
 using namespace bf;
@@ -134,6 +136,21 @@ bf_status bf_direct_forward(const float* f, int64_t H, int64_t W, float T, float
         return BF_EINVAL;
     }
     return launch_direct(f, out, eta, H, W, c.rp, c.sp, c.stream);
+}
+
+bf_status bf_check_range(const float* f, int64_t H, int64_t W, float T, uint32_t* count_dev,
+                         void* stream) {
+    bf_status st = check_image(f, H, W, "f");
+    if (st != BF_OK) return st;
+    if (!count_dev) {
+        set_error("count_dev is NULL");
+        return BF_EINVAL;
+    }
+    if (!(T > 0.0f) || !std::isfinite(T)) {
+        set_error("T=%g must be positive and finite", (double)T);
+        return BF_EINVAL;
+    }
+    return launch_check_range(f, H, W, T, count_dev, static_cast<hipStream_t>(stream));
 }
 
 bf_status bf_sv_forward(const float* f, const int32_t* radius, int64_t H, int64_t W, float T,

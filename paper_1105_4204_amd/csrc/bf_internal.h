@@ -69,6 +69,9 @@ bf_status plan_fwd_tiles(int64_t H, int64_t W, const SpatialParams& sp, int req_
 bf_status launch_fwd(const float* f, float* out, float* eta, float* aux, int64_t H, int64_t W,
                      const RangeParams& rp, const SpatialParams& sp, const TileGeom& g,
                      hipStream_t stream);
+// Count of pixels outside [0, T] (NaN included) into a device counter (bf_check.hip).
+bf_status launch_check_range(const float* f, int64_t H, int64_t W, float T, unsigned* count,
+                             hipStream_t stream);
 bf_status launch_direct(const float* f, float* out, float* eta, int64_t H, int64_t W,
                         const RangeParams& rp, const SpatialParams& sp, hipStream_t stream);
 bf_status plan_bwd_tiles(int64_t H, int64_t W, const SpatialParams& sp, int req_h, int req_w,

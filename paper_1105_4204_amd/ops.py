@@ -53,6 +53,17 @@ def trig_forward(f: torch.Tensor, T: float, sigma_r: float, radii, N: int = 0,
     return (out, eta) if return_eta else out
 
 
+def check_range(f: torch.Tensor, T: float) -> int:
+    """Number of pixels of f outside [0, T] or NaN (the input precondition of
+    the filter, which the kernels do not test); synchronises the stream."""
+    _check_img(f, "f")
+    H, W = f.shape
+    count = torch.empty(1, dtype=torch.int32, device=f.device)
+    nat.check(nat.lib().bf_check_range(_ptr(f), H, W, float(T), _ptr(count), _stream_ptr()),
+              "bf_check_range")
+    return int(count.item()) & 0xFFFFFFFF
+
+
 def direct_forward(f: torch.Tensor, T: float, sigma_r: float, radii, N: int = 0,
                    return_eta: bool = False):
     """Direct-window (O((2R+1)^2) per pixel) filter on the GPU."""

@@ -308,3 +308,13 @@ def test_yvv_forward_validates_before_any_launch():
     assert call(65.0, ws, need) == 2               # above 64
     assert call(3.0, ws, need - 4) == 1            # workspace too small
     assert call(3.0, ctypes.c_void_p(0x100000 + 64), need) == 1   # workspace overlaps f
+
+
+def test_check_range_validation():
+    """The range-check helper rejects bad arguments before any launch."""
+    L = nat.lib()
+    assert L.bf_check_range(None, 8, 8, 255.0, FAKE2, None) == 1      # f NULL
+    assert L.bf_check_range(FAKE, 8, 8, 255.0, None, None) == 1       # counter NULL
+    assert L.bf_check_range(FAKE, 0, 8, 255.0, FAKE2, None) == 1      # empty image
+    assert L.bf_check_range(FAKE, 8, 8, 0.0, FAKE2, None) == 1        # T not positive
+    assert L.bf_check_range(FAKE, 8, 8, float("inf"), FAKE2, None) == 1
