@@ -39,6 +39,7 @@ constexpr int kSvMaxR = 31;                    // largest half-width
 constexpr int kSvMaxE = kSvTile + 2 * 32;      // extended side with Rm rounded up to 32
 constexpr int kSvOwn = (kSvMaxE * kSvMaxE + kSvThreads - 1) / kSvThreads;   // 36
 constexpr int kSvOut = kSvTile * kSvTile / kSvThreads;                      // 4
+constexpr size_t kSvLdsPerCu = 160 * 1024;   // LDS of one CU
 
 struct SvArgs {
     const float* f;
@@ -59,7 +60,10 @@ __host__ __device__ inline size_t sv_lds_bytes(int E) {
     return (size_t)E * E * sizeof(float) + (size_t)(E + 1) * (E + 1) * sizeof(double);
 }
 
-__global__ void __launch_bounds__(kSvThreads) bf_sv_kernel(const SvArgs a) {
+// MINW waves per SIMD: 2 when two workgroups' tables fit the CU's LDS
+// (at most 256 registers a lane, a few spilled), else 1.
+template <int MINW>
+__global__ void __launch_bounds__(kSvThreads, MINW) bf_sv_kernel(const SvArgs a) {
     extern __shared__ __align__(16) float smem[];
     const int E = a.E, Sp = a.E + 1, EE = a.E * a.E;
     float* stg = smem;                                          // E x E, pitch E
@@ -244,10 +248,16 @@ bf_status launch_sv(const float* f, const int32_t* rmap, float* out, float* eta,
     a.center = rp.center;
     for (int q = 0; q < rp.npairs; ++q) a.chat[q] = rp.chat[q];
     const size_t lds = sv_lds_bytes(a.E);
-    (void)hipFuncSetAttribute((const void*)bf_sv_kernel,
-                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    hipLaunchKernelGGL(bf_sv_kernel, dim3((unsigned)(a.tiles_x * tiles_y)), dim3(kSvThreads),
-                       lds, stream, a);
+    const dim3 grid((unsigned)(a.tiles_x * tiles_y));
+    if (2 * lds <= kSvLdsPerCu) {   // two workgroups per CU (rmax up to 24)
+        (void)hipFuncSetAttribute((const void*)bf_sv_kernel<2>,
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        hipLaunchKernelGGL(bf_sv_kernel<2>, grid, dim3(kSvThreads), lds, stream, a);
+    } else {
+        (void)hipFuncSetAttribute((const void*)bf_sv_kernel<1>,
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        hipLaunchKernelGGL(bf_sv_kernel<1>, grid, dim3(kSvThreads), lds, stream, a);
+    }
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) {
         set_error("space-variant forward launch failed: %s", hipGetErrorString(e));
