@@ -137,10 +137,20 @@ def _sample_idx(H, W, R, eta, n_rand, seed):
     for j in list(range(0, R + 1)) + list(range(W - R - 1, W)):
         for i in rng.integers(0, H, size=4):
             idx.add(int(i) * W + int(j))
+    # all pixels within R of the border on two random 64-pixel stretches
+    # (one along the top edge, one along the right edge)
+    c0 = int(rng.integers(0, max(W - 64, 1)))
+    r0 = int(rng.integers(0, max(H - 64, 1)))
+    for i in range(min(R + 1, H)):
+        for j in range(c0, min(c0 + 64, W)):
+            idx.add(i * W + j)
+    for i in range(r0, min(r0 + 64, H)):
+        for j in range(max(W - R - 1, 0), W):
+            idx.add(i * W + j)
     for c in [0, W - 1, (H - 1) * W, H * W - 1]:
         idx.add(c)
     # where the expansion cancels most: smallest eta
-    idx.update(np.argsort(eta.reshape(-1))[:400].tolist())
+    idx.update(np.argsort(eta.reshape(-1))[:1000].tolist())
     return np.array(sorted(idx), dtype=np.int64)
 
 
@@ -157,7 +167,7 @@ def test_full_size_sampled_parity(cfg):
     torch.cuda.synchronize()
     out, eta = out.cpu().numpy(), eta.cpu().numpy()
     H, W = f.shape
-    idx = _sample_idx(H, W, sum(radii), eta, 3000, seed=cfg)
+    idx = _sample_idx(H, W, sum(radii), eta, 65536, seed=cfg)
     ref, eta_ref = oracle.forward_at(f, sr, N, radii, idx, return_eta=True)
     _check(out.reshape(-1)[idx], ref, f"config{cfg} sampled ({idx.size} px)")
     rel = np.abs(eta.reshape(-1)[idx] - eta_ref) / eta_ref

@@ -64,8 +64,10 @@ def test_staged_rejects_adjoint_sums():
 
 def test_wide_kernel_workload_sampled():
     """4096 x 4096 piecewise-smooth image (seed 3), sigma_s = 30 realised as
-    boxes (29, 29, 30), sigma_r = 10, N = 264: 64 random pixels, the 16
-    pixels of smallest eta and the four corners against the oracle."""
+    boxes (29, 29, 30), sigma_r = 10, N = 264: 65536 random pixels, the 1000
+    pixels of smallest eta, every pixel within R of the border on a 64-pixel
+    stretch of the top and of the left edge, and the four corners, against
+    the oracle."""
     from paper_1105_4204_amd import _native as nat
     f_np = synth.config_image(3)
     radii = nat.spatial_gaussian(30.0, 3)
@@ -78,7 +80,11 @@ def test_wide_kernel_workload_sampled():
     e = eta.cpu().numpy().reshape(-1)
     rng = np.random.default_rng(33)
     H = W = 4096
-    idx = np.concatenate([rng.integers(0, H * W, size=64), np.argsort(e)[:16],
-                          np.array([0, W - 1, (H - 1) * W, H * W - 1])])
+    R = sum(radii)
+    c0, r0 = int(rng.integers(0, W - 64)), int(rng.integers(0, H - 64))
+    top = [i * W + j for i in range(R + 1) for j in range(c0, c0 + 64)]
+    left = [i * W + j for i in range(r0, r0 + 64) for j in range(R + 1)]
+    idx = np.unique(np.concatenate([rng.integers(0, H * W, size=65536), np.argsort(e)[:1000],
+                                    np.array(top + left + [0, W - 1, (H - 1) * W, H * W - 1])]))
     ref = oracle.forward_at(f_np, 10.0, N, radii, idx)
     _check(o[idx], ref, "4096^2 sigma_s=30 N=264 sampled")
