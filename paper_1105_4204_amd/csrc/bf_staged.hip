@@ -351,15 +351,13 @@ bool prefer_staged(int64_t H, int64_t W, const SpatialParams& sp, bf_status fuse
                    const TileGeom& g) {
     if (!staged_supported(sp)) return false;
     if (fused_status != BF_OK) return true;
-    static int cus = 0;
-    if (cus == 0) {
-        int dev = 0;
-        if (hipGetDevice(&dev) != hipSuccess ||
-            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) !=
-                hipSuccess ||
-            cus <= 0)
-            cus = 256;
-    }
+    // compute units of the current device (queried per call: no shared state
+    // between threads or devices)
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        cus <= 0)
+        cus = 256;
     auto rounds = [&](double blocks) { return std::ceil(blocks / cus); };
     const int nout_v = std::min(kStLine - 2 * sp.R, kStOutV);
     const int nout_h = staged_nout_h(sp.R);
