@@ -334,7 +334,7 @@ def main():
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print(json.dumps({"error": "this build measures one GPU: the filter would shard by image "
+        print(json.dumps({"error": "this benchmark measures one GPU: the filter would shard by image "
                                    "(batches) or by row strips with an R-row halo (single "
                                    "images), but no multi-GPU path is built; run with --gpus 1"}),
               flush=True)

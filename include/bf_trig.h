@@ -47,7 +47,7 @@ typedef enum {
     BF_ENOMEM = 3,       /* device or host allocation failed */
     BF_EDEVICE = 4,      /* HIP runtime / launch error */
     BF_ECAPTURE = 5,     /* call not allowed while the stream is being captured */
-    BF_EUNSUPPORTED = 6  /* valid request outside what this build implements */
+    BF_EUNSUPPORTED = 6  /* valid request outside what the library implements */
 } bf_status;
 
 #define BF_MAX_BOXES 4      /* iterated boxes per axis */

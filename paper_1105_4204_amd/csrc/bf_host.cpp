@@ -396,7 +396,7 @@ const char* bf_status_string(bf_status s) {
         case BF_ENOMEM: return "BF_ENOMEM: out of memory";
         case BF_EDEVICE: return "BF_EDEVICE: HIP runtime error";
         case BF_ECAPTURE: return "BF_ECAPTURE: not allowed during stream capture";
-        case BF_EUNSUPPORTED: return "BF_EUNSUPPORTED: not supported by this build";
+        case BF_EUNSUPPORTED: return "BF_EUNSUPPORTED: not supported by this library";
     }
     return "unknown bf_status";
 }

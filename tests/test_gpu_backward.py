@@ -1,9 +1,9 @@
 """GPU parity of the fused adjoint kernel against the FP64 oracle.
 
 The oracle's gradient is the exact derivative of the direct window sum; it is
-itself pinned by finite differences in test_oracle_grad.  Tolerance (no value
-is given by the paper or the benchmark spec; derived from the FP32 arithmetic of
-the forward, whose outputs feed the adjoint): per pixel
+itself pinned by finite differences in test_oracle_grad.  Tolerance (the
+paper gives none for the gradient; derived from the FP32 arithmetic of the
+forward, whose outputs feed the adjoint): per pixel
 |g - g_ref| <= 1e-3 * max|g_ref| + 1e-3 * |g_ref|.
 """
 import numpy as np
