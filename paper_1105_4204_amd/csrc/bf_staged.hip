@@ -36,9 +36,11 @@ constexpr int kStThreads = 256;   // four waves: one per channel of a pair
 constexpr int kStCols = 64;       // vertical pass: columns per workgroup
 constexpr int kStOutV = 88;       // vertical pass: outputs per line, at most
 constexpr int kStRows = 64;       // horizontal pass: rows per workgroup
-constexpr int kStOutH = 64;       // horizontal pass: outputs per line, at most
+constexpr int kStOutH = 128;      // horizontal pass: outputs per line, at most
+constexpr int kStHalf = 64;       // horizontal pass: outputs per hand-over round
 constexpr int kStMargin = 128;    // zero columns at least on each side of a V row (>= R)
-static_assert(kStOutH % 4 == 0, "the four waves share the output columns");
+static_assert(kStHalf % 4 == 0 && kStOutH == 2 * kStHalf,
+              "the four waves share the output columns of a round; two rounds at most");
 static_assert(kStThreads == 256 && kStCols == 64 && kStLine % 64 == 0,
               "the phase hand-over: four waves, 16 rows each per block of 64");
 
@@ -161,11 +163,14 @@ bf_stage_v(const StageArgs a) {
 // Horizontal pass.  Workgroup: 64 rows x nout_h output columns; wave w
 // filters channel w along its rows, demodulates with C or S at the outputs,
 // and the four contributions are summed in a fixed order into den and num.
+// ROUNDS: hand-over rounds of kStHalf outputs (1 when nout_h <= kStHalf).
+template <int ROUNDS>
 __global__ void __launch_bounds__(kStThreads) __attribute__((amdgpu_waves_per_eu(1, 1)))
 bf_stage_h(const StageArgs a) {
+    constexpr int kOut = ROUNDS * kStHalf;   // outputs per line at most
     __shared__ float gt[kStRows][kStOutH + 1];
-    __shared__ float red[4][kStOutH][kStRows + 1];
-    __shared__ float csm[2][kStOutH][kStRows + 1];   // C and S at the outputs
+    __shared__ float red[4][kStHalf][kStRows + 1];
+    __shared__ float csm[2][kStHalf][kStRows + 1];   // C and S at a round's outputs
     const int t = threadIdx.x;
     const int wave = __builtin_amdgcn_readfirstlane(t >> 6);
     const int lane = t & 63;
@@ -174,43 +179,30 @@ bf_stage_h(const StageArgs a) {
     const int x0 = blockIdx.x * a.nout_h;
     const int ex0 = x0 - a.R;   // margin + ex0 is a multiple of 4
     const int yc = min(y, a.H - 1);
-    for (int p0 = t; p0 < kStRows * kStOutH; p0 += 8 * kStThreads) {
+    for (int p0 = t; p0 < kStRows * kOut; p0 += 8 * kStThreads) {
         float v8[8];
 #pragma unroll
         for (int u = 0; u < 8; ++u) {
             const int p = p0 + u * kStThreads;
-            const int yy = p / kStOutH, k = p - yy * kStOutH;
+            const int yy = p / kOut, k = p - yy * kOut;
             const int Y = min(yb + yy, a.H - 1), X = min(max(x0 + k, 0), a.W - 1);
             v8[u] = a.f[(size_t)Y * a.W + X];
         }
 #pragma unroll
         for (int u = 0; u < 8; ++u) {
             const int p = p0 + u * kStThreads;
-            const int yy = p / kStOutH, k = p - yy * kStOutH;
+            const int yy = p / kOut, k = p - yy * kOut;
             const int Y = yb + yy, X = x0 + k;
-            if (p < kStRows * kStOutH)
+            if (p < kStRows * kOut)
                 gt[yy][k] = (Y < a.H && X >= 0 && X < a.W && k < a.nout_h) ? v8[u] - a.center
                                                                             : 0.0f;
         }
     }
     __syncthreads();
-    if (!a.centre) {
-        // the phase at the outputs, once per pixel: wave w evaluates the
-        // output columns 16 w .. 16 w + 15 of every row (the flag is uniform)
-#pragma unroll
-        for (int u = 0; u < kStOutH / 4; ++u) {
-            const int k = wave * (kStOutH / 4) + u;
-            float cc, ss;
-            cis_direct(a.malpha, gt[lane][k], cc, ss);
-            csm[0][k][lane] = cc;
-            csm[1][k][lane] = ss;
-        }
-        __syncthreads();
-    }
     const int nch = a.centre ? 2 : 4;
     const int ch = wave;
+    float v[kStLine];
     if (ch < nch) {
-        float v[kStLine];
         // 16-byte buffer loads along the lane's row of V_ch: the row (from
         // the workgroup's first) is the vector offset, the wave-uniform
         // column the scalar offset; the resource spans the workgroup's rows.
@@ -238,40 +230,67 @@ bf_stage_h(const StageArgs a) {
             v[4 * k + 3] = __uint_as_float(q[3]);
         }
         for (int b = 0; b < a.nb; ++b) box_dispatch<kStLine, true>(v, a.r[b]);
-        if (a.centre) {
-#pragma unroll
-            for (int k = 0; k < kStOutH; ++k) red[ch][k][lane] = a.c * v[k];
-        } else {
-            const int cs = ch >= 2 ? 1 : 0;
-#pragma unroll
-            for (int k = 0; k < kStOutH; ++k) red[ch][k][lane] = a.c * v[k] * csm[cs][k][lane];
-        }
     }
-    __syncthreads();
-    // fixed-order sums: den = (C F[C] + S F[S]), num = (C F[gC] + S F[gS]);
-    // wave w updates the output columns 16 w .. 16 w + 15 of its rows, the
-    // loads of all 16 first (clamped, unconditional), then the stores
-    if (y < a.H) {
-        constexpr int kPer = kStOutH / 4;
-        float d16[kPer], n16[kPer];
+    // The outputs are handed over in rounds of kStHalf columns (the LDS
+    // arrays hold one round); every test below is uniform, so all four
+    // waves pass the barriers.
 #pragma unroll
-        for (int u = 0; u < kPer; ++u) {
-            const int k = wave * kPer + u;
-            const size_t idx = (size_t)min(max(x0 + k, 0), a.W - 1) * a.H + y;
-            d16[u] = a.den_t[idx];
-            n16[u] = a.num_t[idx];
+    for (int h = 0; h < ROUNDS; ++h) {
+        const int k0 = h * kStHalf;
+        if (k0 >= a.nout_h) break;
+        if (!a.centre) {
+            // the phase at the round's outputs, once per pixel: wave w
+            // evaluates columns k0 + 16 w .. k0 + 16 w + 15 of every row
+#pragma unroll
+            for (int u = 0; u < kStHalf / 4; ++u) {
+                const int kk = wave * (kStHalf / 4) + u;
+                float cc, ss;
+                cis_direct(a.malpha, gt[lane][k0 + kk], cc, ss);
+                csm[0][kk][lane] = cc;
+                csm[1][kk][lane] = ss;
+            }
+            __syncthreads();
         }
+        if (ch < nch) {
+            if (a.centre) {
 #pragma unroll
-        for (int u = 0; u < kPer; ++u) {
-            const int k = wave * kPer + u;
-            const int X = x0 + k;
-            if (k < a.nout_h && X >= 0 && X < a.W) {
-                const float d = a.centre ? red[0][k][lane] : red[0][k][lane] + red[2][k][lane];
-                const float n = a.centre ? red[1][k][lane] : red[1][k][lane] + red[3][k][lane];
-                a.den_t[(size_t)X * a.H + y] = d16[u] + d;
-                a.num_t[(size_t)X * a.H + y] = n16[u] + n;
+                for (int kk = 0; kk < kStHalf; ++kk) red[ch][kk][lane] = a.c * v[k0 + kk];
+            } else {
+                const int cs = ch >= 2 ? 1 : 0;
+#pragma unroll
+                for (int kk = 0; kk < kStHalf; ++kk)
+                    red[ch][kk][lane] = a.c * v[k0 + kk] * csm[cs][kk][lane];
             }
         }
+        __syncthreads();
+        // fixed-order sums: den = (C F[C] + S F[S]), num = (C F[gC] + S F[gS]);
+        // wave w updates the round's columns 16 w .. 16 w + 15 of its rows,
+        // the loads of all 16 first (clamped, unconditional), then the stores
+        if (y < a.H) {
+            constexpr int kPer = kStHalf / 4;
+            float d16[kPer], n16[kPer];
+#pragma unroll
+            for (int u = 0; u < kPer; ++u) {
+                const int k = k0 + wave * kPer + u;
+                const size_t idx = (size_t)min(max(x0 + k, 0), a.W - 1) * a.H + y;
+                d16[u] = a.den_t[idx];
+                n16[u] = a.num_t[idx];
+            }
+#pragma unroll
+            for (int u = 0; u < kPer; ++u) {
+                const int kk = wave * kPer + u, k = k0 + kk;
+                const int X = x0 + k;
+                if (k < a.nout_h && X >= 0 && X < a.W) {
+                    const float d =
+                        a.centre ? red[0][kk][lane] : red[0][kk][lane] + red[2][kk][lane];
+                    const float n =
+                        a.centre ? red[1][kk][lane] : red[1][kk][lane] + red[3][kk][lane];
+                    a.den_t[(size_t)X * a.H + y] = d16[u] + d;
+                    a.num_t[(size_t)X * a.H + y] = n16[u] + n;
+                }
+            }
+        }
+        __syncthreads();   // the next round rewrites csm and red
     }
 }
 
@@ -329,8 +348,15 @@ bf_stage_final(const StageArgs a) {
 static int staged_pitch(int64_t W) { return (int)((W + 2 * kStMargin + 4 + 63) / 64 * 64); }
 
 // nout_h for the sum of radii R: at most 256 - 2R (every kept output sees its
-// whole box in the line) and a multiple of 4 (16-byte aligned lines).
-static int staged_nout_h(int R) { return std::min(kStLine - 2 * R, kStOutH) / 4 * 4; }
+// whole box in the line), a multiple of 4 (16-byte aligned lines), and one
+// or two whole hand-over rounds where the line allows: a partial second
+// round costs as much as a full one (sigma_s 30 at 2048^2: 80 outputs per
+// line measured 7.8 ms, 64 outputs 7.2 ms).
+static int staged_nout_h(int R) {
+    const int room = kStLine - 2 * R;
+    if (room >= kStOutH) return kStOutH;
+    return std::min(room, kStHalf) / 4 * 4;
+}
 
 size_t staged_workspace_bytes(int64_t H, int64_t W) {
     return ((size_t)4 * (size_t)H * (size_t)staged_pitch(W) + (size_t)2 * H * W) * sizeof(float);
@@ -408,7 +434,10 @@ bf_status launch_staged(const float* f, float* out, float* eta, int64_t H, int64
         a.c = rp.chat[q];
         a.malpha = (double)m * rp.alpha;
         hipLaunchKernelGGL(bf_stage_v, gv, dim3(kStThreads), lds_v, stream, a);
-        hipLaunchKernelGGL(bf_stage_h, gh, dim3(kStThreads), 0, stream, a);
+        if (a.nout_h > kStHalf)
+            hipLaunchKernelGGL(bf_stage_h<2>, gh, dim3(kStThreads), 0, stream, a);
+        else
+            hipLaunchKernelGGL(bf_stage_h<1>, gh, dim3(kStThreads), 0, stream, a);
     }
     hipLaunchKernelGGL(bf_stage_final, dim3((unsigned)((W + 31) / 32), (unsigned)((H + 31) / 32)),
                        dim3(256), 0, stream, a);

@@ -37,6 +37,7 @@ CASES = [
     (70, 300, 20.0, 0, [31, 31, 31]),       # R = 93, taller than the image
     (1, 90, 40.0, 0, [30, 30, 10]),         # single row
     (40, 40, 12.0, 0, [31, 20, 20]),        # N = 184, image smaller than the halo
+    (100, 260, 25.0, 0, [21, 21, 22]),      # R = 64: 128 outputs per horizontal line
 ]
 
 
