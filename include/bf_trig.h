@@ -120,7 +120,7 @@ bf_status bf_spatial_gaussian(double sigma_s, int32_t n_boxes, bf_spatial_spec* 
  * channels of each cosine pair in two separable passes through this
  * workspace (Sec. 2.1, eq. (final-form)), is required (sum of radii
  * 63 < R <= 124) or faster (the fused tiles shrink as R grows; from R of
- * about 53 on a 2048^2 image).  Every radius must be <= 31;
+ * about 42 on a 2048^2 image).  Every radius must be <= 31;
  * BF_EUNSUPPORTED when neither path handles the kernel.  The staged path is
  * forward only: with aux_out set the forward uses the fused kernel, which
  * exists for R <= 63; without the workspace it also falls back to the fused

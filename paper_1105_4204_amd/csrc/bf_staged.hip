@@ -372,7 +372,7 @@ bool staged_supported(const SpatialParams& sp) {
 // of fused tiles (one workgroup per CU) takes about 16 us whatever the tile
 // size, a round of staged workgroups about 30 us in either pass.  The fused
 // tiles shrink as R grows (the extended line is at most 128 samples), so
-// past R of about 50 the staged passes are faster.
+// past R of about 42 (2048^2) the staged passes are faster.
 bool prefer_staged(int64_t H, int64_t W, const SpatialParams& sp, bf_status fused_status,
                    const TileGeom& g) {
     if (!staged_supported(sp)) return false;
