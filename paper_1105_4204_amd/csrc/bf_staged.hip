@@ -8,7 +8,7 @@
 // the |x| <= pi/4 polynomial):
 //   vertical pass   (bf_stage_v): lane = image column; a 256-sample register
 //     line down the column holds a channel (C, gC, S, gS; 1, g for m = 0)
-//     on the extended rows, the box stages run along it, and the up to 88
+//     on the extended rows, the box stages run along it, and the up to 176
 //     outputs are written to a row-major plane V_ch (consecutive lanes,
 //     consecutive columns);
 //   horizontal pass (bf_stage_h): lane = image row; a 256-sample line along
@@ -34,7 +34,8 @@ namespace bf {
 constexpr int kStLine = 256;      // register line of the staged passes
 constexpr int kStThreads = 256;   // four waves: one per channel of a pair
 constexpr int kStCols = 64;       // vertical pass: columns per workgroup
-constexpr int kStOutV = 88;       // vertical pass: outputs per line, at most
+constexpr int kStOutV = 176;      // vertical pass: outputs per line, at most (written
+                                  // straight from registers, so only the line bounds it)
 constexpr int kStRows = 64;       // horizontal pass: rows per workgroup
 constexpr int kStOutH = 128;      // horizontal pass: outputs per line, at most
 constexpr int kStHalf = 64;       // horizontal pass: outputs per hand-over round
