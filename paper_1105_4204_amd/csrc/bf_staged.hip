@@ -371,7 +371,7 @@ bool staged_supported(const SpatialParams& sp) {
 
 // Cost model, per cosine pair, calibrated on MI355X (2048^2, N = 66): a round
 // of fused tiles (one workgroup per CU) takes about 16 us whatever the tile
-// size, a round of staged workgroups about 30 us in either pass.  The fused
+// size, a round of staged workgroups about 33 us in either pass.  The fused
 // tiles shrink as R grows (the extended line is at most 128 samples), so
 // past R of about 42 (2048^2) the staged passes are faster.
 bool prefer_staged(int64_t H, int64_t W, const SpatialParams& sp, bf_status fused_status,
@@ -391,7 +391,7 @@ bool prefer_staged(int64_t H, int64_t W, const SpatialParams& sp, bf_status fuse
     const double bv = std::ceil((double)W / kStCols) * std::ceil((double)H / nout_v);
     const double bh = std::ceil((double)W / nout_h) * std::ceil((double)H / kStRows);
     const double fused_us = rounds((double)g.tiles_x * g.tiles_y) * 16.0;
-    const double staged_us = (rounds(bv) + rounds(bh)) * 30.0;
+    const double staged_us = (rounds(bv) + rounds(bh)) * 33.0;
     return staged_us < fused_us;
 }
 
