@@ -178,12 +178,16 @@ bf_status bf_sv_forward(const float* f, const int32_t* radius, int64_t H, int64_
  * (BF_ERANGE outside), over whole image lines with zero extension at both
  * ends, so the spatial kernel is the exact two-sided impulse response of the
  * passes (infinite support).  Evaluated through eq. (final-form) like the
- * forward; the filtered channels of up to 32 cosine pairs at a time pass
+ * forward; the filtered channels of up to 40 cosine pairs at a time pass
  * through opts->workspace (required; at least bf_yvv_workspace_bytes bytes,
  * device memory, not overlapping the images).  opts: stream, N, eta_out and
  * trunc_tol (the bound of bf_range_truncate with this kernel's centre tap and
  * mass); tiles and aux_out are ignored.  out must not overlap f or eta_out.
- * Asynchronous on opts->stream; no adjoint. */
+ * Asynchronous on opts->stream; no adjoint.
+ * bf_yvv_coeffs writes the line-pass coefficients for sigma_s to coeffs_out[0..4):
+ * the gain B and a1, a2, a3 of the recursions above (host only; BF_ERANGE for
+ * sigma_s outside [0.5, 64]). */
+bf_status bf_yvv_coeffs(double sigma_s, double* coeffs_out);
 bf_status bf_yvv_workspace_bytes(int64_t H, int64_t W, float T, float sigma_r, int32_t N,
                                  int64_t* bytes_out);
 bf_status bf_yvv_forward(const float* f, int64_t H, int64_t W, float T, float sigma_r,

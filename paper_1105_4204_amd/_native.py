@@ -24,7 +24,7 @@ STATUS = {0: "BF_OK", 1: "BF_EINVAL", 2: "BF_ERANGE", 3: "BF_ENOMEM", 4: "BF_EDE
 EXPORTS = ["bf_range_degree", "bf_range_coeffs", "bf_range_truncate", "bf_spatial_gaussian",
            "bf_trig_workspace_bytes", "bf_trig_forward",
            "bf_trig_forward_ex", "bf_trig_backward", "bf_sv_forward",
-           "bf_yvv_workspace_bytes", "bf_yvv_forward", "bf_direct_forward", "bf_check_range",
+           "bf_yvv_coeffs", "bf_yvv_workspace_bytes", "bf_yvv_forward", "bf_direct_forward", "bf_check_range",
            "bf_batch_plan_create", "bf_batch_bind", "bf_batch_launch", "bf_batch_check",
            "bf_batch_plan_destroy", "bf_status_string", "bf_last_error"]
 
@@ -94,6 +94,7 @@ def lib():
         "bf_trig_forward_ex": [vp, i64, i64, f32, f32, sp, vp, op],
         "bf_trig_backward": [vp, vp, vp, vp, vp, i64, i64, f32, f32, sp, vp, op],
         "bf_sv_forward": [vp, vp, i64, i64, f32, f32, i32, vp, op],
+        "bf_yvv_coeffs": [f64, ctypes.POINTER(f64)],
         "bf_yvv_workspace_bytes": [i64, i64, f32, f32, i32, ctypes.POINTER(i64)],
         "bf_yvv_forward": [vp, i64, i64, f32, f32, f32, vp, op],
         "bf_direct_forward": [vp, i64, i64, f32, f32, sp, vp, op],
@@ -175,6 +176,13 @@ def workspace_bytes(H: int, W: int, radii) -> int:
     check(lib().bf_trig_workspace_bytes(int(H), int(W), ctypes.byref(spec), ctypes.byref(n)),
           "bf_trig_workspace_bytes")
     return int(n.value)
+
+
+def yvv_coeffs(sigma_s: float):
+    """(B, a1, a2, a3) of the library's recursive-Gaussian line passes."""
+    c = (ctypes.c_double * 4)()
+    check(lib().bf_yvv_coeffs(float(sigma_s), c), "bf_yvv_coeffs")
+    return tuple(float(c[i]) for i in range(4))
 
 
 def yvv_workspace_bytes(H: int, W: int, T: float, sigma_r: float, N: int = 0) -> int:

@@ -327,6 +327,21 @@ bf_status bf_range_truncate(int32_t N, double T, const bf_spatial_spec* spatial_
     return BF_OK;
 }
 
+bf_status bf_yvv_coeffs(double sigma_s, double* coeffs_out) {
+    if (!coeffs_out) {
+        set_error("coeffs_out is NULL");
+        return BF_EINVAL;
+    }
+    YvvParams yp;
+    const bf_status st = make_yvv(sigma_s, &yp);
+    if (st != BF_OK) return st;
+    coeffs_out[0] = yp.B;
+    coeffs_out[1] = yp.a1;
+    coeffs_out[2] = yp.a2;
+    coeffs_out[3] = yp.a3;
+    return BF_OK;
+}
+
 bf_status bf_range_degree(double T, double sigma_r, int32_t* N_out) {
     if (!N_out) {
         set_error("N_out is NULL");

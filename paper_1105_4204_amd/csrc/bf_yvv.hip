@@ -31,8 +31,9 @@
 // the 66-degree workload runs as one chunk), so that no chunk is a small tail
 // with few workgroups.
 // Unlike the fused box kernel, the filtered channels of a chunk pass through
-// device memory: this path is bound by HBM traffic, about 120 bytes per pixel
-// and pair.
+// device memory: this path is bound by HBM traffic, about 108 bytes per pixel
+// and pair (24 bytes per pixel, channel and pair, plus the per-group and
+// per-chunk terms).
 #include <algorithm>
 
 #include "bf_tile.h"
