@@ -1,18 +1,22 @@
 #!/usr/bin/env python3
 """Benchmark of the O(1) trigonometric bilateral filter on one MI355X.
 
-One step = one pass of the hot path over one synthetic image: the fused
-forward kernel (degree, coefficients, phase recurrence, modulation, iterated-
-box running sums, demodulation, FP64 division) followed by the fused adjoint
-kernel for an SSD loss gradient.  Default workload: a 2048 x 2048 float32
-piecewise-smooth image, spatial Gaussian sigma_s = 10 as three boxes of radii
-9, 9, 10, sigma_r = 20 (N = 66), T = 255.
+One step = one pass of the whole hot path over one batch of synthetic input.
+Default (headline) workload: the ragged batch of 256 float32 images (H, W ~
+U{64..1024}, sigma_s ~ U[2,16] as three boxes, sigma_r ~ U[10,60], each image
+with its own degree N), forward + per-image SSD loss + adjoint, one persistent
+kernel replayed from a HIP graph with autotuned tiles.  `value` is that step's
+Mpixel/s (forward+backward).
 
-Prints ONE JSON line.  `value` is forward+backward Mpixel/s; the same line
-carries forward-only Mpixel/s, the direct-window GPU filter's Mpixel/s on the
-same image, HBM figures, the roofline of the dominant kernel (timed with HIP
-events on the launch stream) and the FP64 oracle timed on the host cores over
-a bounded sample of the same workload.
+The same JSON line carries the single-image workloads as extras: 256^2 box
+r = 5 forward; 2048^2 sigma_s = 10, sigma_r = 20 (N = 66) forward and
+forward+backward with the direct-window GPU filter beside it; 16 x 512^2
+forward+backward; 4096^2 sigma_s = 30, sigma_r = 10 (N = 264) forward; a
+sigma_s sweep at fixed N; the recursive-Gaussian and space-variant kernels.
+Every timed kernel's time comes from HIP events on its launch stream; the
+roofline of the headline's kernel (and of the extras' dominant kernels) uses
+the algorithmic operation counts per pixel; the FP64 oracle is timed on the
+host cores over a bounded sample of the headline workload.
 """
 from __future__ import annotations
 
@@ -30,6 +34,11 @@ PEAK_FP32_TFLOPS = 157.3      # MI355X vector FP32 (FMA = 2 flops)
 PEAK_HBM_GBS = 8000.0         # MI355X HBM3E
 
 METRIC = "Megapixels/s fwd and fwd+bwd at stated N vs direct GPU filter; % HBM peak"
+
+BATCH_DESC = ("256 ragged f32 images, H,W~U{64..1024}, sigma_s~U[2,16] (3 boxes), "
+              "sigma_r~U[10,60] (per-image N), same piecewise-smooth generator; forward + "
+              "per-image SSD loss + backward in one persistent kernel replayed from a HIP "
+              "graph, autotuned tiles")
 
 WORKLOADS = {
     "config2": dict(H=2048, W=2048, sigma_s=10.0, sigma_r=20.0, gen="smooth", seed=2,
@@ -52,10 +61,14 @@ WORKLOADS = {
 # x 2.0, WRITE_SIZE x 1.0 for a 512 MiB device copy); valid only for the
 # kernel sources they were taken on (hash of TILE_SOURCES).  Record:
 # profiles/bf_tile_kernels_2048x2048_N66_hbm_traffic.md.
+_TILE_PROFILE = "profiles/bf_tile_kernels_2048x2048_N66_hbm_traffic.md"
 MEASURED_TRAFFIC = {
-    ("bf_tile_kernel<kForward,false>", "config2"): {"bytes": 51079993, "src": "9da9b8efdfe2"},
-    ("bf_tile_kernel<kForward,true>", "config2"): {"bytes": 101592485, "src": "9da9b8efdfe2"},
-    ("bf_tile_kernel<kBackward,false>", "config2"): {"bytes": 217940168, "src": "9da9b8efdfe2"},
+    ("bf_tile_kernel<kForward,false>", "config2"): {"bytes": 51079993, "src": "9da9b8efdfe2",
+                                                    "profile": _TILE_PROFILE},
+    ("bf_tile_kernel<kForward,true>", "config2"): {"bytes": 101592485, "src": "9da9b8efdfe2",
+                                                   "profile": _TILE_PROFILE},
+    ("bf_tile_kernel<kBackward,false>", "config2"): {"bytes": 217940168, "src": "9da9b8efdfe2",
+                                                     "profile": _TILE_PROFILE},
 }
 TILE_SOURCES = ("bf_tile.h", "bf_box.h", "bf_tile.hip")
 
@@ -114,48 +127,6 @@ def bwd_flops_per_pixel(N: int, nb: int) -> int:
     per_pair = 6 + 2 + 16 * nb + 10 + 8
     centre = 0 if N % 2 else (4 * nb + 2)
     return full * per_pair + centre + 6
-
-
-def batch_bench(reps: int = 3):
-    """256 ragged images (H, W ~ U{64..1024}, sigma_s ~ U[2,16], sigma_r ~
-    U[10,60]): forward, per-image SSD loss and adjoint in one graph replay."""
-    import torch
-
-    from paper_1105_4204_amd import batch, synth
-    from paper_1105_4204_amd import autotune
-    specs = synth.ragged_batch_specs(256, seed=5)
-    fs, ts = synth.ragged_batch_images(specs)
-    f = [torch.from_numpy(x).cuda() for x in fs]
-    t = [torch.from_numpy(x).cuda() for x in ts]
-    del fs, ts
-    # tiles from the autotuner (cached per device, mode, radii and N bucket;
-    # tuning happens here, before the timed replays)
-    tuner = autotune.Tuner(reps=2, probe_tiles=(8, 32))
-    t0 = time.perf_counter()
-    for s in specs:
-        tuner.tune(s, "fwd")
-        tuner.tune(s, "bwd")
-    tune_s = time.perf_counter() - t0
-    plan = batch.BatchPlan(specs, tuner=tuner)
-    out, eta, gf, loss = plan.allocate()
-    plan.bind(f, t, out, eta, gf, loss)
-    g = batch.capture(plan)
-    torch.cuda.synchronize()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record()
-    for _ in range(reps):
-        g.replay()
-    e1.record()
-    torch.cuda.synchronize()
-    plan.check()
-    ms = e0.elapsed_time(e1) / reps
-    px = sum(s["H"] * s["W"] for s in specs)
-    return {"images": len(specs), "pixels": px, "ms": round(ms, 3),
-            "mpix_s_fwd_bwd": round(px / 1e6 / (ms / 1e3), 3),
-            "autotune": {"keys": len(tuner.table), "seconds": round(tune_s, 1)},
-            "desc": "256 ragged images, H,W~U{64..1024}, sigma_s~U[2,16] (3 boxes), "
-                    "sigma_r~U[10,60] (per-image N), fwd + SSD loss + bwd, one persistent "
-                    "kernel replayed from a HIP graph, tiles from the autotuner"}
 
 
 def sigma_s_sweep(f, T, sr, sigmas=(2.0, 4.0, 6.0, 10.0, 16.0, 20.0, 30.0),
@@ -226,6 +197,10 @@ def wide_config_bench(reps=2):
         torch.cuda.synchronize()
         ms = e0.elapsed_time(e1) / reps
         row = {"fwd_ms": round(ms, 2), "fwd_mpix_s": round(H * W / 1e6 / (ms / 1e3), 1)}
+        if tol == 0:
+            row["roofline"] = roofline_of(res["path"] + " forward", ms,
+                                          ops_per_pixel(N, len(radii), "fwd") * H * W,
+                                          fwd_flops_per_pixel(N, len(radii)) * H * W)
         if tol > 0:
             q, bound = _native.range_truncate(N, T, radii, tol)
             row.update({"pairs_kept": q, "error_bound_gray": bound})
@@ -289,24 +264,261 @@ def other_spatial_kernels(f, T, sr, reps=3):
     return {"recursive_gaussian": yv, "space_variant_box": sv}
 
 
-def cpu_baseline(f, sigma_r, N, radii, budget_s=12.0, max_rows=1024):
+def ops_per_pixel(N: int, nb: int, mode: str) -> int:
+    """Algorithmic VALU operations per output pixel, the count the hot-path
+    scope fixes for the roofline: forward (floor(N/2)+1)(12 + 16 nb) (phase
+    step 4, channel products 2, box adds 4 channels x 2 directions x 2 per box,
+    demodulation 6), adjoint (floor(N/2)+1)(20 + 32 nb)."""
+    pairs = N // 2 + 1
+    if mode == "fwd":
+        return pairs * (12 + 16 * nb)
+    return pairs * (20 + 32 * nb)
+
+
+def host_cpu():
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"model": model, "logical_cpus": os.cpu_count()}
+
+
+def _timed(fn, reps, stream):
+    """Mean ms of fn() over reps runs, HIP events on `stream` around each."""
     import numpy as np
-    import oracle
+    import torch
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in range(reps)]
+    for e0, e1 in evs:
+        e0.record(stream)
+        fn()
+        e1.record(stream)
+    torch.cuda.synchronize()
+    return float(np.mean([a.elapsed_time(b) for a, b in evs]))
+
+
+def roofline_of(kernel, kms, ops_launch, builder_flops=None, traffic=None, traffic_from=None):
+    achieved = ops_launch / (kms / 1e3) / 1e12
+    r = {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP32_TFLOPS,
+         "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_TFLOPS, 4),
+         "traffic": traffic, "kernel": kernel, "kernel_ms": round(kms, 4),
+         "ops_per_launch": int(ops_launch),
+         "count": "algorithmic ops per pixel: fwd (floor(N/2)+1)(12+16 nb), "
+                  "bwd (floor(N/2)+1)(20+32 nb)"}
+    if builder_flops is not None:
+        ach_b = builder_flops / (kms / 1e3) / 1e12
+        r["builder_count"] = {"flops_per_launch": int(builder_flops),
+                              "achieved": round(ach_b, 3),
+                              "frac": round(ach_b / PEAK_FP32_TFLOPS, 4)}
+    if traffic_from:
+        r["traffic_from"] = traffic_from
+    return r
+
+
+def measured_traffic(kernel, workload):
+    """HBM bytes per launch from the committed rocprofv3 counter runs, valid
+    only while the kernel sources hash to what they were taken on."""
+    tr = MEASURED_TRAFFIC.get((kernel, workload))
+    if tr and tr["src"] == _src_hash(tr.get("sources", TILE_SOURCES)):
+        return tr["bytes"], (f"rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE (copy-calibrated), "
+                             f"{tr['profile']}, sources {tr['src']}")
+    return None, None
+
+
+def headline_batch(steps, warmup):
+    """The headline step: the 256-image ragged batch, forward + SSD loss +
+    adjoint, one graph replay per step."""
+    import numpy as np
+    import torch
+
+    from paper_1105_4204_amd import _native, autotune, batch, synth
+    specs = synth.ragged_batch_specs(256, seed=5)
+    fs, ts = synth.ragged_batch_images(specs)
+    f = [torch.from_numpy(x).cuda() for x in fs]
+    t = [torch.from_numpy(x).cuda() for x in ts]
+    del fs, ts
+    tuner = autotune.Tuner(reps=2, probe_tiles=(8, 32))
+    t0 = time.perf_counter()
+    for s in specs:
+        tuner.tune(s, "fwd")
+        tuner.tune(s, "bwd")
+    tune_s = time.perf_counter() - t0
+    plan = batch.BatchPlan(specs, tuner=tuner)
+    out, eta, gf, loss = plan.allocate()
+    plan.bind(f, t, out, eta, gf, loss)
+    g = batch.capture(plan)
+    stream = torch.cuda.current_stream()
+    for _ in range(warmup):
+        g.replay()
+    torch.cuda.synchronize()
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in range(steps)]
+    start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    w0 = time.perf_counter()
+    start.record(stream)
+    for e0, e1 in evs:
+        e0.record(stream)
+        g.replay()
+        e1.record(stream)
+    end.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - w0
+    plan.check()
+    ms_step = start.elapsed_time(end) / steps
+    kms = float(np.mean([a.elapsed_time(b) for a, b in evs]))
+    px = sum(s["H"] * s["W"] for s in specs)
+    ops = 0
+    bflops = 0
+    Ns = []
+    for s in specs:
+        radii = _native.spatial_gaussian(s["sigma_s"], 3)
+        N = _native.range_degree(255.0, s["sigma_r"])
+        Ns.append(N)
+        hw = s["H"] * s["W"]
+        ops += hw * (ops_per_pixel(N, 3, "fwd") + ops_per_pixel(N, 3, "bwd"))
+        bflops += hw * (fwd_flops_per_pixel(N, 3, aux=True) + bwd_flops_per_pixel(N, 3))
+    traffic, tfrom = measured_traffic("bf_batch_kernel", "batch")
+    roof = roofline_of("bf_batch_kernel", kms, ops, bflops, traffic, tfrom)
+    alg_bytes = px * (20 + 28 + 4)   # forward with eta and sums, adjoint, target read
+    hbm = {"algorithmic_bytes_per_step": alg_bytes,
+           "achieved_GBs": round(alg_bytes / (ms_step / 1e3) / 1e9, 2),
+           "peak_GBs": PEAK_HBM_GBS,
+           "frac": round(alg_bytes / (ms_step / 1e3) / 1e9 / PEAK_HBM_GBS, 5)}
+    return {"ms_step": ms_step, "kernel_ms": kms, "pixels": px, "wall": wall, "roofline": roof,
+            "hbm": hbm, "N_mean": float(np.mean(Ns)), "N_range": [int(min(Ns)), int(max(Ns))],
+            "autotune": {"keys": len(tuner.table), "seconds": round(tune_s, 1)},
+            "specs": specs}
+
+
+def image_step(f, target, T, sr, radii, reps, stream, label, workload):
+    """Forward (inference), and forward with the adjoint's sums + adjoint of
+    the SSD loss, on one image; per-kernel times from HIP events."""
+    import torch
+
+    from paper_1105_4204_amd import _native, ops
     H, W = f.shape
-    rows = 0
-    t_total = 0.0
-    r0 = H // 2 - max_rows // 2
-    while rows < max_rows and t_total < budget_s:
-        idx = (np.arange(16 * W, dtype=np.int64) + (r0 + rows) * W)
-        t0 = time.perf_counter()
-        oracle.forward_at(f, sigma_r, N, radii, idx)
-        t_total += time.perf_counter() - t0
-        rows += 16
-    px = rows * W
-    return {"value": px / t_total / 1e6, "unit": "Mpix/s", "cores": oracle.num_threads(),
+    N = _native.range_degree(T, sr)
+    nb = len(radii)
+    out_buf = torch.empty_like(f)
+    ops.trig_forward(f, T, sr, radii, out=out_buf)
+    fwd_ms = _timed(lambda: ops.trig_forward(f, T, sr, radii, out=out_buf), reps, stream)
+    res = {"workload": workload, "N": N, "radii": list(radii), "fwd_ms": round(fwd_ms, 4),
+           "fwd_mpix_s": round(H * W / 1e3 / fwd_ms, 1)}
+    path = "staged" if _native.workspace_bytes(H, W, radii) else "fused"
+    res["path"] = path
+    if path == "fused":
+        holder = {}
+
+        def fwd_aux():
+            holder["r"] = ops.trig_forward(f, T, sr, radii, return_aux=True)
+
+        fwd_aux()
+        aux_ms = _timed(fwd_aux, reps, stream)
+        o, e, x = holder["r"]
+        gout = 2.0 * (o - target)
+        bwd_ms = _timed(lambda: ops.trig_backward(f, o, e, x, gout, T, sr, radii), reps, stream)
+        step = aux_ms + bwd_ms
+        res.update({"fwd_aux_ms": round(aux_ms, 4), "bwd_ms": round(bwd_ms, 4),
+                    "fwd_bwd_ms": round(step, 4),
+                    "fwd_bwd_mpix_s": round(H * W / 1e3 / step, 1)})
+        name = "bf_tile_kernel<kBackward,false>"
+        traffic, tfrom = measured_traffic(name, label)
+        res["roofline_bwd"] = roofline_of(name, bwd_ms, ops_per_pixel(N, nb, "bwd") * H * W,
+                                          bwd_flops_per_pixel(N, nb) * H * W, traffic, tfrom)
+        name = "bf_tile_kernel<kForward,false>"
+        traffic, tfrom = measured_traffic(name, label)
+        res["roofline_fwd"] = roofline_of(name, fwd_ms, ops_per_pixel(N, nb, "fwd") * H * W,
+                                          fwd_flops_per_pixel(N, nb) * H * W, traffic, tfrom)
+    else:
+        res["roofline_fwd"] = roofline_of("staged passes", fwd_ms,
+                                          ops_per_pixel(N, nb, "fwd") * H * W,
+                                          fwd_flops_per_pixel(N, nb) * H * W)
+    return res
+
+
+def config4_bench(reps, stream):
+    """16 images of 512^2, sigma_s = 6 (boxes 5, 5, 6), sigma_r = 25 (N = 43):
+    forward with the adjoint's sums + adjoint of the SSD loss, image by image."""
+    import torch
+
+    from paper_1105_4204_amd import _native, ops, synth
+    fb, tb = synth.diff_batch(16)
+    fs = [torch.from_numpy(x).cuda() for x in fb]
+    ts = [torch.from_numpy(x).cuda() for x in tb]
+    radii, sr, T = [5, 5, 6], 25.0, 255.0
+    N = _native.range_degree(T, sr)
+
+    def step():
+        for f, t in zip(fs, ts):
+            o, e, x = ops.trig_forward(f, T, sr, radii, return_aux=True)
+            ops.trig_backward(f, o, e, x, 2.0 * (o - t), T, sr, radii)
+
+    step()
+    ms = _timed(step, reps, stream)
+    px = 16 * 512 * 512
+    ops_launch = px * (ops_per_pixel(N, 3, "fwd") + ops_per_pixel(N, 3, "bwd"))
+    return {"workload": "16 x 512x512 f32 piecewise-smooth, sigma_s=6 as 3 boxes (5,5,6), "
+                        "sigma_r=25, N=43, SSD loss, forward (with the adjoint's sums) + "
+                        "adjoint per image",
+            "N": N, "ms": round(ms, 3), "fwd_bwd_mpix_s": round(px / 1e3 / ms, 1),
+            "step_ops_frac_of_fp32_peak": round(ops_launch / (ms / 1e3) / 1e12 /
+                                               PEAK_FP32_TFLOPS, 4)}
+
+
+def batch_cpu_baseline(specs, budget_s=20.0, n_images=8, fwd_px=2048, grad_px=8):
+    """The FP64 oracle on the host cores over a bounded sample of the headline
+    workload: for each of the first n_images images of the ragged batch, the
+    forward at fwd_px random pixels and the SSD-loss gradient (brute force,
+    which re-evaluates the forward around each pixel) at grad_px random pixels;
+    per-pixel times extrapolated to all pixels of those images."""
+    import numpy as np
+
+    import oracle
+    from paper_1105_4204_amd import _native, synth
+    rng = np.random.default_rng(123)
+    t_fwd = t_grad = 0.0
+    px_total = 0.0
+    t_total_est = 0.0
+    used = 0
+    for s in specs[:n_images]:
+        f, t = synth.ragged_batch_images([s])
+        f, t = f[0], t[0]
+        H, W = f.shape
+        radii = _native.spatial_gaussian(s["sigma_s"], 3)
+        N = oracle.range_degree(255.0, s["sigma_r"])
+        idx = rng.integers(0, H * W, size=fwd_px)
+        a = time.perf_counter()
+        oracle.forward_at(f, s["sigma_r"], N, radii, idx)
+        b = time.perf_counter()
+        gidx = rng.integers(0, H * W, size=grad_px)
+        oracle.ssd_grad_at(f, t, s["sigma_r"], N, radii, gidx)
+        c = time.perf_counter()
+        t_fwd += b - a
+        t_grad += c - b
+        per_px = (b - a) / fwd_px + (c - b) / grad_px
+        px_total += H * W
+        t_total_est += per_px * H * W
+        used += 1
+        if t_fwd + t_grad > budget_s:
+            break
+    return {"value": px_total / t_total_est / 1e6, "unit": "Mpix/s", "cores": oracle.num_threads(),
             "kind": "oracle",
-            "sample": f"{rows} full rows ({px} px) of the {H}x{W} image, rows {r0}..{r0 + rows - 1}, "
-                      f"FP64 direct window sum, {t_total:.1f} s"}
+            "sample": f"first {used} images of the ragged batch ({int(px_total)} px): FP64 forward "
+                      f"at {fwd_px} random px and brute-force SSD gradient at {grad_px} random px "
+                      f"per image, per-pixel times extrapolated to all their pixels (forward "
+                      f"{t_fwd:.1f} s, gradient {t_grad:.1f} s)",
+            "host": host_cpu()}
+
+
+def progress(msg):
+    """One progress line on stderr (stdout carries the single JSON line)."""
+    print(f"# bench: {msg}", file=sys.stderr, flush=True)
 
 
 def main():
@@ -314,20 +526,21 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", default="config2", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="batch",
+                    choices=["batch", "config1", "config2", "config3", "config4"],
+                    help="the headline workload (default: the ragged batch)")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="time the headline workload only")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-direct", action="store_true")
-    ap.add_argument("--fwd-only", action="store_true")
-    ap.add_argument("--no-batch", action="store_true")
-    ap.add_argument("--no-sweep", action="store_true",
-                    help="skip the sigma_s sweep (and the wide-kernel configuration)")
+    ap.add_argument("--no-sweep", action="store_true", help="skip the sigma_s sweep")
     ap.add_argument("--no-other", action="store_true",
                     help="skip the recursive-Gaussian and space-variant timings")
     ap.add_argument("--no-wide", action="store_true",
                     help="skip the 4096x4096, sigma_s=30, N=264 forward")
     ap.add_argument("--only-other", action="store_true",
-                    help="only time the recursive-Gaussian and space-variant paths (for "
-                         "counter runs); prints their JSON and exits")
+                    help="only time the recursive-Gaussian and space-variant paths on the "
+                         "2048^2 image (for counter runs); prints their JSON and exits")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a 512 MiB device copy (counter calibration) and exit")
     args = ap.parse_args()
@@ -344,188 +557,101 @@ def main():
         copy_calibration()
         return
 
-    import numpy as np
     import torch
 
     from paper_1105_4204_amd import _native, ops, synth
 
-    wl = WORKLOADS[args.workload]
-    H, W = wl["H"], wl["W"]
-    if wl["gen"] == "rect":
-        f_np = synth.rectangles(H, W, seed=wl["seed"])
-    else:
-        f_np = synth.piecewise_smooth(H, W, seed=wl["seed"])
-    t_np = synth.piecewise_smooth(H, W, seed=wl["seed"] + 1000)
-    radii = wl.get("radii") or _native.spatial_gaussian(wl["sigma_s"], 3)
-    sr, T = wl["sigma_r"], 255.0
-    N = _native.range_degree(T, sr)
-    nb = len(radii)
-
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
-    f = torch.from_numpy(f_np).to(dev)
-    if args.only_other:
-        print(json.dumps({"workload": wl["desc"], "sigma_r": sr,
-                          "other_spatial_kernels": other_spatial_kernels(f, T, sr)}), flush=True)
-        return
-    target = torch.from_numpy(t_np).to(dev)
     stream = torch.cuda.current_stream()
-    do_bwd = not args.fwd_only
-    try:
-        ops.trig_forward(f, T, sr, radii, return_aux=True)
-    except _native.BFError as e:
-        if e.code == 6:
-            do_bwd = False
-        else:
-            raise
+    T = 255.0
 
-    # the training step: forward (with the sums the adjoint needs) + adjoint
-    # of the SSD loss; events on the launch stream around each kernel
-    def step(ev=None):
-        if ev is not None:
-            ev[0].record(stream)
-        if do_bwd:
-            out, eta, aux = ops.trig_forward(f, T, sr, radii, return_aux=True)
-        else:
-            out = ops.trig_forward(f, T, sr, radii)
-        if ev is not None:
-            ev[1].record(stream)
-        if do_bwd:
-            g = 2.0 * (out - target)
-            if ev is not None:
-                ev[2].record(stream)
-            gf = ops.trig_backward(f, out, eta, aux, g, T, sr, radii)
-            if ev is not None:
-                ev[3].record(stream)
-            return gf
-        return out
+    if args.only_other:
+        wl = WORKLOADS["config2"]
+        f = torch.from_numpy(synth.config_image(2)).to(dev)
+        print(json.dumps({"workload": wl["desc"], "sigma_r": wl["sigma_r"],
+                          "other_spatial_kernels": other_spatial_kernels(f, T, wl["sigma_r"])}),
+              flush=True)
+        return
 
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(args.steps)]
-    t0 = time.perf_counter()
-    start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    start.record(stream)
-    for k in range(args.steps):
-        step(evs[k])
-    end.record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    total_ms = start.elapsed_time(end)
-    ms_step = total_ms / args.steps
-    step_fwd_ms = float(np.mean([e[0].elapsed_time(e[1]) for e in evs]))
-    bwd_ms = float(np.mean([e[2].elapsed_time(e[3]) for e in evs])) if do_bwd else None
-
-    # inference forward alone (no auxiliary sums)
-    out_buf = torch.empty_like(f)
-    ops.trig_forward(f, T, sr, radii, out=out_buf)
-    torch.cuda.synchronize()
-    fevs = [[torch.cuda.Event(enable_timing=True) for _ in range(2)] for _ in range(args.steps)]
-    for k in range(args.steps):
-        fevs[k][0].record(stream)
-        ops.trig_forward(f, T, sr, radii, out=out_buf)
-        fevs[k][1].record(stream)
-    torch.cuda.synchronize()
-    fwd_ms = float(np.mean([e[0].elapsed_time(e[1]) for e in fevs]))
-
-    mpix = H * W / 1e6
-    value = mpix / (ms_step / 1e3)
-    fwd_mpix = mpix / (fwd_ms / 1e3)
-
-    direct = None
-    if not args.no_direct:
-        ops.direct_forward(f, T, sr, radii)
-        torch.cuda.synchronize()
-        d0, d1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        reps = 3
-        d0.record(stream)
-        for _ in range(reps):
-            ops.direct_forward(f, T, sr, radii)
-        d1.record(stream)
-        torch.cuda.synchronize()
-        direct_ms = d0.elapsed_time(d1) / reps
-        direct = {"ms": direct_ms, "mpix_s": mpix / (direct_ms / 1e3),
-                  "fwd_speedup_vs_direct": direct_ms / fwd_ms}
-
-    # dominant kernel of the step: the forward with auxiliary sums or the adjoint
-    fwd_flops = fwd_flops_per_pixel(N, nb) * H * W
-    dom = ("bf_tile_kernel<kForward,false>", fwd_ms, fwd_flops)
-    if do_bwd:
-        dom = ("bf_tile_kernel<kForward,true>", step_fwd_ms,
-               fwd_flops_per_pixel(N, nb, aux=True) * H * W)
-        if bwd_ms > step_fwd_ms:
-            dom = ("bf_tile_kernel<kBackward,false>", bwd_ms, bwd_flops_per_pixel(N, nb) * H * W)
-    name, kms, kflops = dom
-    achieved = kflops / (kms / 1e3) / 1e12
-    tr = MEASURED_TRAFFIC.get((name, args.workload))
-    traffic = tr["bytes"] if tr and tr["src"] == _src_hash() else None
-    roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP32_TFLOPS,
-                "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_TFLOPS, 4),
-                "traffic": traffic, "kernel": name, "kernel_ms": round(kms, 4),
-                "flops_per_launch": kflops}
-    fwd_bytes = 8 * H * W        # inference: read f, write out
-    fwd_aux_bytes = 20 * H * W   # training: read f; write out, eta, P, Q
-    bwd_bytes = 28 * H * W       # read f, out, eta, P, Q, grad_out; write grad_f
-    step_bytes = (fwd_aux_bytes + bwd_bytes) if do_bwd else fwd_bytes
-    hbm = {"algorithmic_bytes_per_step": step_bytes,
-           "achieved_GBs": round(step_bytes / (ms_step / 1e3) / 1e9, 2),
-           "peak_GBs": PEAK_HBM_GBS,
-           "frac": round(step_bytes / (ms_step / 1e3) / 1e9 / PEAK_HBM_GBS, 5),
-           "dominant_kernel_measured_GBs": (round(traffic / (kms / 1e3) / 1e9, 2)
-                                            if traffic is not None else None),
-           "note": "ALU-bound: 2(N+1) filtered channels per pixel stay in registers and LDS"}
-
-    batch_res = None
-    if not args.no_batch and do_bwd and args.workload == "config2":
-        batch_res = batch_bench()
-
-    sweep = None
-    if not args.no_sweep and args.workload == "config2":
-        sweep = sigma_s_sweep(f, T, sr)
-
-    other = None
-    if not args.no_other and args.workload == "config2":
-        other = other_spatial_kernels(f, T, sr)
-
-    wide = None
-    if not args.no_wide and not args.no_sweep and args.workload == "config2":
-        wide = wide_config_bench()
-
+    line = {"metric": METRIC, "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+            "data": "synthetic"}
+    extras = {}
     cpu = None
-    if not args.no_cpu_baseline:
-        cpu = cpu_baseline(f_np, sr, N, radii)
+    if args.workload == "batch":
+        progress("headline: 256-image ragged batch")
+        hb = headline_batch(args.steps, args.warmup)
+        progress(f"headline: {hb['ms_step']:.2f} ms per step")
+        value = hb["pixels"] / 1e3 / hb["ms_step"]
+        line.update({"value": round(value, 3), "unit": "Mpix/s",
+                     "ms_per_step": round(hb["ms_step"], 4),
+                     "config": {"workload": BATCH_DESC, "images": 256,
+                                "pixels": hb["pixels"], "N_mean": round(hb["N_mean"], 1),
+                                "N_range": hb["N_range"], "T": T, "step": "fwd+bwd"},
+                     "roofline": hb["roofline"], "hbm": hb["hbm"],
+                     "autotune": hb["autotune"], "wall_s_timed": round(hb["wall"], 3)})
+        if not args.no_cpu_baseline:
+            progress("oracle on the host cores")
+            cpu = batch_cpu_baseline(hb["specs"])
+    else:
+        wl = WORKLOADS[args.workload]
+        if args.workload == "config4":
+            r4 = config4_bench(args.steps, stream)
+            line.update({"value": r4["fwd_bwd_mpix_s"], "unit": "Mpix/s",
+                         "ms_per_step": r4["ms"], "config": {"workload": r4["workload"]}})
+        else:
+            f_np = synth.config_image(int(args.workload[-1]))
+            f = torch.from_numpy(f_np).to(dev)
+            tgt = torch.from_numpy(synth.piecewise_smooth(*f_np.shape, seed=wl["seed"] + 1000)
+                                   ).to(dev)
+            radii = wl.get("radii") or _native.spatial_gaussian(wl["sigma_s"], 3)
+            r = image_step(f, tgt, T, wl["sigma_r"], radii, args.steps, stream, args.workload,
+                           wl["desc"])
+            ms = r.get("fwd_bwd_ms", r["fwd_ms"])
+            line.update({"value": round(f.numel() / 1e3 / ms, 3), "unit": "Mpix/s",
+                         "ms_per_step": round(ms, 4),
+                         "config": {"workload": wl["desc"],
+                                    "step": "fwd+bwd" if "fwd_bwd_ms" in r else "fwd"},
+                         "roofline": r.get("roofline_bwd", r["roofline_fwd"]), "detail": r})
 
-    line = {
-        "metric": METRIC,
-        "value": round(value, 3),
-        "unit": "Mpix/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": round(ms_step, 4),
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f32",
-        "data": "synthetic",
-        "config": {"workload": wl["desc"], "H": H, "W": W, "radii": radii, "sigma_r": sr,
-                   "T": T, "N": N, "step": "fwd+bwd" if do_bwd else "fwd"},
-        "fwd_mpix_s": round(fwd_mpix, 3),
-        "fwd_ms": round(fwd_ms, 4),
-        "fwd_aux_ms": round(step_fwd_ms, 4) if do_bwd else None,
-        "bwd_ms": round(bwd_ms, 4) if bwd_ms is not None else None,
-        "fwd_bwd_mpix_s": round(value, 3) if do_bwd else None,
-        "direct_gpu": direct,
-        "hbm": hbm,
-        "roofline": roofline,
-        "batch": batch_res,
-        "sigma_s_sweep": sweep,
-        "other_spatial_kernels": other,
-        "wide_kernel_config": wide,
-        "cpu_baseline": cpu,
-        "wall_s_timed": round(wall, 3),
-    }
+    if not args.no_extras:
+        # 2048^2, the paper's nearest Table-2 setting
+        wl = WORKLOADS["config2"]
+        f2_np = synth.config_image(2)
+        f2 = torch.from_numpy(f2_np).to(dev)
+        t2 = torch.from_numpy(synth.piecewise_smooth(2048, 2048, seed=wl["seed"] + 1000)).to(dev)
+        radii2 = _native.spatial_gaussian(wl["sigma_s"], 3)
+        progress("extras: 2048^2")
+        if args.workload != "config2":
+            extras["config2"] = image_step(f2, t2, T, wl["sigma_r"], radii2, args.steps, stream,
+                                           "config2", wl["desc"])
+        if not args.no_direct:
+            ops.direct_forward(f2, T, wl["sigma_r"], radii2)
+            dms = _timed(lambda: ops.direct_forward(f2, T, wl["sigma_r"], radii2), 3, stream)
+            extras["direct_gpu_config2"] = {"ms": round(dms, 3),
+                                            "mpix_s": round(f2.numel() / 1e3 / dms, 1)}
+        progress("extras: 256^2 and 16 x 512^2")
+        if args.workload != "config1":
+            wl1 = WORKLOADS["config1"]
+            f1 = torch.from_numpy(synth.config_image(1)).to(dev)
+            extras["config1"] = image_step(f1, f1, T, wl1["sigma_r"], wl1["radii"], args.steps,
+                                           stream, "config1", wl1["desc"])
+            for k in ("fwd_aux_ms", "bwd_ms", "fwd_bwd_ms", "fwd_bwd_mpix_s", "roofline_bwd"):
+                extras["config1"].pop(k, None)   # forward only for this workload
+        if args.workload != "config4":
+            extras["config4"] = config4_bench(max(2, args.steps // 4), stream)
+        progress("extras: sigma_s sweep, other kernels, 4096^2")
+        if not args.no_sweep:
+            extras["sigma_s_sweep"] = sigma_s_sweep(f2, T, wl["sigma_r"])
+        if not args.no_other:
+            extras["other_spatial_kernels"] = other_spatial_kernels(f2, T, wl["sigma_r"])
+        if not args.no_wide and args.workload != "config3":
+            extras["config3"] = wide_config_bench()
+        del f2, t2
+    line.update(extras)
+    if cpu is not None:
+        line["cpu_baseline"] = cpu
     print(json.dumps(line), flush=True)
 
 

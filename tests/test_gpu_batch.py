@@ -115,11 +115,13 @@ def test_batch_graph_replay():
 
 
 def test_ragged_workload_sample_vs_oracle():
-    """24 images drawn like the 256-image ragged workload (H, W in [64,1024],
-    sigma_s in [2,16], sigma_r in [10,60]); per image 24 random pixels of the
-    forward and 6 of the SSD gradient against the FP64 oracle."""
+    """The first 64 images of the 256-image ragged workload (H, W in
+    [64,1024], sigma_s in [2,16], sigma_r in [10,60], per-image N), run as one
+    batch; per image 8 random pixels of the forward and 2 of the SSD gradient
+    against the FP64 oracle, at the forward's tolerance and the gradient's
+    (1e-3 of the largest sampled |gradient| of the image + 1e-3 relative)."""
     batch, ops = _mods()
-    specs = synth.ragged_batch_specs(24, seed=5)
+    specs = synth.ragged_batch_specs(64, seed=5)
     fs, ts = synth.ragged_batch_images(specs)
     plan = batch.BatchPlan(specs)
     out, eta, gf, loss = plan.allocate()
@@ -133,16 +135,19 @@ def test_ragged_workload_sample_vs_oracle():
         radii = s.get("radii") or nat.spatial_gaussian(s["sigma_s"], 3)
         N = oracle.range_degree(255.0, s["sigma_r"])
         H, W = s["H"], s["W"]
-        idx = rng.integers(0, H * W, size=24)
+        idx = rng.integers(0, H * W, size=8)
         ref = oracle.forward_at(fs[i], s["sigma_r"], N, radii, idx)
         got = out[i].cpu().numpy().reshape(-1)[idx].astype(np.float64)
         err = np.abs(got - ref)
         assert np.all(err <= 1e-2 + 1e-4 * np.abs(ref)), (i, s, err.max())
-        gidx = rng.integers(0, H * W, size=6)
+        gidx = rng.integers(0, H * W, size=4)
         gref = oracle.ssd_grad_at(fs[i], ts[i], s["sigma_r"], N, radii, gidx)
         gg = gf[i].cpu().numpy().reshape(-1)[gidx].astype(np.float64)
         scale = max(np.abs(gref).max(), 1e-6)
-        assert np.all(np.abs(gg - gref) <= 1e-3 * scale + 1e-3 * np.abs(gref) + 2e-3), (i, gg, gref)
+        gerr = np.abs(gg - gref)
+        print(f"image {i} {H}x{W} N={N} R={sum(radii)}: fwd {err.max():.2e} "
+              f"grad {gerr.max():.2e} (scale {scale:.2e})", flush=True)
+        assert np.all(gerr <= 1e-3 * scale + 1e-3 * np.abs(gref)), (i, gg, gref)
 
 
 def test_colour_channels_as_batch_items():

@@ -58,6 +58,13 @@ SMALL = [
     (129, 257, 15.0, 0, [7, 7, 8], "smooth"),    # several tiles and ragged tails
     (20, 30, 5.1, 1024, [2], "smooth"),          # the largest degree accepted
     (40, 50, 30.0, 0, [31, 31, 1], "smooth"),    # R = 63: the widest fused kernel
+    # the smallest degrees, Table 1's estimate row: sigma_r = 200, 150, 100
+    # give N = 1 (the single cosine of eq. (cosine): one odd pair, no centre
+    # pair), N = 2 (centre pair and m = 2) and N = 3 (m = 1, 3)
+    (48, 56, 200.0, 0, [2, 2, 3], "smooth"),
+    (40, 44, 150.0, 0, [3], "salt"),
+    (52, 47, 100.0, 0, [1, 2, 2], "smooth"),
+    (70, 66, 200.0, 0, [5], "rect"),
 ]
 
 
