@@ -51,8 +51,16 @@ typedef enum {
 } bf_status;
 
 #define BF_MAX_BOXES 4      /* iterated boxes per axis */
-#define BF_MAX_RADIUS 128   /* per box */
+#define BF_MAX_RADIUS 256   /* per box (BF_ERANGE above).  The fused kernel takes
+                               radii <= 31 with R = sum of radii <= 63; the
+                               streamed passes take any radii up to this with
+                               W + 2R <= 5184 and prod(2 radius + 1) < 2^31 */
 #define BF_MAX_DEGREE 1024  /* largest raised-cosine degree N */
+
+/* bf_opts.path: which forward evaluation runs. */
+#define BF_PATH_AUTO 0      /* the library's choice (cost model) */
+#define BF_PATH_FUSED 1     /* fused tile kernel (radii <= 31, R <= 63) */
+#define BF_PATH_STREAMED 2  /* streamed whole-line passes (any R the limits allow) */
 
 /* Spatial kernel: n_boxes boxes per axis (1 = plain box; 3 approximates a
  * Gaussian, Sec. 2.1 and Algorithm 1 step 4).  radius[i] >= 0; box i has
@@ -74,13 +82,15 @@ typedef struct {
     float* aux_out;      /* forward only: optional 2*H*W device buffer for the
                             two auxiliary sums the backward needs (see
                             bf_trig_backward); NULL = not computed */
-    void* workspace;     /* forward only: device scratch for spatial kernels
-                            wider than the fused kernel handles (see
-                            bf_trig_workspace_bytes); NULL if none */
+    void* workspace;     /* forward only: device scratch of the streamed passes
+                            (see bf_trig_workspace_bytes), 256-byte aligned, not
+                            overlapping the images; NULL = the library's own */
     int64_t workspace_bytes;
     float trunc_tol;     /* 0 = every cosine pair; > 0 = drop the outer pairs
                             while the bound of bf_range_truncate stays <= this
                             many gray levels (forward and backward must agree) */
+    int32_t path;        /* forward only: BF_PATH_AUTO (0), BF_PATH_FUSED or
+                            BF_PATH_STREAMED */
 } bf_opts;
 
 /* Algorithm 1 steps 1-2: N = ceil((gamma sigma_r)^-2), gamma = pi/(2T).
@@ -112,25 +122,34 @@ bf_status bf_range_truncate(int32_t N, double T, const bf_spatial_spec* spatial_
  * the narrower ones first, ties to the narrower. */
 bf_status bf_spatial_gaussian(double sigma_s, int32_t n_boxes, bf_spatial_spec* out);
 
-/* Device workspace the forward wants for image size H x W and this spatial
- * kernel.  0: the fused single-pass kernel is used.  Otherwise
- * 4 * (4 H Wp + 2 H W) bytes, Wp = W + 260 rounded up to a multiple of 64
- * (four channel planes with zero margins, then den and num; the
- * workspace must be 16-byte aligned): the staged path, which filters the
- * channels of each cosine pair in two separable passes through this
- * workspace (Sec. 2.1, eq. (final-form)), is required (sum of radii
- * 63 < R <= 124) or faster (the fused tiles shrink as R grows; from R of
- * about 42 on a 2048^2 image).  Every radius must be <= 31;
- * BF_EUNSUPPORTED when neither path handles the kernel.  The staged path is
- * forward only: with aux_out set the forward uses the fused kernel, which
- * exists for R <= 63; without the workspace it also falls back to the fused
- * kernel where that exists. */
+/* Device workspace of the forward's streamed passes for image size H x W and
+ * this spatial kernel: 0 when the library evaluates this geometry with the
+ * fused tile kernel (no workspace), otherwise the recommended size,
+ * 16 P H Wp + 8 H W bytes for P = 16 cosine pairs, Wp = W rounded up to a
+ * multiple of 64.  The streamed passes (Sec. 2.1, eq. (final-form)) filter
+ * the four channels of each pair along whole columns and then whole rows;
+ * the column-filtered channels of a chunk of pairs wait in the workspace
+ * between the two passes, the partial den and num between chunks.  Any size
+ * from one pair's (P = 1) up works: smaller workspaces only mean more chunks.
+ * They run where the fused kernel cannot hold the kernel width (a radius
+ * above 31 or R > 63) or where its tiles, shrunken by the halo, cost more.
+ * BF_EUNSUPPORTED when neither evaluation handles the kernel. */
 bf_status bf_trig_workspace_bytes(int64_t H, int64_t W, const bf_spatial_spec* spatial_spec,
                                   int64_t* bytes_out);
 
 /* Forward filter, eq. (BF)/(normalization) with the raised-cosine kernel.
  * f: H*W input; out: H*W output (must not overlap f).  sigma_r > 0, T > 0.
- * Equivalent to bf_trig_forward_ex with opts == NULL. */
+ * Equivalent to bf_trig_forward_ex with opts == NULL: every kernel width the
+ * limits above allow runs; where the streamed passes run, the library uses a
+ * workspace of its own (bf_trig_workspace_bytes with P = min(pairs, 16)),
+ * allocated on first need per device and kept until the process ends, so
+ * such a call may not be captured (BF_ECAPTURE) and may return BF_ENOMEM.
+ * Calls that share it are ordered on the device, whatever their streams.
+ *
+ * bf_trig_forward_ex: opts->aux_out (the adjoint's sums) forces the fused
+ * kernel (BF_EUNSUPPORTED for kernels it cannot hold), as does a tile
+ * override; opts->path forces either evaluation; a caller workspace smaller
+ * than one pair's returns BF_EINVAL. */
 bf_status bf_trig_forward(const float* f, int64_t H, int64_t W, float T, float sigma_r,
                           const bf_spatial_spec* spatial_spec, float* out);
 

@@ -14,7 +14,8 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libbftrig.so")
 
 BF_MAX_BOXES = 4
-BF_MAX_RADIUS = 128
+BF_MAX_RADIUS = 256
+PATH_AUTO, PATH_FUSED, PATH_STREAMED = 0, 1, 2
 BF_MAX_DEGREE = 1024
 
 STATUS = {0: "BF_OK", 1: "BF_EINVAL", 2: "BF_ERANGE", 3: "BF_ENOMEM", 4: "BF_EDEVICE",
@@ -58,7 +59,7 @@ class Opts(ctypes.Structure):
                 ("eta_out", ctypes.c_void_p), ("tile_h", ctypes.c_int32),
                 ("tile_w", ctypes.c_int32), ("aux_out", ctypes.c_void_p),
                 ("workspace", ctypes.c_void_p), ("workspace_bytes", ctypes.c_int64),
-                ("trunc_tol", ctypes.c_float)]
+                ("trunc_tol", ctypes.c_float), ("path", ctypes.c_int32)]
 
 
 class ImageDesc(ctypes.Structure):
@@ -146,7 +147,7 @@ def spatial_gaussian(sigma_s: float, n_boxes: int = 3):
 
 
 def make_opts(stream=None, N=0, eta_out=None, tile=None, aux_out=None, workspace=None,
-              workspace_bytes=0, trunc_tol=0.0) -> Opts:
+              workspace_bytes=0, trunc_tol=0.0, path=PATH_AUTO) -> Opts:
     o = Opts()
     o.stream = stream
     o.N = int(N)
@@ -156,6 +157,7 @@ def make_opts(stream=None, N=0, eta_out=None, tile=None, aux_out=None, workspace
     o.workspace = workspace
     o.workspace_bytes = int(workspace_bytes)
     o.trunc_tol = float(trunc_tol)
+    o.path = int(path)
     return o
 
 
@@ -170,12 +172,21 @@ def range_truncate(N: int, T: float, radii, tol: float):
 
 
 def workspace_bytes(H: int, W: int, radii) -> int:
-    """Device workspace the forward needs (0 for the fused single-pass kernel)."""
+    """Recommended device workspace of the forward's streamed passes (0 where
+    the library evaluates this geometry with the fused kernel)."""
     n = ctypes.c_int64()
     spec = SpatialSpec.of(radii)
     check(lib().bf_trig_workspace_bytes(int(H), int(W), ctypes.byref(spec), ctypes.byref(n)),
           "bf_trig_workspace_bytes")
     return int(n.value)
+
+
+def stream_workspace_bytes(H: int, W: int, pairs: int) -> int:
+    """Workspace of the streamed passes for chunks of `pairs` cosine pairs:
+    four column-filtered planes per pair (pitch W rounded up to 64) plus the
+    den and num partials (the layout bf_trig_workspace_bytes documents)."""
+    Wp = (int(W) + 63) // 64 * 64
+    return 16 * int(pairs) * int(H) * Wp + 8 * int(H) * int(W)
 
 
 def yvv_coeffs(sigma_s: float):

@@ -9,7 +9,7 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libbftrig.so")
 SOURCES = ["bf_host.cpp", "bf_api.cpp", "bf_batch.hip", "bf_tile.hip",
-           "bf_direct.hip", "bf_staged.hip", "bf_sv.hip",
+           "bf_direct.hip", "bf_stream.hip", "bf_sv.hip",
            "bf_yvv.hip", "bf_check.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

@@ -1,7 +1,10 @@
 // extern "C" entry points of libbftrig: argument validation, parameter
-// derivation and dispatch to the HIP kernels.  Nothing here allocates on the
-// single-image paths, so they may be captured into a hipGraph.
+// derivation and dispatch to the HIP kernels.  The single-image paths
+// allocate nothing, except the streamed forward's workspace when the caller
+// passes none (allocated once per device, outside stream capture).
+#include <algorithm>
 #include <cmath>
+#include <mutex>
 
 #include "bf_internal.h"
 
@@ -31,7 +34,89 @@ bf_status prepare(const float* f, int64_t H, int64_t W, float T, float sigma_r,
     return BF_OK;
 }
 
+// Workspace of the streamed path for callers that pass none: one buffer per
+// device, grown on demand (hipMalloc, never during stream capture) and kept
+// until the process ends.  Calls on different streams are ordered through an
+// event recorded after each use, so they never share it concurrently.
+struct LibWorkspace {
+    void* p = nullptr;
+    size_t n = 0;
+    hipEvent_t done = nullptr;
+    bool pending = false;
+};
+constexpr int kMaxDevices = 64;
+std::mutex g_ws_mu;
+LibWorkspace g_ws[kMaxDevices];
+thread_local int g_ws_dev = -1;
+
 }  // namespace
+
+namespace bf {
+
+bf_status library_workspace(size_t need, hipStream_t stream, void** out) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) {
+        set_error("no current HIP device for the library workspace");
+        return BF_EDEVICE;
+    }
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(stream, &cs) != hipSuccess) cs = hipStreamCaptureStatusNone;
+    g_ws_mu.lock();   // held until library_workspace_done (or an error below)
+    LibWorkspace& w = g_ws[dev];
+    if (cs != hipStreamCaptureStatusNone) {
+        g_ws_mu.unlock();
+        set_error("the streamed path needs opts->workspace while the stream is being captured");
+        return BF_ECAPTURE;
+    }
+    if (!w.done && hipEventCreateWithFlags(&w.done, hipEventDisableTiming) != hipSuccess) {
+        w.done = nullptr;
+        g_ws_mu.unlock();
+        set_error("hipEventCreateWithFlags failed");
+        return BF_EDEVICE;
+    }
+    if (w.n < need) {
+        if (w.p) {
+            if (hipDeviceSynchronize() != hipSuccess || hipFree(w.p) != hipSuccess) {
+                g_ws_mu.unlock();
+                set_error("freeing the library workspace failed");
+                return BF_EDEVICE;
+            }
+            w.p = nullptr;
+            w.n = 0;
+            w.pending = false;
+        }
+        if (hipMalloc(&w.p, need) != hipSuccess) {
+            w.p = nullptr;
+            (void)hipGetLastError();
+            g_ws_mu.unlock();
+            set_error("allocating the %zu-byte library workspace failed", need);
+            return BF_ENOMEM;
+        }
+        w.n = need;
+    }
+    if (w.pending && hipStreamWaitEvent(stream, w.done, 0) != hipSuccess) {
+        g_ws_mu.unlock();
+        set_error("hipStreamWaitEvent on the library workspace failed");
+        return BF_EDEVICE;
+    }
+    g_ws_dev = dev;
+    *out = w.p;
+    return BF_OK;
+}
+
+bf_status library_workspace_done(hipStream_t stream) {
+    LibWorkspace& w = g_ws[g_ws_dev];
+    const bool ok = hipEventRecord(w.done, stream) == hipSuccess;
+    w.pending = ok;
+    g_ws_mu.unlock();
+    if (!ok) {
+        set_error("hipEventRecord on the library workspace failed");
+        return BF_EDEVICE;
+    }
+    return BF_OK;
+}
+
+}  // namespace bf
 
 extern "C" {
 
@@ -52,44 +137,65 @@ bf_status bf_trig_forward_ex(const float* f, int64_t H, int64_t W, float T, floa
         set_error("out / eta_out / aux_out must not overlap f or each other");
         return BF_EINVAL;
     }
+    const int path = opts ? opts->path : BF_PATH_AUTO;
+    if (path != BF_PATH_AUTO && path != BF_PATH_FUSED && path != BF_PATH_STREAMED) {
+        set_error("opts->path=%d is not one of BF_PATH_AUTO, BF_PATH_FUSED, BF_PATH_STREAMED",
+                  path);
+        return BF_EINVAL;
+    }
     TileGeom g = {};
     const int req_h = opts ? opts->tile_h : 0, req_w = opts ? opts->tile_w : 0;
-    st = plan_fwd_tiles(H, W, c.sp, req_h, req_w, &g);
-    const bool fused_ok = st == BF_OK;
-    const size_t need = staged_workspace_bytes(H, W);
+    const bf_status fst = plan_fwd_tiles(H, W, c.sp, req_h, req_w, &g);
+    // the streamed passes: where the fused kernel cannot hold the kernel width,
+    // or where its shrunken tiles cost more (no adjoint sums requested and no
+    // tile shape forced), or on request
+    bool streamed;
+    if (path == BF_PATH_FUSED || aux || req_h > 0 || req_w > 0)
+        streamed = false;
+    else if (path == BF_PATH_STREAMED)
+        streamed = true;
+    else
+        streamed = prefer_stream(H, W, c.sp, fst, g);
+    if (!streamed) {
+        if (fst != BF_OK && aux && stream_supported(W, c.sp))
+            set_error("R=%d: the adjoint's sums (aux_out) are only produced by the fused "
+                      "kernel (every radius <= 31, R <= 63)", c.sp.R);
+        if (fst != BF_OK) return fst == BF_EUNSUPPORTED && aux ? BF_EUNSUPPORTED : fst;
+        return launch_fwd(f, out, eta, aux, H, W, c.rp, c.sp, g, c.stream);
+    }
+    if (!stream_supported(W, c.sp)) {
+        set_error("the streamed path handles W + 2R <= 5184 and a kernel mass below 2^31 "
+                  "(W=%lld, R=%d)", (long long)W, c.sp.R);
+        return BF_EUNSUPPORTED;
+    }
     void* ws = opts ? opts->workspace : nullptr;
-    const bool have_ws = ws && opts->workspace_bytes >= (int64_t)need;
-    // the staged passes: where the fused kernel cannot hold the kernel width,
-    // or where its shrunken tiles cost more (and a workspace is given, no
-    // adjoint sums are requested and no tile shape was forced)
-    const bool staged =
-        staged_supported(c.sp) &&
-        (!fused_ok || (have_ws && !aux && req_h <= 0 && req_w <= 0 &&
-                       prefer_staged(H, W, c.sp, st, g)));
-    if (staged) {
-        if (aux) {
-            set_error("R=%d: the adjoint's sums (aux_out) are only produced by the fused kernel "
-                      "(R <= 63)", c.sp.R);
-            return BF_EUNSUPPORTED;
-        }
-        if (!have_ws) {
-            set_error("R=%d needs the staged path and a workspace of %zu bytes "
-                      "(bf_trig_workspace_bytes)", c.sp.R, need);
-            return BF_EINVAL;
-        }
-        if (overlaps(ws, (int64_t)need, f, bytes) || overlaps(ws, (int64_t)need, out, bytes) ||
-            overlaps(ws, (int64_t)need, eta, bytes)) {
+    size_t wsb = opts && opts->workspace_bytes > 0 ? (size_t)opts->workspace_bytes : 0;
+    if (ws) {
+        if (overlaps(ws, (int64_t)wsb, f, bytes) || overlaps(ws, (int64_t)wsb, out, bytes) ||
+            overlaps(ws, (int64_t)wsb, eta, bytes)) {
             set_error("workspace must not overlap the images");
             return BF_EINVAL;
         }
-        if ((reinterpret_cast<uintptr_t>(ws) & 15) != 0) {
-            set_error("the staged path's workspace must be 16-byte aligned");
+        if ((reinterpret_cast<uintptr_t>(ws) & 255) != 0) {
+            set_error("the streamed path's workspace must be 256-byte aligned");
             return BF_EINVAL;
         }
-        return launch_staged(f, out, eta, H, W, c.rp, c.sp, ws, c.stream);
+        if (stream_chunk_pairs(H, W, wsb, c.rp.npairs) <= 0) {
+            set_error("workspace of %zu bytes is below the %zu bytes of one cosine pair",
+                      wsb, stream_workspace_bytes(H, W, 1));
+            return BF_EINVAL;
+        }
+    } else {
+        wsb = stream_workspace_bytes(H, W, std::min(c.rp.npairs, kStreamChunkPairs));
+        st = library_workspace(wsb, c.stream, &ws);
+        if (st != BF_OK) return st;
     }
-    if (st != BF_OK) return st;
-    return launch_fwd(f, out, eta, aux, H, W, c.rp, c.sp, g, c.stream);
+    st = launch_stream(f, out, eta, H, W, c.rp, c.sp, ws, wsb, c.stream);
+    if (!(opts && opts->workspace)) {
+        const bf_status st2 = library_workspace_done(c.stream);   // releases the lock
+        if (st == BF_OK) st = st2;
+    }
+    return st;
 }
 
 bf_status bf_trig_workspace_bytes(int64_t H, int64_t W, const bf_spatial_spec* spatial_spec,
@@ -109,10 +215,13 @@ bf_status bf_trig_workspace_bytes(int64_t H, int64_t W, const bf_spatial_spec* s
     TileGeom g = {};
     st = plan_fwd_tiles(H, W, sp, 0, 0, &g);
     if (st != BF_OK && st != BF_EUNSUPPORTED) return st;
-    if (prefer_staged(H, W, sp, st, g)) {
-        *bytes_out = (int64_t)staged_workspace_bytes(H, W);
+    if (prefer_stream(H, W, sp, st, g)) {
+        *bytes_out = (int64_t)stream_workspace_bytes(H, W, kStreamChunkPairs);
         return BF_OK;
     }
+    if (st != BF_OK)
+        set_error("neither the fused kernel nor the streamed passes handle W=%lld, R=%d",
+                  (long long)W, sp.R);
     return st;
 }
 

@@ -76,15 +76,25 @@ bf_status launch_direct(const float* f, float* out, float* eta, int64_t H, int64
                         const RangeParams& rp, const SpatialParams& sp, hipStream_t stream);
 bf_status plan_bwd_tiles(int64_t H, int64_t W, const SpatialParams& sp, int req_h, int req_w,
                          TileGeom* g, const float* f);
-// Staged forward for spatial radii beyond the fused kernel (bf_staged.hip).
-bool staged_supported(const SpatialParams& sp);
-struct TileGeom;
-bool prefer_staged(int64_t H, int64_t W, const SpatialParams& sp, bf_status fused_status,
+// Streamed forward for wide spatial kernels (bf_stream.hip): whole-line
+// column and row passes whose cost does not depend on the radii; the
+// column-filtered channels of a chunk of pairs pass through a workspace.
+bool stream_supported(int64_t W, const SpatialParams& sp);
+size_t stream_workspace_bytes(int64_t H, int64_t W, int pairs);   // planes + den/num partials
+int stream_chunk_pairs(int64_t H, int64_t W, size_t ws_bytes, int npairs);
+bool prefer_stream(int64_t H, int64_t W, const SpatialParams& sp, bf_status fused_status,
                    const TileGeom& g);
-size_t staged_workspace_bytes(int64_t H, int64_t W);
-bf_status launch_staged(const float* f, float* out, float* eta, int64_t H, int64_t W,
+bf_status launch_stream(const float* f, float* out, float* eta, int64_t H, int64_t W,
                         const RangeParams& rp, const SpatialParams& sp, void* workspace,
-                        hipStream_t stream);
+                        size_t ws_bytes, hipStream_t stream);
+// Pairs per chunk of the workspace the library allocates when the caller
+// passes none (and that bf_trig_workspace_bytes recommends).
+constexpr int kStreamChunkPairs = 16;
+// The library's own streamed-path workspace for the current device (bf_api.cpp):
+// library_workspace takes a lock and orders `stream` after the previous user;
+// library_workspace_done records that use and releases the lock.
+bf_status library_workspace(size_t need, hipStream_t stream, void** out);
+bf_status library_workspace_done(hipStream_t stream);
 // Space-variant box kernel through tile-local summed-area tables (bf_sv.hip).
 bf_status launch_sv(const float* f, const int32_t* rmap, float* out, float* eta, int64_t H,
                     int64_t W, int32_t rmax, const RangeParams& rp, hipStream_t stream);

@@ -31,8 +31,13 @@ def _ptr(x):
 
 def trig_forward(f: torch.Tensor, T: float, sigma_r: float, radii, N: int = 0,
                  return_eta: bool = False, tile=None, out: torch.Tensor | None = None,
-                 return_aux: bool = False, trunc_tol: float = 0.0):
-    """O(1) raised-cosine bilateral filter of a 2-D image (fused HIP kernel).
+                 return_aux: bool = False, trunc_tol: float = 0.0, path: int = nat.PATH_AUTO,
+                 workspace: torch.Tensor | None = None):
+    """O(1) raised-cosine bilateral filter of a 2-D image: the fused tile
+    kernel, or the streamed whole-line passes for wide spatial kernels (the
+    library's choice unless `path` forces one).  The streamed passes' workspace
+    comes from torch's allocator (`workspace`, else a fresh buffer of the
+    recommended size).
 
     Returns out, or (out, eta) with return_eta, or (out, eta, aux) with
     return_aux, where aux (2 x H x W) holds the sums the backward needs."""
@@ -42,9 +47,16 @@ def trig_forward(f: torch.Tensor, T: float, sigma_r: float, radii, N: int = 0,
     eta = torch.empty_like(f) if (return_eta or return_aux) else None
     aux = torch.empty((2, H, W), device=f.device, dtype=f.dtype) if return_aux else None
     spec = nat.SpatialSpec.of(radii)
-    nws = nat.workspace_bytes(H, W, radii)     # > 0: staged path for wide spatial kernels
-    ws = torch.empty(nws, device=f.device, dtype=torch.uint8) if nws else None
-    opts = nat.make_opts(_stream_ptr(), N, _ptr(eta), tile, _ptr(aux), _ptr(ws), nws, trunc_tol)
+    ws, nws = None, 0
+    if not return_aux and tile is None and path != nat.PATH_FUSED:
+        if workspace is not None:
+            ws, nws = workspace, workspace.numel() * workspace.element_size()
+        else:
+            nws = nat.workspace_bytes(H, W, radii) if path == nat.PATH_AUTO else \
+                nat.stream_workspace_bytes(H, W, 16)
+            ws = torch.empty(nws, device=f.device, dtype=torch.uint8) if nws else None
+    opts = nat.make_opts(_stream_ptr(), N, _ptr(eta), tile, _ptr(aux), _ptr(ws), nws, trunc_tol,
+                         path)
     nat.check(nat.lib().bf_trig_forward_ex(_ptr(f), H, W, float(T), float(sigma_r),
                                            ctypes.byref(spec), _ptr(out), ctypes.byref(opts)),
               "bf_trig_forward_ex")

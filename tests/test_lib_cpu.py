@@ -157,41 +157,52 @@ def test_phase_polynomial_constants_and_accuracy():
     assert np.abs(s - np.sin(xr)).max() < 2e-7
 
 
-def test_workspace_query_and_staged_validation():
-    """R <= 63 (every radius <= 31) runs fused and needs no workspace; up to
-    R = 124 (four boxes of 31) the staged path needs its channel planes with
-    zero margins plus den and num; wider kernels are unsupported.  The forward rejects a staged request without workspace
-    (BF_EINVAL) and a request for the adjoint's sums (BF_EUNSUPPORTED)."""
-    assert nat.workspace_bytes(64, 80, [9, 9, 10]) == 0
-    def staged(H, W):   # four channel planes with 128-column zero margins, den, num
-        return 4 * (4 * H * ((W + 260 + 63) // 64 * 64) + 2 * H * W)
-    # R = 63 still fits the fused kernel, but its tiles are 2 x 2 there: the
-    # cost model may ask for the staged workspace (the forward falls back to
-    # the fused kernel without it)
-    assert nat.workspace_bytes(64, 80, [31, 31, 1]) in (0, staged(64, 80))
-    assert nat.workspace_bytes(64, 80, [29, 29, 30]) == staged(64, 80)
-    assert nat.workspace_bytes(10, 10, [31, 31, 31, 31]) == staged(10, 10)   # R = 124
+def test_workspace_query_and_streamed_validation():
+    """Kernels the fused tiles hold at full size need no workspace; wider
+    ones (a radius above 31, R > 63) or ones whose tiles the halo shrinks go
+    through the streamed passes, whose recommended workspace is 16 pairs'
+    column-filtered planes (pitch W rounded up to 64) plus den and num.  The
+    documented limits, through the C ABI: radii up to BF_MAX_RADIUS = 256
+    (BF_ERANGE above), W + 2R <= 5184 and a composite mass below 2^31
+    (BF_EUNSUPPORTED otherwise); the adjoint's sums only from the fused
+    kernel; a workspace below one pair's, or not 256-byte aligned, and an
+    unknown path are BF_EINVAL.  None of these calls reaches the GPU."""
+    assert nat.BF_MAX_RADIUS == 256
+    assert nat.workspace_bytes(2048, 2048, [9, 9, 10]) == 0
+    assert nat.workspace_bytes(2048, 2048, [29, 29, 30]) == nat.stream_workspace_bytes(2048, 2048, 16)
+    assert nat.stream_workspace_bytes(64, 80, 16) == 16 * 16 * 64 * 128 + 8 * 64 * 80
+    assert nat.workspace_bytes(10, 10, [100, 100, 100]) == nat.stream_workspace_bytes(10, 10, 16)
+    assert nat.workspace_bytes(64, 4584, [100, 100, 100]) > 0        # W + 2R = 5184
     with pytest.raises(nat.BFError) as e:
-        nat.workspace_bytes(64, 80, [40])
+        nat.workspace_bytes(64, 4588, [100, 100, 100])               # W + 2R = 5188
     assert e.value.code == 6
     with pytest.raises(nat.BFError) as e:
-        nat.workspace_bytes(64, 80, [32, 31, 31])                 # a radius above 31
+        nat.workspace_bytes(64, 80, [257])
+    assert e.value.code == 2
+    with pytest.raises(nat.BFError) as e:
+        nat.workspace_bytes(16, 16, [200, 200, 200, 200])            # mass 401^4 > 2^31
     assert e.value.code == 6
     L = nat.lib()
     s = nat.SpatialSpec.of([29, 29, 30])
-    o = nat.make_opts(None, 0)
+    o2 = nat.make_opts(None, 0, None, None, FAKE3)
     assert L.bf_trig_forward_ex(FAKE, 8, 8, 255.0, 10.0, ctypes.byref(s), FAKE2,
-                                ctypes.byref(o)) == 1          # no workspace
-    o2 = nat.make_opts(None, 0, None, None, FAKE3, ctypes.c_void_p(0x40000000), 24 * 64)
-    assert L.bf_trig_forward_ex(FAKE, 8, 8, 255.0, 10.0, ctypes.byref(s), FAKE2,
-                                ctypes.byref(o2)) == 6         # aux_out with the staged path
-    o3 = nat.make_opts(None, 0, None, None, None, ctypes.c_void_p(0x40000000), 24 * 64 - 4)
+                                ctypes.byref(o2)) == 6         # aux_out with R = 88
+    one = nat.stream_workspace_bytes(8, 8, 1)
+    o3 = nat.make_opts(None, 0, None, None, None, ctypes.c_void_p(0x40000000), one - 4)
     assert L.bf_trig_forward_ex(FAKE, 8, 8, 255.0, 10.0, ctypes.byref(s), FAKE2,
                                 ctypes.byref(o3)) == 1         # workspace too small
-    o4 = nat.make_opts(None, 0, None, None, None, ctypes.c_void_p(0x40000004), staged(8, 8))
+    assert b"one cosine pair" in L.bf_last_error()
+    o4 = nat.make_opts(None, 0, None, None, None, ctypes.c_void_p(0x40000010), one)
     assert L.bf_trig_forward_ex(FAKE, 8, 8, 255.0, 10.0, ctypes.byref(s), FAKE2,
-                                ctypes.byref(o4)) == 1         # workspace not 16-byte aligned
+                                ctypes.byref(o4)) == 1         # workspace not 256-byte aligned
     assert b"aligned" in L.bf_last_error()
+    o5 = nat.make_opts(None, 0, path=3)
+    assert L.bf_trig_forward_ex(FAKE, 8, 8, 255.0, 10.0, ctypes.byref(s), FAKE2,
+                                ctypes.byref(o5)) == 1         # unknown path
+    s2 = nat.SpatialSpec.of([40, 2])
+    o6 = nat.make_opts(None, 0, path=1)
+    assert L.bf_trig_forward_ex(FAKE, 8, 8, 255.0, 10.0, ctypes.byref(s2), FAKE2,
+                                ctypes.byref(o6)) == 6         # fused forced, radius 40
 
 
 def _tail_bound(N, T, radii, Q):
