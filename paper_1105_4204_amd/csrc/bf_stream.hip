@@ -6,19 +6,21 @@
 // Column pass (bf_strm_v).  A box of width L is (1 - z^-L) / (1 - z^-1), so
 // the causal composite of nb boxes is
 //     b * x = S^nb d,   d[t] = sum_{A subset of boxes} (-1)^|A| x[t - sum_{k in A} L_k],
-// with S the running sum (integrator).  On integer samples every step is an
-// exact integer operation: the channels are quantised once (a fixed-point
-// grid close to float32 resolution), the sparse difference d takes 2^nb taps
-// of them, and the nb integrators run in FP64, which is exact for integers
-// below 2^53 (the composite's mass times the largest sample stays below that).
-// A lane owns one image column and G consecutive cosine pairs and walks down
-// the column; the taps are recomputed from f at their rows (phase, channel,
-// quantisation), so no history of the filtered signal is kept and nothing
-// depends on the radii except the tap offsets.  A lane may start part-way
-// down the image: it then treats the rows above its segment's halo as zero
-// and runs 2R warm-up rows, which reproduces the true integrator state
-// exactly.  Outputs (the column-filtered channels C, gC, S, gS of each pair;
-// 1, g for m = 0) go to row-major planes in the workspace.
+// with S the running sum (integrator).  A lane owns one image column and G
+// consecutive cosine pairs and walks down the column: at each row it
+// recomputes the channels at the 2^nb tap rows from f (phase, channel), forms
+// d from the float samples in FP64 and runs the nb integrators in FP64.  No
+// history of the filtered signal is kept, and nothing depends on the radii
+// but the tap offsets.  Integrators never damp their rounding errors; in FP64
+// the drift stays below 1e-5 of one sample after thousands of rows, far below
+// the float32 resolution of the outputs (a fixed-point grid instead would be
+// exact but, at a usable width, coarser than float32 on smooth regions, where
+// its error adds up coherently over the whole window).  A lane may start
+// part-way down the image: the integrator state there is a weighted sum of
+// the 2R + nb rows above (closed-form binomial weights of the taps), so the
+// start costs about a quarter of that many steps.  Outputs (the
+// column-filtered channels C, gC, S, gS of each pair; 1, g for m = 0) go to
+// row-major planes in the workspace.
 //
 // Row pass (bf_strm_h).  One workgroup per image row; wave w filters channel
 // w of each pair along the whole row with exact int32 box sums: the samples
@@ -45,8 +47,8 @@ namespace bf {
 constexpr int kSmThreads = 256;
 constexpr int kSmMaxTaps = 16;        // 2^BF_MAX_BOXES
 constexpr int kSmMaxGroups = 64;      // pair groups per chunk
+constexpr int kSmMaxChunk = 256;      // pairs per chunk
 constexpr int kSmLineMax = 81;        // row pass: samples per lane at most (odd)
-constexpr float kSmMagic = 12582912.0f;   // 1.5 * 2^23: fma(x, s, M) rounds x s to an integer
 
 // Cody-Waite split of pi/2: two 12-bit parts (exact products with |k| < 2^12)
 // and a float remainder.
@@ -77,34 +79,56 @@ struct StrmVArgs {
     float* vp;              // planes [pair][4][H][Wp]
     int H, W, Wp;
     int ntaps;
-    int toff[kSmMaxTaps];       // tap offsets (rows back from the current step)
-    float tsc[kSmMaxTaps][2];   // sign of the tap's coefficient times the scale (C, S / gC, gS)
-    int tmul[kSmMaxTaps];       // |coefficient|: 1, or a binomial count where offsets merge
-    uint32_t dbias;             // minus the magic constant's bits times sum |c_j|
+    int toff[kSmMaxTaps];   // tap offsets (rows back from the current step)
+    int tcoef[kSmMaxTaps];  // tap coefficients (+-1; binomial counts where offsets merge)
+    int kinit;              // rows of the segment-start sums: 2R + nb
     int R;
     int npairs;             // pairs of this chunk
     int ngroups, ncolg, seg, nseg;
     float center, two_alpha;
-    float vinv[2];          // inverse quantisation scale: C, S / gC, gS
     float mh[kSmMaxGroups], ml[kSmMaxGroups];   // m a of each group's first pair, hi + lo
 };
 
 template <int NB, int G>
 __global__ void __launch_bounds__(kSmThreads) bf_strm_v(const StrmVArgs a) {
     constexpr int NT = 1 << NB;
+    extern __shared__ double wtab[];   // [k][s]: integrator weights of the segment start
     const int lane = threadIdx.x & 63;
+    const int H = a.H;
+    // I_s[t] = sum_k w_s[k] x[t - k] with sum_k w_s[k] z^-k = D(z) / (1 - z^-1)^s,
+    // D the taps' polynomial: w_s[k] = sum_j c_j C(k - o_j + s - 1, s - 1) over
+    // o_j <= k (integers, exact in FP64); zero past k = 2R + nb - s.
+    for (int k = threadIdx.x; k < a.kinit; k += kSmThreads) {
+        double w[NB];
+#pragma unroll
+        for (int s = 0; s < NB; ++s) w[s] = 0.0;
+        for (int j = 0; j < a.ntaps; ++j) {
+            const double n = (double)(k - a.toff[j]);
+            if (n >= 0.0) {
+                const double c = (double)a.tcoef[j];
+                double b = 1.0;   // C(n + s, s) for s = 0, 1, ...
+#pragma unroll
+                for (int s = 0; s < NB; ++s) {
+                    w[s] += c * b;
+                    b = b * (n + (double)(s + 1)) / (double)(s + 1);
+                }
+            }
+        }
+#pragma unroll
+        for (int s = 0; s < NB; ++s) wtab[k * NB + s] = w[s];
+    }
+    __syncthreads();
     const int gw = blockIdx.x * (kSmThreads / 64) + (threadIdx.x >> 6);
     const int pg = gw % a.ngroups;
     const int rest = gw / a.ngroups;
     const int cg = rest % a.ncolg;
     const int sg = rest / a.ncolg;
-    if (sg >= a.nseg) return;
+    if (sg >= a.nseg) return;   // after the only barrier
     const int x = cg * 64 + lane;
-    if (x >= a.W) return;   // no barriers or LDS in this kernel
-    const int H = a.H;
+    if (x >= a.W) return;
     const int n0 = sg * a.seg, n1 = min(H, n0 + a.seg);
-    const int ylo = max(n0 - a.R, 0);   // rows above read as zero (warm-up from zero state)
-    const int tb = ylo, te = n1 + a.R, tout = n0 + a.R;
+    const int t0 = n0 + a.R;            // first step that emits a row (row n0)
+    const int te = n1 + a.R;
     const float mh = a.mh[pg], ml = a.ml[pg];
     const int q0 = pg * G;
     const int nq = min(G, a.npairs - q0);
@@ -115,14 +139,48 @@ __global__ void __launch_bounds__(kSmThreads) bf_strm_v(const StrmVArgs a) {
         for (int k = 0; k < 4; ++k)
 #pragma unroll
             for (int s = 0; s < NB; ++s) I[q][k][s] = 0.0;
+
+    // the state before step t0 from the rows above it: y = t0 - 1 - k in [0, H)
+    {
+        const int kb = max(0, t0 - H), ke = min(a.kinit - 1, t0 - 1);
+        float gpre = (a.f + (size_t)min(max(t0 - 1 - kb, 0), H - 1) * a.W)[x];
+        for (int k = kb; k <= ke; ++k) {
+            const float g = gpre - a.center;
+            gpre = (a.f + (size_t)max(t0 - 2 - k, 0) * a.W)[x];
+            float ur, ui, zr, zi;
+            cis_small(a.two_alpha * g, ur, ui);
+            cis_wide(mh, ml, g, zr, zi);
+            double w[NB];
+#pragma unroll
+            for (int s = 0; s < NB; ++s) w[s] = wtab[k * NB + s];
+#pragma unroll
+            for (int q = 0; q < G; ++q) {
+                const double c0 = (double)zr, c1 = (double)(g * zr);
+                const double c2 = (double)zi, c3 = (double)(g * zi);
+#pragma unroll
+                for (int s = 0; s < NB; ++s) {
+                    I[q][0][s] = fma(w[s], c0, I[q][0][s]);
+                    I[q][1][s] = fma(w[s], c1, I[q][1][s]);
+                    I[q][2][s] = fma(w[s], c2, I[q][2][s]);
+                    I[q][3][s] = fma(w[s], c3, I[q][3][s]);
+                }
+                if (q + 1 < G) {
+                    const float nr = zr * ur - zi * ui;
+                    zi = zr * ui + zi * ur;
+                    zr = nr;
+                }
+            }
+        }
+    }
+
     // tap rows are wave-uniform: row base in SGPRs, the lane's column as offset
     float gnext[NT];
 #pragma unroll
     for (int j = 0; j < NT; ++j) {
-        const int y = min(max(tb - a.toff[j], 0), H - 1);
+        const int y = min(max(t0 - a.toff[j], 0), H - 1);
         gnext[j] = (a.f + (size_t)y * a.W)[x];
     }
-    for (int t = tb; t < te; ++t) {
+    for (int t = t0; t < te; ++t) {
         float gcur[NT];
 #pragma unroll
         for (int j = 0; j < NT; ++j) gcur[j] = gnext[j];
@@ -132,45 +190,30 @@ __global__ void __launch_bounds__(kSmThreads) bf_strm_v(const StrmVArgs a) {
             const int y = min(max(t + 1 - a.toff[j], 0), H - 1);
             gnext[j] = (a.f + (size_t)y * a.W)[x];
         }
-        // d = sum_j c_j q_j: the sign of c_j rides on the quantisation scale
-        // (round to nearest even is odd-symmetric), |c_j| multiplies, and the
-        // magic constant's bits, added once per unit of |c_j|, are removed
-        // by the starting value
-        uint32_t d[G][4];
+        // d = sum_j c_j x[t - o_j], the float samples summed in FP64
+        double d[G][4];
 #pragma unroll
         for (int q = 0; q < G; ++q)
 #pragma unroll
-            for (int k = 0; k < 4; ++k) d[q][k] = a.dbias;
+            for (int k = 0; k < 4; ++k) d[q][k] = 0.0;
 #pragma unroll
         for (int j = 0; j < NT; ++j) {
             if (j < a.ntaps) {   // uniform
                 const int y = t - a.toff[j];
-                const bool in = y >= ylo && y < H;
+                const bool in = y >= 0 && y < H;
                 const float g = in ? gcur[j] - a.center : 0.0f;
                 float ur, ui, zr, zi;
                 cis_small(a.two_alpha * g, ur, ui);
                 cis_wide(mh, ml, g, zr, zi);
                 zr = in ? zr : 0.0f;
                 zi = in ? zi : 0.0f;
-                const float sc = a.tsc[j][0], sg2 = a.tsc[j][1];
-                const uint32_t mul = (uint32_t)a.tmul[j];
+                const double c = (double)a.tcoef[j];
 #pragma unroll
                 for (int q = 0; q < G; ++q) {
-                    const uint32_t b0 = __float_as_uint(fmaf(zr, sc, kSmMagic));
-                    const uint32_t b1 = __float_as_uint(fmaf(g * zr, sg2, kSmMagic));
-                    const uint32_t b2 = __float_as_uint(fmaf(zi, sc, kSmMagic));
-                    const uint32_t b3 = __float_as_uint(fmaf(g * zi, sg2, kSmMagic));
-                    if (mul == 1u) {   // uniform
-                        d[q][0] += b0;
-                        d[q][1] += b1;
-                        d[q][2] += b2;
-                        d[q][3] += b3;
-                    } else {
-                        d[q][0] += mul * b0;
-                        d[q][1] += mul * b1;
-                        d[q][2] += mul * b2;
-                        d[q][3] += mul * b3;
-                    }
+                    d[q][0] = fma(c, (double)zr, d[q][0]);
+                    d[q][1] = fma(c, (double)(g * zr), d[q][1]);
+                    d[q][2] = fma(c, (double)zi, d[q][2]);
+                    d[q][3] = fma(c, (double)(g * zi), d[q][3]);
                     if (q + 1 < G) {
                         const float nr = zr * ur - zi * ui;
                         zi = zr * ui + zi * ur;
@@ -183,21 +226,18 @@ __global__ void __launch_bounds__(kSmThreads) bf_strm_v(const StrmVArgs a) {
         for (int q = 0; q < G; ++q)
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
-                I[q][k][0] += (double)(int32_t)d[q][k];
+                I[q][k][0] += d[q][k];
 #pragma unroll
                 for (int s = 1; s < NB; ++s) I[q][k][s] += I[q][k][s - 1];
             }
-        if (t >= tout) {   // uniform
-            float* dst = a.vp + (size_t)(t - a.R) * a.Wp + x;
-            const size_t plane = (size_t)H * a.Wp;
+        float* dst = a.vp + (size_t)(t - a.R) * a.Wp + x;
+        const size_t plane = (size_t)H * a.Wp;
 #pragma unroll
-            for (int q = 0; q < G; ++q) {
-                if (q < nq) {   // uniform
+        for (int q = 0; q < G; ++q) {
+            if (q < nq) {   // uniform
 #pragma unroll
-                    for (int k = 0; k < 4; ++k)
-                        dst[((size_t)(q0 + q) * 4 + k) * plane] =
-                            (float)(I[q][k][NB - 1] * (double)a.vinv[k & 1]);
-                }
+                for (int k = 0; k < 4; ++k)
+                    dst[((size_t)(q0 + q) * 4 + k) * plane] = (float)I[q][k][NB - 1];
             }
         }
     }
@@ -216,12 +256,12 @@ struct StrmHArgs {
     int npairs;             // pairs of this chunk
     int centre0;            // the chunk's first pair is m = 0
     int first, last;        // first / last chunk
-    float center, two_alpha;
-    float mh, ml;           // m a of the chunk's first pair, hi + lo
+    float center;
     float hsc[2];           // stage-1 quantisation scale: C, S / gC, gS
     int sh[BF_MAX_BOXES][2];   // right shift after each stage
     float hout[2];          // value of one unit of the last stage's sums
-    float chat[kMaxPairs];  // coefficients of the chunk's pairs
+    float chat[kSmMaxChunk];          // coefficients of the chunk's pairs
+    float mh[kSmMaxChunk], ml[kSmMaxChunk];   // m a of each pair, hi + lo
 };
 
 // Exclusive prefix sum of v over the 64 lanes of a wave (modulo 2^32).
@@ -251,19 +291,16 @@ __global__ void __launch_bounds__(kSmThreads) bf_strm_h(const StrmHArgs a) {
     uint32_t* line = buf + a.padl;
     const int nx = (W + kSmThreads - 1) / kSmThreads;
 
-    // demodulation state of pixels x = t + 256 i
-    float zr[NX], zi[NX], ur[NX], ui[NX], den[NX], num[NX];
+    // demodulation state of pixels x = t + 256 i: g and the two sums (the
+    // phase of each pair is evaluated directly, so none is carried)
+    float gx[NX], den[NX], num[NX];
     const float* frow = a.f + (size_t)y * W;
 #pragma unroll
     for (int i = 0; i < NX; ++i) {
-        if (i < nx) {   // uniform
-            const int x = min(t + i * kSmThreads, W - 1);
-            const float g = frow[x] - a.center;
-            cis_small(a.two_alpha * g, ur[i], ui[i]);
-            cis_wide(a.mh, a.ml, g, zr[i], zi[i]);
-            den[i] = a.first ? 0.0f : a.part[(size_t)y * W + x];
-            num[i] = a.first ? 0.0f : a.part[(size_t)(a.H + y) * W + x];
-        }
+        const int x = min(t + i * kSmThreads, W - 1);
+        gx[i] = frow[x] - a.center;
+        den[i] = a.first ? 0.0f : a.part[(size_t)y * W + x];
+        num[i] = a.first ? 0.0f : a.part[(size_t)(a.H + y) * W + x];
     }
     __syncthreads();
 
@@ -276,21 +313,40 @@ __global__ void __launch_bounds__(kSmThreads) bf_strm_h(const StrmHArgs a) {
             const int cls = wave & 1;
             const float* src = a.vp + ((size_t)qq * 4 + wave) * plane + (size_t)y * a.Wp;
             const float hs = a.hsc[cls];
-            // the quantised row into the line at position R + x, in coalesced
-            // 16-byte loads (plane rows are 256-byte aligned, Wp >= W rounded
-            // up to 4); the margins [0, R) and [R + W4, 64 E) are zero
+            // the quantised row into the line at position R + x, in 16-byte
+            // buffer loads (lane offset in a register, the chunk in the
+            // instruction; the buffer ends at W rounded up to 4, so chunks past
+            // it read zero) and aligned 16-byte LDS stores; then the zero
+            // margins [0, R) and [R + W, end of the line)
             const int W4 = (W + 3) & ~3;
-            for (int x = 4 * lane; x < W4; x += 256) {
-                const float4 q = *reinterpret_cast<const float4*>(src + x);
-                uint4 o;
-                o.x = (uint32_t)__float2int_rn(q.x * hs);
-                o.y = (uint32_t)__float2int_rn((x + 1 < W ? q.y : 0.0f) * hs);
-                o.z = (uint32_t)__float2int_rn((x + 2 < W ? q.z : 0.0f) * hs);
-                o.w = (uint32_t)__float2int_rn((x + 3 < W ? q.w : 0.0f) * hs);
-                *reinterpret_cast<uint4*>(line + R + x) = o;
+            const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+                const_cast<float*>(src), 0, W4 * (int)sizeof(float), kBufferWord3);
+            uint32_t* dst4 = line + R + 4 * lane;
+            constexpr int NH = (NX + 1) / 2;   // two batches: half the staging registers
+#pragma unroll
+            for (int b = 0; b < NX; b += NH) {
+                float4 ld[NH];
+#pragma unroll
+                for (int i = 0; i < NH; ++i) {
+                    const auto q = __builtin_amdgcn_raw_buffer_load_b128(
+                        rs, 16 * lane, 1024 * (b + i), 0);
+                    ld[i] = make_float4(__uint_as_float(q[0]), __uint_as_float(q[1]),
+                                        __uint_as_float(q[2]), __uint_as_float(q[3]));
+                }
+#pragma unroll
+                for (int i = 0; i < NH; ++i) {
+                    if (b + i < NX) {
+                        uint4 o;
+                        o.x = (uint32_t)__float2int_rn(ld[i].x * hs);
+                        o.y = (uint32_t)__float2int_rn(ld[i].y * hs);
+                        o.z = (uint32_t)__float2int_rn(ld[i].z * hs);
+                        o.w = (uint32_t)__float2int_rn(ld[i].w * hs);
+                        *reinterpret_cast<uint4*>(dst4 + 256 * (b + i)) = o;
+                    }
+                }
             }
             for (int p = lane; p < R; p += 64) line[p] = 0u;
-            for (int p = R + W4 + lane; p < 64 * E; p += 64) line[p] = 0u;
+            for (int p = R + W + lane; p < 64 * E; p += 64) line[p] = 0u;
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
             __builtin_amdgcn_wave_barrier();
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
@@ -312,11 +368,17 @@ __global__ void __launch_bounds__(kSmThreads) bf_strm_h(const StrmHArgs a) {
                 __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
                 __builtin_amdgcn_wave_barrier();
                 __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-                // window sums: prefix at p + r minus prefix at p - r - 1
+                // window sums: prefix at p + r minus prefix at p - r - 1, in
+                // blocks of 8 (a scheduling fence keeps the compiler from
+                // hoisting all 2 E reads, which would hold 2 E registers)
                 const uint32_t* hi = line + p0 + r;
                 const uint32_t* lo = line + p0 - r - 1;
 #pragma unroll
-                for (int e = 0; e < E; ++e) v[e] = hi[e] - lo[e];
+                for (int e0 = 0; e0 < E; e0 += 8) {
+#pragma unroll
+                    for (int e = e0; e < (e0 + 8 < E ? e0 + 8 : E); ++e) v[e] = hi[e] - lo[e];
+                    __builtin_amdgcn_sched_barrier(0);
+                }
                 __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
                 __builtin_amdgcn_wave_barrier();
                 __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
@@ -334,14 +396,16 @@ __global__ void __launch_bounds__(kSmThreads) bf_strm_h(const StrmHArgs a) {
         __syncthreads();
         const float c = a.chat[qq];
         const float cc = c * a.hout[0], cg = c * a.hout[1];
+        const float mh = a.mh[qq], ml = a.ml[qq];
         const uint32_t* l0 = slds + a.padl + R;
         const uint32_t* l1 = l0 + a.bufsz;
         const uint32_t* l2 = l1 + a.bufsz;
         const uint32_t* l3 = l2 + a.bufsz;
+        // every pixel slot (slots past W read inside the lines and are never stored)
 #pragma unroll
         for (int i = 0; i < NX; ++i) {
-            if (i < nx) {   // uniform
-                const int x = min(t + i * kSmThreads, W - 1);
+            {
+                const int x = t + i * kSmThreads;
                 const float D0 = (float)(int32_t)l0[x];
                 const float D1 = (float)(int32_t)l1[x];
                 if (centre) {   // m = 0: channels 1 and g, C = 1, S = 0
@@ -350,12 +414,11 @@ __global__ void __launch_bounds__(kSmThreads) bf_strm_h(const StrmHArgs a) {
                 } else {
                     const float D2 = (float)(int32_t)l2[x];
                     const float D3 = (float)(int32_t)l3[x];
-                    den[i] = fmaf(cc * zr[i], D0, fmaf(cc * zi[i], D2, den[i]));
-                    num[i] = fmaf(cg * zr[i], D1, fmaf(cg * zi[i], D3, num[i]));
+                    float zr, zi;
+                    cis_wide(mh, ml, gx[i], zr, zi);
+                    den[i] = fmaf(cc * zr, D0, fmaf(cc * zi, D2, den[i]));
+                    num[i] = fmaf(cg * zr, D1, fmaf(cg * zi, D3, num[i]));
                 }
-                const float nr = zr[i] * ur[i] - zi[i] * ui[i];
-                zi[i] = zr[i] * ui[i] + zi[i] * ur[i];
-                zr[i] = nr;
             }
         }
         __syncthreads();
@@ -382,7 +445,7 @@ namespace {
 
 // pairs per lane in the column pass: the integrator state (4 channels x nb
 // doubles per pair) must leave room for two waves per SIMD
-constexpr int sm_group(int nb) { return nb <= 2 ? 8 : (nb == 3 ? 6 : 4); }
+constexpr int sm_group(int nb) { return nb <= 2 ? 6 : (nb == 3 ? 4 : 3); }
 
 // Row-pass instantiations: samples per lane (odd).
 constexpr int kSmLines[] = {9, 17, 25, 33, 37, 41, 45, 49, 57, 65, 69, 73, 81};
@@ -459,15 +522,17 @@ int stream_chunk_pairs(int64_t H, int64_t W, size_t ws_bytes, int npairs) {
     const size_t per = (size_t)16 * H * stream_plane_pitch(W);
     if (ws_bytes < part + per) return 0;
     size_t g = (ws_bytes - part) / per;
-    g = std::min<size_t>(g, (size_t)kSmMaxGroups * 4);
+    g = std::min<size_t>(g, (size_t)kSmMaxChunk);
     return (int)std::min<size_t>(g, (size_t)npairs);
 }
 
 namespace {
 
 template <int NB>
-void launch_v(const StrmVArgs& a, hipStream_t s, unsigned blocks) {
-    hipLaunchKernelGGL((bf_strm_v<NB, sm_group(NB)>), dim3(blocks), dim3(kSmThreads), 0, s, a);
+void launch_v(const StrmVArgs& a, hipStream_t s, unsigned blocks, size_t lds) {
+    (void)hipFuncSetAttribute((const void*)bf_strm_v<NB, sm_group(NB)>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipLaunchKernelGGL((bf_strm_v<NB, sm_group(NB)>), dim3(blocks), dim3(kSmThreads), lds, s, a);
 }
 
 template <int I = 0>
@@ -491,6 +556,7 @@ void launch_h(const StrmHArgs& a, int E, hipStream_t s, unsigned blocks, size_t 
 // the streamed passes cost the same for any R.
 constexpr double kFusedRoundUs = 16.0;        // per pair and round of fused tiles
 constexpr double kStreamPixUs = 2.0e-5;       // per pair and pixel, both passes
+constexpr double kStreamPairUs = 10.0;        // per pair: two launches, row-pass rounds
 
 bool prefer_stream(int64_t H, int64_t W, const SpatialParams& sp, bf_status fused_status,
                    const TileGeom& g) {
@@ -502,7 +568,7 @@ bool prefer_stream(int64_t H, int64_t W, const SpatialParams& sp, bf_status fuse
         cus <= 0)
         cus = 256;
     const double fused_us = std::ceil((double)g.tiles_x * g.tiles_y / cus) * kFusedRoundUs;
-    const double stream_us = (double)H * (double)W * kStreamPixUs;
+    const double stream_us = (double)H * (double)W * kStreamPixUs + kStreamPairUs;
     return stream_us < fused_us;
 }
 
@@ -526,30 +592,19 @@ bf_status launch_stream(const float* f, float* out, float* eta, int64_t H, int64
     const double Tg = (double)rp.center;                  // |g| <= T/2
     const double mass = mass_1d(sp);
 
-    // column pass: |x s| < 2^21 keeps the magic-constant rounding exact
+    // column pass: taps and the segment-start weights' extent
     StrmVArgs va = {};
     va.f = f;
     va.vp = vp;
     va.H = (int)H;
     va.W = (int)W;
     va.Wp = Wp;
-    int tcoef[kSmMaxTaps];
-    va.ntaps = make_taps(sp, va.toff, tcoef);
+    va.ntaps = make_taps(sp, va.toff, va.tcoef);
     va.R = sp.R;
     va.center = rp.center;
     va.two_alpha = (float)(2.0 * rp.alpha);
-    const int ev[2] = {21, floor_log2(2097152.0 / Tg)};
-    for (int c = 0; c < 2; ++c) va.vinv[c] = std::ldexp(1.0f, -ev[c]);
-    uint32_t units = 0;
-    for (int j = 0; j < va.ntaps; ++j) {
-        const int s = tcoef[j] > 0 ? 1 : -1;
-        for (int c = 0; c < 2; ++c) va.tsc[j][c] = (float)s * std::ldexp(1.0f, ev[c]);
-        va.tmul[j] = tcoef[j] > 0 ? tcoef[j] : -tcoef[j];
-        units += (uint32_t)va.tmul[j];
-    }
-    uint32_t mbits;
-    std::memcpy(&mbits, &kSmMagic, sizeof mbits);
-    va.dbias = 0u - mbits * units;
+    va.kinit = 2 * sp.R + sp.nb;
+    const size_t lds_v = (size_t)va.kinit * sp.nb * sizeof(double);
     // row pass scales: stage-1 samples |V| <= mass xmax; each stage's window
     // sum must stay below 2^30
     StrmHArgs ha = {};
@@ -570,9 +625,13 @@ bf_status launch_stream(const float* f, float* out, float* eta, int64_t H, int64
     }
     const int E = line_lanes(W, sp.R);
     ha.padl = ((rmax + 1 + sp.R + 3) & ~3) - sp.R;   // line + R is 16-byte aligned
-    ha.bufsz = (ha.padl + 64 * E + rmax + 1 + 3) & ~3;
+    // after the line: rmax + 1 for the window reads of unused outputs, and
+    // room for the row's 16-byte stores and the demodulation's pixel slots,
+    // which run to R + 256 ceil(64 E / 256)
+    const int nxs = (64 * E + kSmThreads - 1) / kSmThreads;
+    const int tail = std::max(rmax + 1, sp.R + kSmThreads * nxs - 64 * E);
+    ha.bufsz = (ha.padl + 64 * E + tail + 3) & ~3;
     ha.center = rp.center;
-    ha.two_alpha = va.two_alpha;
     const double xmax[2] = {1.0, Tg};
     for (int c = 0; c < 2; ++c) {
         // V samples are bounded by mass * xmax (plus the quantisation slack)
@@ -629,8 +688,9 @@ bf_status launch_stream(const float* f, float* out, float* eta, int64_t H, int64
             const int seg = (int)((H + ns - 1) / ns);
             if (ns > 1 && seg < 16) break;
             const double waves = (double)ncolg * ngroups * ns;
-            const double cost = std::ceil(waves / slots) * (seg + 2.0 * sp.R) +
-                                0.05 * waves / slots * (seg + 2.0 * sp.R);
+            const double start = ns > 1 ? 0.25 * (2.0 * sp.R + sp.nb) : 0.25 * sp.R;
+            const double cost = std::ceil(waves / slots) * (seg + start) +
+                                0.05 * waves / slots * (seg + start);
             if (cost < best_cost) {
                 best_cost = cost;
                 best = ns;
@@ -641,19 +701,21 @@ bf_status launch_stream(const float* f, float* out, float* eta, int64_t H, int64
         const long long waves = (long long)ncolg * ngroups * va.nseg;
         const unsigned vblocks = (unsigned)((waves + 3) / 4);
         switch (sp.nb) {
-            case 1: launch_v<1>(va, stream, vblocks); break;
-            case 2: launch_v<2>(va, stream, vblocks); break;
-            case 3: launch_v<3>(va, stream, vblocks); break;
-            default: launch_v<4>(va, stream, vblocks); break;
+            case 1: launch_v<1>(va, stream, vblocks, lds_v); break;
+            case 2: launch_v<2>(va, stream, vblocks, lds_v); break;
+            case 3: launch_v<3>(va, stream, vblocks, lds_v); break;
+            default: launch_v<4>(va, stream, vblocks, lds_v); break;
         }
         ha.npairs = np;
         ha.centre0 = (qb == 0 && rp.odd == 0) ? 1 : 0;
         ha.first = ci == 0;
         ha.last = ci == nchunks - 1;
-        const double ma = (double)(rp.odd + 2 * qb) * rp.alpha;
-        ha.mh = (float)ma;
-        ha.ml = (float)(ma - (double)ha.mh);
-        for (int q = 0; q < np; ++q) ha.chat[q] = rp.chat[qb + q];
+        for (int q = 0; q < np; ++q) {
+            ha.chat[q] = rp.chat[qb + q];
+            const double ma = (double)(rp.odd + 2 * (qb + q)) * rp.alpha;
+            ha.mh[q] = (float)ma;
+            ha.ml[q] = (float)(ma - (double)ha.mh[q]);
+        }
         launch_h(ha, E, stream, (unsigned)H, lds_h);
     }
     const hipError_t e = hipGetLastError();

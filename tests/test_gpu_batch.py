@@ -80,7 +80,7 @@ def test_batch_forward_only_and_rebind():
     from paper_1105_4204_amd import _native as nat
     for i, s in enumerate(SPECS[:3]):
         radii = s.get("radii") or nat.spatial_gaussian(s["sigma_s"], 3)
-        assert torch.equal(ops.trig_forward(f[i], 255.0, s["sigma_r"], radii), out[i])
+        assert torch.equal(ops.trig_forward(f[i], 255.0, s["sigma_r"], radii, path=1), out[i])
     # rebind to new buffers
     f2 = [x.flip(0).contiguous() for x in f]
     out2 = [torch.empty_like(x) for x in out]
@@ -89,7 +89,7 @@ def test_batch_forward_only_and_rebind():
     plan.check()
     for i, s in enumerate(SPECS[:3]):
         radii = s.get("radii") or nat.spatial_gaussian(s["sigma_s"], 3)
-        assert torch.equal(ops.trig_forward(f2[i], 255.0, s["sigma_r"], radii), out2[i])
+        assert torch.equal(ops.trig_forward(f2[i], 255.0, s["sigma_r"], radii, path=1), out2[i])
 
 
 def test_batch_graph_replay():
@@ -162,7 +162,7 @@ def test_colour_channels_as_batch_items():
     N = oracle.range_degree(255.0, 25.0)
     rng = np.random.default_rng(4)
     for c in range(3):
-        single = ops.trig_forward(x[c].contiguous(), 255.0, 25.0, [3, 3, 4])
+        single = ops.trig_forward(x[c].contiguous(), 255.0, 25.0, [3, 3, 4], path=1)
         torch.cuda.synchronize()
         assert torch.equal(single, out[c]), c
         idx = rng.integers(0, 120 * 150, size=20)

@@ -112,8 +112,8 @@ def test_forward_tile_override_consistent():
 
 def test_forward_fused_wide_kernel_tile_override():
     """R = 46 forced through the fused kernel (a tile shape is given, so the
-    staged path is not taken): 36 x 36 tiles on the 128-sample line, against
-    the oracle, and against the staged path the library picks unforced."""
+    streamed passes are not taken): 36 x 36 tiles on the 128-sample line,
+    against the oracle, and the evaluation the library picks unforced."""
     H, W, radii, sr = 90, 100, [15, 15, 16], 30.0
     f_np = synth.piecewise_smooth(H, W, seed=46, n_shapes=4)
     f = _cuda(f_np)

@@ -1,6 +1,6 @@
 """GPU checks of term truncation with an error bound (bf_range_truncate):
 the truncated filter stays within bound + the usual FP32 tolerance of the
-exact FP64 oracle, in the fused and the staged paths, the batch honours a
+exact FP64 oracle, in the fused and the streamed evaluations, the batch honours a
 per-image tolerance bit for bit, and the adjoint of the truncated forward is
 what autograd returns."""
 import numpy as np
@@ -63,7 +63,7 @@ def test_truncated_2048_sampled():
 
 
 def test_truncated_wide_kernel_sampled():
-    """The 4096^2, sigma_s = 30, N = 264 workload through the staged path with
+    """The 4096^2, sigma_s = 30, N = 264 workload through the streamed passes with
     truncation at 1e-2 gray (48 of 133 pairs)."""
     nat, ops, _ = _mods()
     f_np = synth.config_image(3)
@@ -111,6 +111,6 @@ def test_truncated_adjoint_and_batch():
     torch.cuda.synchronize()
     assert torch.equal(bo[0], o2)
     assert torch.equal(bg[0], g2)
-    o4 = ops.trig_forward(fs[1], 255.0, 30.0, [2, 2, 3])
+    o4 = ops.trig_forward(fs[1], 255.0, 30.0, [2, 2, 3], path=1)
     torch.cuda.synchronize()
     assert torch.equal(bo[1], o4)
