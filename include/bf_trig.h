@@ -125,17 +125,25 @@ bf_status bf_spatial_gaussian(double sigma_s, int32_t n_boxes, bf_spatial_spec* 
 /* Device workspace of the forward's streamed passes for image size H x W and
  * this spatial kernel: 0 when the library evaluates this geometry with the
  * fused tile kernel (no workspace), otherwise the recommended size,
- * 16 P H Wp + 8 H W bytes for P = 16 cosine pairs, Wp = W rounded up to a
- * multiple of 64.  The streamed passes (Sec. 2.1, eq. (final-form)) filter
+ * 16 P H Wp + 24 H W bytes for P = 16 cosine pairs, Wp = W rounded up to a
+ * multiple of 64 (of 4 for W < 64).  The streamed passes (Sec. 2.1, eq. (final-form)) filter
  * the four channels of each pair along whole columns and then whole rows;
  * the column-filtered channels of a chunk of pairs wait in the workspace
- * between the two passes, the partial den and num between chunks.  Any size
- * from one pair's (P = 1) up works: smaller workspaces only mean more chunks.
+ * between the two passes, the partial sums between chunks (and the adjoint's
+ * per-pixel weights).  Any size from one pair's (P = 1) up works: smaller
+ * workspaces only mean more chunks.
  * They run where the fused kernel cannot hold the kernel width (a radius
  * above 31 or R > 63) or where its tiles, shrunken by the halo, cost more.
  * BF_EUNSUPPORTED when neither evaluation handles the kernel. */
 bf_status bf_trig_workspace_bytes(int64_t H, int64_t W, const bf_spatial_spec* spatial_spec,
                                   int64_t* bytes_out);
+
+/* The same for a given degree (T, sigma_r and N as for the forward): the
+ * recommended size holds every cosine pair of that degree in one chunk, up to
+ * 4 GiB of planes (at least 16 pairs), which is the size of the library's
+ * own workspace.  0 where the fused kernel is used. */
+bf_status bf_trig_workspace_bytes_ex(int64_t H, int64_t W, float T, float sigma_r, int32_t N,
+                                     const bf_spatial_spec* spatial_spec, int64_t* bytes_out);
 
 /* Forward filter, eq. (BF)/(normalization) with the raised-cosine kernel.
  * f: H*W input; out: H*W output (must not overlap f).  sigma_r > 0, T > 0.

@@ -23,7 +23,7 @@ STATUS = {0: "BF_OK", 1: "BF_EINVAL", 2: "BF_ERANGE", 3: "BF_ENOMEM", 4: "BF_EDE
 
 # exported symbols, in the order include/bf_trig.h declares them
 EXPORTS = ["bf_range_degree", "bf_range_coeffs", "bf_range_truncate", "bf_spatial_gaussian",
-           "bf_trig_workspace_bytes", "bf_trig_forward",
+           "bf_trig_workspace_bytes", "bf_trig_workspace_bytes_ex", "bf_trig_forward",
            "bf_trig_forward_ex", "bf_trig_backward", "bf_sv_forward",
            "bf_yvv_coeffs", "bf_yvv_workspace_bytes", "bf_yvv_forward", "bf_direct_forward", "bf_check_range",
            "bf_batch_plan_create", "bf_batch_bind", "bf_batch_launch", "bf_batch_check",
@@ -91,6 +91,7 @@ def lib():
         "bf_range_truncate": [i32, f64, sp, f64, ctypes.POINTER(i32), ctypes.POINTER(f64)],
         "bf_spatial_gaussian": [f64, i32, sp],
         "bf_trig_workspace_bytes": [i64, i64, sp, ctypes.POINTER(i64)],
+        "bf_trig_workspace_bytes_ex": [i64, i64, f32, f32, i32, sp, ctypes.POINTER(i64)],
         "bf_trig_forward": [vp, i64, i64, f32, f32, sp, vp],
         "bf_trig_forward_ex": [vp, i64, i64, f32, f32, sp, vp, op],
         "bf_trig_backward": [vp, vp, vp, vp, vp, i64, i64, f32, f32, sp, vp, op],
@@ -183,10 +184,24 @@ def workspace_bytes(H: int, W: int, radii) -> int:
 
 def stream_workspace_bytes(H: int, W: int, pairs: int) -> int:
     """Workspace of the streamed passes for chunks of `pairs` cosine pairs:
-    four column-filtered planes per pair (pitch W rounded up to 64) plus the
-    den and num partials (the layout bf_trig_workspace_bytes documents)."""
-    Wp = (int(W) + 63) // 64 * 64
-    return 16 * int(pairs) * int(H) * Wp + 8 * int(H) * int(W)
+    four column-filtered planes per pair (pitch W rounded up to 64, to 4 below
+    64), the
+    partial sums and the adjoint's weights (the layout bf_trig_workspace_bytes
+    documents)."""
+    W = int(W)
+    Wp = (W + 3) // 4 * 4 if W < 64 else (W + 63) // 64 * 64
+    return 16 * int(pairs) * int(H) * Wp + 24 * int(H) * W
+
+
+def workspace_bytes_ex(H: int, W: int, T: float, sigma_r: float, N: int, radii) -> int:
+    """Recommended workspace of the streamed passes for this degree (every
+    pair in one chunk up to 4 GiB of planes; 0 where the fused kernel runs)."""
+    n = ctypes.c_int64()
+    spec = SpatialSpec.of(radii)
+    check(lib().bf_trig_workspace_bytes_ex(int(H), int(W), float(T), float(sigma_r), int(N),
+                                           ctypes.byref(spec), ctypes.byref(n)),
+          "bf_trig_workspace_bytes_ex")
+    return int(n.value)
 
 
 def yvv_coeffs(sigma_s: float):

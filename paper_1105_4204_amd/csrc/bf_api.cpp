@@ -116,6 +116,51 @@ bf_status library_workspace_done(hipStream_t stream) {
     return BF_OK;
 }
 
+// The streamed passes with the caller's workspace (validated) or the
+// library's own.
+bf_status run_stream(int mode, const StreamIO& io, int64_t H, int64_t W, const Common& c,
+                     const bf_opts* opts, int64_t bytes) {
+    if (!stream_supported(W, c.sp)) {
+        set_error("the streamed path handles W + 2R <= 5184 and a kernel mass below 2^31 "
+                  "(W=%lld, R=%d)", (long long)W, c.sp.R);
+        return BF_EUNSUPPORTED;
+    }
+    void* ws = opts ? opts->workspace : nullptr;
+    size_t wsb = opts && opts->workspace_bytes > 0 ? (size_t)opts->workspace_bytes : 0;
+    bf_status st = BF_OK;
+    if (ws) {
+        const void* imgs[9] = {io.f, io.out, io.eta, io.aux, io.fout, io.feta,
+                               io.faux, io.gout, io.gf};
+        const int64_t sizes[9] = {bytes, bytes, bytes, 2 * bytes, bytes, bytes,
+                                  2 * bytes, bytes, bytes};
+        for (int i = 0; i < 9; ++i) {
+            if (imgs[i] && overlaps(ws, (int64_t)wsb, imgs[i], sizes[i])) {
+                set_error("workspace must not overlap the images");
+                return BF_EINVAL;
+            }
+        }
+        if ((reinterpret_cast<uintptr_t>(ws) & 255) != 0) {
+            set_error("the streamed path's workspace must be 256-byte aligned");
+            return BF_EINVAL;
+        }
+        if (stream_chunk_pairs(H, W, wsb, c.rp.npairs) <= 0) {
+            set_error("workspace of %zu bytes is below the %zu bytes of one cosine pair",
+                      wsb, stream_workspace_bytes(H, W, 1));
+            return BF_EINVAL;
+        }
+    } else {
+        wsb = stream_default_workspace(H, W, c.rp.npairs);
+        st = library_workspace(wsb, c.stream, &ws);
+        if (st != BF_OK) return st;
+    }
+    st = launch_stream(mode, io, H, W, c.rp, c.sp, ws, wsb, c.stream);
+    if (!(opts && opts->workspace)) {
+        const bf_status st2 = library_workspace_done(c.stream);   // releases the lock
+        if (st == BF_OK) st = st2;
+    }
+    return st;
+}
+
 }  // namespace bf
 
 extern "C" {
@@ -147,57 +192,25 @@ bf_status bf_trig_forward_ex(const float* f, int64_t H, int64_t W, float T, floa
     const int req_h = opts ? opts->tile_h : 0, req_w = opts ? opts->tile_w : 0;
     const bf_status fst = plan_fwd_tiles(H, W, c.sp, req_h, req_w, &g);
     // the streamed passes: where the fused kernel cannot hold the kernel width,
-    // or where its shrunken tiles cost more (no adjoint sums requested and no
-    // tile shape forced), or on request
+    // or where its shrunken tiles cost more (no tile shape forced), or on request
     bool streamed;
-    if (path == BF_PATH_FUSED || aux || req_h > 0 || req_w > 0)
+    if (path == BF_PATH_FUSED || req_h > 0 || req_w > 0)
         streamed = false;
     else if (path == BF_PATH_STREAMED)
         streamed = true;
     else
         streamed = prefer_stream(H, W, c.sp, fst, g);
     if (!streamed) {
-        if (fst != BF_OK && aux && stream_supported(W, c.sp))
-            set_error("R=%d: the adjoint's sums (aux_out) are only produced by the fused "
-                      "kernel (every radius <= 31, R <= 63)", c.sp.R);
-        if (fst != BF_OK) return fst == BF_EUNSUPPORTED && aux ? BF_EUNSUPPORTED : fst;
+        if (fst != BF_OK) return fst;
         return launch_fwd(f, out, eta, aux, H, W, c.rp, c.sp, g, c.stream);
     }
-    if (!stream_supported(W, c.sp)) {
-        set_error("the streamed path handles W + 2R <= 5184 and a kernel mass below 2^31 "
-                  "(W=%lld, R=%d)", (long long)W, c.sp.R);
-        return BF_EUNSUPPORTED;
-    }
-    void* ws = opts ? opts->workspace : nullptr;
-    size_t wsb = opts && opts->workspace_bytes > 0 ? (size_t)opts->workspace_bytes : 0;
-    if (ws) {
-        if (overlaps(ws, (int64_t)wsb, f, bytes) || overlaps(ws, (int64_t)wsb, out, bytes) ||
-            overlaps(ws, (int64_t)wsb, eta, bytes)) {
-            set_error("workspace must not overlap the images");
-            return BF_EINVAL;
-        }
-        if ((reinterpret_cast<uintptr_t>(ws) & 255) != 0) {
-            set_error("the streamed path's workspace must be 256-byte aligned");
-            return BF_EINVAL;
-        }
-        if (stream_chunk_pairs(H, W, wsb, c.rp.npairs) <= 0) {
-            set_error("workspace of %zu bytes is below the %zu bytes of one cosine pair",
-                      wsb, stream_workspace_bytes(H, W, 1));
-            return BF_EINVAL;
-        }
-    } else {
-        wsb = stream_workspace_bytes(H, W, std::min(c.rp.npairs, kStreamChunkPairs));
-        st = library_workspace(wsb, c.stream, &ws);
-        if (st != BF_OK) return st;
-    }
-    st = launch_stream(f, out, eta, H, W, c.rp, c.sp, ws, wsb, c.stream);
-    if (!(opts && opts->workspace)) {
-        const bf_status st2 = library_workspace_done(c.stream);   // releases the lock
-        if (st == BF_OK) st = st2;
-    }
-    return st;
+    StreamIO io = {};
+    io.f = f;
+    io.out = out;
+    io.eta = eta;
+    io.aux = aux;
+    return run_stream(kStreamFwd, io, H, W, c, opts, bytes);
 }
-
 bf_status bf_trig_workspace_bytes(int64_t H, int64_t W, const bf_spatial_spec* spatial_spec,
                                   int64_t* bytes_out) {
     if (!bytes_out) {
@@ -223,6 +236,20 @@ bf_status bf_trig_workspace_bytes(int64_t H, int64_t W, const bf_spatial_spec* s
         set_error("neither the fused kernel nor the streamed passes handle W=%lld, R=%d",
                   (long long)W, sp.R);
     return st;
+}
+
+bf_status bf_trig_workspace_bytes_ex(int64_t H, int64_t W, float T, float sigma_r, int32_t N,
+                                     const bf_spatial_spec* spatial_spec, int64_t* bytes_out) {
+    bf_status st = bf_trig_workspace_bytes(H, W, spatial_spec, bytes_out);
+    if (st != BF_OK || *bytes_out == 0) return st;
+    RangeParams rp;
+    st = make_range((double)T, (double)sigma_r, N, &rp);
+    if (st != BF_OK) {
+        *bytes_out = 0;
+        return st;
+    }
+    *bytes_out = (int64_t)stream_default_workspace(H, W, rp.npairs);
+    return BF_OK;
 }
 
 bf_status bf_trig_forward(const float* f, int64_t H, int64_t W, float T, float sigma_r,
@@ -363,10 +390,34 @@ bf_status bf_trig_backward(const float* f, const float* out, const float* eta,
             return BF_EINVAL;
         }
     }
-    TileGeom g;
-    st = plan_bwd_tiles(H, W, c.sp, opts ? opts->tile_h : 0, opts ? opts->tile_w : 0, &g, f);
-    if (st != BF_OK) return st;
-    return launch_bwd(f, out, eta, aux, grad_out, grad_f, H, W, c.rp, c.sp, g, c.stream);
+    const int path = opts ? opts->path : BF_PATH_AUTO;
+    if (path != BF_PATH_AUTO && path != BF_PATH_FUSED && path != BF_PATH_STREAMED) {
+        set_error("opts->path=%d is not one of BF_PATH_AUTO, BF_PATH_FUSED, BF_PATH_STREAMED",
+                  path);
+        return BF_EINVAL;
+    }
+    const int req_h = opts ? opts->tile_h : 0, req_w = opts ? opts->tile_w : 0;
+    TileGeom g = {};
+    const bf_status fst = plan_bwd_tiles(H, W, c.sp, req_h, req_w, &g, f);
+    bool streamed;
+    if (path == BF_PATH_FUSED || req_h > 0 || req_w > 0)
+        streamed = false;
+    else if (path == BF_PATH_STREAMED)
+        streamed = true;
+    else
+        streamed = prefer_stream(H, W, c.sp, fst, g);
+    if (!streamed) {
+        if (fst != BF_OK) return fst;
+        return launch_bwd(f, out, eta, aux, grad_out, grad_f, H, W, c.rp, c.sp, g, c.stream);
+    }
+    StreamIO io = {};
+    io.f = f;
+    io.fout = out;
+    io.feta = eta;
+    io.faux = aux;
+    io.gout = grad_out;
+    io.gf = grad_f;
+    return run_stream(kStreamBwd, io, H, W, c, opts, bytes);
 }
 
 }  // extern "C"

@@ -76,20 +76,35 @@ bf_status launch_direct(const float* f, float* out, float* eta, int64_t H, int64
                         const RangeParams& rp, const SpatialParams& sp, hipStream_t stream);
 bf_status plan_bwd_tiles(int64_t H, int64_t W, const SpatialParams& sp, int req_h, int req_w,
                          TileGeom* g, const float* f);
-// Streamed forward for wide spatial kernels (bf_stream.hip): whole-line
-// column and row passes whose cost does not depend on the radii; the
-// column-filtered channels of a chunk of pairs pass through a workspace.
+// Streamed forward and adjoint (bf_stream.hip): whole-line column and row
+// passes whose cost does not depend on the radii; the column-filtered
+// channels of a chunk of pairs pass through a workspace.
+struct StreamIO {
+    const float* f;
+    float* out;           // forward
+    float* eta;           // forward, optional
+    float* aux;           // forward, optional (P, Q)
+    const float* fout;    // adjoint: the forward's out, eta and P, Q
+    const float* feta;
+    const float* faux;
+    const float* gout;    // adjoint: dL/dout
+    float* gf;            // adjoint: dL/df
+};
+constexpr int kStreamFwd = 0, kStreamBwd = 1;
 bool stream_supported(int64_t W, const SpatialParams& sp);
-size_t stream_workspace_bytes(int64_t H, int64_t W, int pairs);   // planes + den/num partials
+size_t stream_workspace_bytes(int64_t H, int64_t W, int pairs);   // planes + partials + A, B
 int stream_chunk_pairs(int64_t H, int64_t W, size_t ws_bytes, int npairs);
 bool prefer_stream(int64_t H, int64_t W, const SpatialParams& sp, bf_status fused_status,
                    const TileGeom& g);
-bf_status launch_stream(const float* f, float* out, float* eta, int64_t H, int64_t W,
+bf_status launch_stream(int mode, const StreamIO& io, int64_t H, int64_t W,
                         const RangeParams& rp, const SpatialParams& sp, void* workspace,
                         size_t ws_bytes, hipStream_t stream);
-// Pairs per chunk of the workspace the library allocates when the caller
-// passes none (and that bf_trig_workspace_bytes recommends).
+// Pairs per chunk of the workspace bf_trig_workspace_bytes recommends; the
+// library's own workspace and bf_trig_workspace_bytes_ex hold every pair up
+// to a budget of 4 GiB of planes (but at least this many pairs).
 constexpr int kStreamChunkPairs = 16;
+constexpr size_t kStreamBudget = (size_t)4 << 30;
+size_t stream_default_workspace(int64_t H, int64_t W, int npairs);
 // The library's own streamed-path workspace for the current device (bf_api.cpp):
 // library_workspace takes a lock and orders `stream` after the previous user;
 // library_workspace_done records that use and releases the lock.

@@ -1,7 +1,7 @@
-// Streamed forward for wide spatial kernels: eq. (final-form) with the
-// separable iterated-box averaging of Sec. 2.1 split into a column pass and a
-// row pass over whole image lines, so that the work per pixel and cosine pair
-// does not depend on the box radii.
+// Streamed forward and adjoint: eq. (final-form) with the separable
+// iterated-box averaging of Sec. 2.1 split into a column pass and a row pass
+// over whole image lines, so that the work per pixel and cosine pair does
+// not depend on the box radii.
 //
 // Column pass (bf_strm_v).  A box of width L is (1 - z^-L) / (1 - z^-1), so
 // the causal composite of nb boxes is
@@ -12,8 +12,8 @@
 // d from the float samples in FP64 and runs the nb integrators in FP64.  No
 // history of the filtered signal is kept, and nothing depends on the radii
 // but the tap offsets.  Integrators never damp their rounding errors; in FP64
-// the drift stays below 1e-5 of one sample after thousands of rows, far below
-// the float32 resolution of the outputs (a fixed-point grid instead would be
+// the drift stays far below the float32 resolution of the outputs over
+// segments of at most 2048 rows (a fixed-point grid instead would be
 // exact but, at a usable width, coarser than float32 on smooth regions, where
 // its error adds up coherently over the whole window).  A lane may start
 // part-way down the image: the integrator state there is a weighted sum of
@@ -24,13 +24,20 @@
 //
 // Row pass (bf_strm_h).  One workgroup per image row; wave w filters channel
 // w of each pair along the whole row with exact int32 box sums: the samples
-// are quantised, and each box stage is a wave prefix scan written to LDS and
-// differenced at +-(r+1) (the prefix wraps modulo 2^32; the window sums do
-// not, by the choice of scales).  Between stages the sums are shifted right
-// so that the next window sum fits again.  The four filtered channels then
-// meet in LDS and every thread demodulates its pixels with C and S from the
-// phase recurrence Z <- Z exp(j 2 a g), accumulating den and num across the
-// pairs; the last pair chunk divides in FP64.
+// are quantised on a grid scaled to the row's largest magnitude (so a window
+// sum of the first stage stays below 2^30), and each box stage is a wave
+// prefix scan written to LDS and differenced at +-(r+1) (the prefix wraps
+// modulo 2^32; the window sums do not).  Between stages the sums are shifted
+// right so that the next window sum fits again.  The four filtered channels
+// then meet in LDS and every thread demodulates its pixels with C and S
+// evaluated directly for each pair, accumulating den and num (and, for the
+// adjoint's sake, P and Q) across the pairs; the last pair chunk divides in
+// FP64.
+//
+// The adjoint (see the fused kernel's header for its formula) runs the same
+// two passes on the channels A C, B C, A S, B S (A = G / eta, B = A (out -
+// T/2), precomputed planes), demodulates with its own coefficients and adds
+// the closing term a (A P - B Q).
 //
 // Unlike the fused tile kernel, the column-filtered channels of a chunk of
 // pairs pass through device memory (16 bytes per pixel and pair, written
@@ -49,6 +56,8 @@ constexpr int kSmMaxTaps = 16;        // 2^BF_MAX_BOXES
 constexpr int kSmMaxGroups = 64;      // pair groups per chunk
 constexpr int kSmMaxChunk = 256;      // pairs per chunk
 constexpr int kSmLineMax = 81;        // row pass: samples per lane at most (odd)
+constexpr int kSmSegMax = 2048;       // column pass: rows per segment at most
+enum SmMode { kSmFwd = 0, kSmBwd = 1 };
 
 // Cody-Waite split of pi/2: two 12-bit parts (exact products with |k| < 2^12)
 // and a float remainder.
@@ -76,6 +85,7 @@ __device__ __forceinline__ void cis_wide(float mh, float ml, float g, float& c, 
 
 struct StrmVArgs {
     const float* f;
+    const float* ab;        // adjoint: A and B planes (2 H W)
     float* vp;              // planes [pair][4][H][Wp]
     int H, W, Wp;
     int ntaps;
@@ -89,9 +99,28 @@ struct StrmVArgs {
     float mh[kSmMaxGroups], ml[kSmMaxGroups];   // m a of each group's first pair, hi + lo
 };
 
-template <int NB, int G>
+// The four channels of a pair at one pixel: forward C, gC, S, gS (g = f -
+// T/2); adjoint A C, B C, A S, B S.
+template <int MODE>
+__device__ __forceinline__ void channels(float zr, float zi, float g, float av, float bv,
+                                         float (&c)[4]) {
+    if (MODE == kSmFwd) {
+        c[0] = zr;
+        c[1] = g * zr;
+        c[2] = zi;
+        c[3] = g * zi;
+    } else {
+        c[0] = av * zr;
+        c[1] = bv * zr;
+        c[2] = av * zi;
+        c[3] = bv * zi;
+    }
+}
+
+template <int NB, int G, int MODE>
 __global__ void __launch_bounds__(kSmThreads) bf_strm_v(const StrmVArgs a) {
     constexpr int NT = 1 << NB;
+    constexpr bool BWD = MODE == kSmBwd;
     extern __shared__ double wtab[];   // [k][s]: integrator weights of the segment start
     const int lane = threadIdx.x & 63;
     const int H = a.H;
@@ -132,6 +161,7 @@ __global__ void __launch_bounds__(kSmThreads) bf_strm_v(const StrmVArgs a) {
     const float mh = a.mh[pg], ml = a.ml[pg];
     const int q0 = pg * G;
     const int nq = min(G, a.npairs - q0);
+    const size_t HW = (size_t)H * a.W;
     double I[G][4][NB];
 #pragma unroll
     for (int q = 0; q < G; ++q)
@@ -143,10 +173,16 @@ __global__ void __launch_bounds__(kSmThreads) bf_strm_v(const StrmVArgs a) {
     // the state before step t0 from the rows above it: y = t0 - 1 - k in [0, H)
     {
         const int kb = max(0, t0 - H), ke = min(a.kinit - 1, t0 - 1);
-        float gpre = (a.f + (size_t)min(max(t0 - 1 - kb, 0), H - 1) * a.W)[x];
+        size_t o = (size_t)min(max(t0 - 1 - kb, 0), H - 1) * a.W + x;
+        float gpre = a.f[o], apre = BWD ? a.ab[o] : 0.0f, bpre = BWD ? a.ab[HW + o] : 0.0f;
         for (int k = kb; k <= ke; ++k) {
-            const float g = gpre - a.center;
-            gpre = (a.f + (size_t)max(t0 - 2 - k, 0) * a.W)[x];
+            const float g = gpre - a.center, av = apre, bv = bpre;
+            o = (size_t)max(t0 - 2 - k, 0) * a.W + x;
+            gpre = a.f[o];
+            if (BWD) {
+                apre = a.ab[o];
+                bpre = a.ab[HW + o];
+            }
             float ur, ui, zr, zi;
             cis_small(a.two_alpha * g, ur, ui);
             cis_wide(mh, ml, g, zr, zi);
@@ -155,15 +191,13 @@ __global__ void __launch_bounds__(kSmThreads) bf_strm_v(const StrmVArgs a) {
             for (int s = 0; s < NB; ++s) w[s] = wtab[k * NB + s];
 #pragma unroll
             for (int q = 0; q < G; ++q) {
-                const double c0 = (double)zr, c1 = (double)(g * zr);
-                const double c2 = (double)zi, c3 = (double)(g * zi);
+                float c[4];
+                channels<MODE>(zr, zi, g, av, bv, c);
 #pragma unroll
-                for (int s = 0; s < NB; ++s) {
-                    I[q][0][s] = fma(w[s], c0, I[q][0][s]);
-                    I[q][1][s] = fma(w[s], c1, I[q][1][s]);
-                    I[q][2][s] = fma(w[s], c2, I[q][2][s]);
-                    I[q][3][s] = fma(w[s], c3, I[q][3][s]);
-                }
+                for (int ch = 0; ch < 4; ++ch)
+#pragma unroll
+                    for (int s = 0; s < NB; ++s)
+                        I[q][ch][s] = fma(w[s], (double)c[ch], I[q][ch][s]);
                 if (q + 1 < G) {
                     const float nr = zr * ur - zi * ui;
                     zi = zr * ui + zi * ur;
@@ -174,21 +208,35 @@ __global__ void __launch_bounds__(kSmThreads) bf_strm_v(const StrmVArgs a) {
     }
 
     // tap rows are wave-uniform: row base in SGPRs, the lane's column as offset
-    float gnext[NT];
+    float gnext[NT], anext[NT], bnext[NT];
 #pragma unroll
     for (int j = 0; j < NT; ++j) {
-        const int y = min(max(t0 - a.toff[j], 0), H - 1);
-        gnext[j] = (a.f + (size_t)y * a.W)[x];
+        const size_t o = (size_t)min(max(t0 - a.toff[j], 0), H - 1) * a.W;
+        gnext[j] = (a.f + o)[x];
+        if (BWD) {
+            anext[j] = (a.ab + o)[x];
+            bnext[j] = (a.ab + HW + o)[x];
+        }
     }
     for (int t = t0; t < te; ++t) {
-        float gcur[NT];
+        float gcur[NT], acur[NT], bcur[NT];
 #pragma unroll
-        for (int j = 0; j < NT; ++j) gcur[j] = gnext[j];
+        for (int j = 0; j < NT; ++j) {
+            gcur[j] = gnext[j];
+            if (BWD) {
+                acur[j] = anext[j];
+                bcur[j] = bnext[j];
+            }
+        }
         // next step's taps: clamped unconditional loads, in flight during this step
 #pragma unroll
         for (int j = 0; j < NT; ++j) {
-            const int y = min(max(t + 1 - a.toff[j], 0), H - 1);
-            gnext[j] = (a.f + (size_t)y * a.W)[x];
+            const size_t o = (size_t)min(max(t + 1 - a.toff[j], 0), H - 1) * a.W;
+            gnext[j] = (a.f + o)[x];
+            if (BWD) {
+                anext[j] = (a.ab + o)[x];
+                bnext[j] = (a.ab + HW + o)[x];
+            }
         }
         // d = sum_j c_j x[t - o_j], the float samples summed in FP64
         double d[G][4];
@@ -207,13 +255,14 @@ __global__ void __launch_bounds__(kSmThreads) bf_strm_v(const StrmVArgs a) {
                 cis_wide(mh, ml, g, zr, zi);
                 zr = in ? zr : 0.0f;
                 zi = in ? zi : 0.0f;
-                const double c = (double)a.tcoef[j];
+                const float av = BWD ? acur[j] : 0.0f, bv = BWD ? bcur[j] : 0.0f;
+                const double cj = (double)a.tcoef[j];
 #pragma unroll
                 for (int q = 0; q < G; ++q) {
-                    d[q][0] = fma(c, (double)zr, d[q][0]);
-                    d[q][1] = fma(c, (double)(g * zr), d[q][1]);
-                    d[q][2] = fma(c, (double)zi, d[q][2]);
-                    d[q][3] = fma(c, (double)(g * zi), d[q][3]);
+                    float c[4];
+                    channels<MODE>(zr, zi, g, av, bv, c);
+#pragma unroll
+                    for (int ch = 0; ch < 4; ++ch) d[q][ch] = fma(cj, (double)c[ch], d[q][ch]);
                     if (q + 1 < G) {
                         const float nr = zr * ur - zi * ui;
                         zi = zr * ui + zi * ur;
@@ -243,24 +292,39 @@ __global__ void __launch_bounds__(kSmThreads) bf_strm_v(const StrmVArgs a) {
     }
 }
 
+// A = G / eta and B = A (out - T/2), the adjoint's per-pixel weights.
+__global__ void __launch_bounds__(kSmThreads) bf_strm_ab(const float* gout, const float* feta,
+                                                          const float* fout, float* ab,
+                                                          size_t n, float center) {
+    for (size_t i = (size_t)blockIdx.x * kSmThreads + threadIdx.x; i < n;
+         i += (size_t)gridDim.x * kSmThreads) {
+        const float A = gout[i] / feta[i];
+        ab[i] = A;
+        ab[n + i] = A * (fout[i] - center);
+    }
+}
+
 struct StrmHArgs {
     const float* f;
     const float* vp;
-    float* out;
-    float* eta;
-    float* part;            // den, num partial planes (2 H W) between chunks, or NULL
+    float* out;             // forward: filtered image; adjoint: dL/df
+    float* eta;             // forward: optional eta
+    float* aux;             // forward: optional P and Q planes (2 H W)
+    const float* faux;      // adjoint: P and Q of the forward
+    const float* ab;        // adjoint: A and B planes
+    float* part;            // partial sums between chunks (den, num, P, Q; adjoint: one)
     int H, W, Wp;
     int R, nb;
     int r[BF_MAX_BOXES];
-    int padl, bufsz;        // LDS: per wave padl zeros, then 64 E + rmax samples
+    int padl, bufsz;        // LDS: per wave padl zeros, then the line and its tail
     int npairs;             // pairs of this chunk
-    int centre0;            // the chunk's first pair is m = 0
+    int m0;                 // m of the chunk's first pair
     int first, last;        // first / last chunk
-    float center;
-    float hsc[2];           // stage-1 quantisation scale: C, S / gC, gS
-    int sh[BF_MAX_BOXES][2];   // right shift after each stage
-    float hout[2];          // value of one unit of the last stage's sums
-    float chat[kSmMaxChunk];          // coefficients of the chunk's pairs
+    float center, alpha;
+    int sh[BF_MAX_BOXES];   // right shift after each stage
+    int shtot;              // their sum
+    float L1;               // width of the first box
+    float chat[kSmMaxChunk];                  // coefficients of the chunk's pairs
     float mh[kSmMaxChunk], ml[kSmMaxChunk];   // m a of each pair, hi + lo
 };
 
@@ -275,53 +339,71 @@ __device__ __forceinline__ uint32_t wave_excl_scan(uint32_t v, int lane) {
     return incl - v;
 }
 
+__device__ __forceinline__ float wave_max(float v) {
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) v = fmaxf(v, __shfl_xor(v, o, 64));
+    return v;
+}
+
+__device__ __forceinline__ void wave_sync_lds() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // E: samples per lane (odd, so lanes E words apart hit distinct LDS banks);
-// the line covers 64 E >= W + 2R positions.
-template <int E>
+// the line covers 64 E >= W + 2R positions.  MODE: forward (AUX: also the
+// adjoint's sums P and Q) or adjoint.
+template <int E, int MODE, bool AUX>
 __global__ void __launch_bounds__(kSmThreads) bf_strm_h(const StrmHArgs a) {
     constexpr int NX = (64 * E + kSmThreads - 1) / kSmThreads;   // pixels per thread at most
+    constexpr bool BWD = MODE == kSmBwd;
+    constexpr int NACC = BWD ? 1 : (AUX ? 4 : 2);   // sums per pixel
     extern __shared__ __align__(16) uint32_t slds[];
     const int t = threadIdx.x;
     const int wave = __builtin_amdgcn_readfirstlane(t >> 6);
     const int lane = t & 63;
     const int y = blockIdx.x;
     const int W = a.W, R = a.R;
+    const size_t HW = (size_t)a.H * W;
     uint32_t* buf = slds + wave * a.bufsz;
     for (int i = lane; i < a.padl; i += 64) buf[i] = 0u;   // prefix before the line: 0
     uint32_t* line = buf + a.padl;
+    float* linef = reinterpret_cast<float*>(line);
     const int nx = (W + kSmThreads - 1) / kSmThreads;
 
-    // demodulation state of pixels x = t + 256 i: g and the two sums (the
-    // phase of each pair is evaluated directly, so none is carried)
-    float gx[NX], den[NX], num[NX];
+    // demodulation state of pixels x = t + 256 i: g and the sums (the phase
+    // of each pair is evaluated directly, so none is carried)
+    float gx[NX], acc[NACC][NX];
     const float* frow = a.f + (size_t)y * W;
 #pragma unroll
     for (int i = 0; i < NX; ++i) {
         const int x = min(t + i * kSmThreads, W - 1);
         gx[i] = frow[x] - a.center;
-        den[i] = a.first ? 0.0f : a.part[(size_t)y * W + x];
-        num[i] = a.first ? 0.0f : a.part[(size_t)(a.H + y) * W + x];
+#pragma unroll
+        for (int c = 0; c < NACC; ++c)
+            acc[c][i] = a.first ? 0.0f : a.part[c * HW + (size_t)y * W + x];
     }
     __syncthreads();
 
     const size_t plane = (size_t)a.H * a.Wp;
     const int p0 = lane * E;
     for (int qq = 0; qq < a.npairs; ++qq) {
-        const bool centre = a.centre0 && qq == 0;
-        const int nch = centre ? 2 : 4;
+        const int m = a.m0 + 2 * qq;
+        const bool centre = m == 0;
+        const int nch = centre ? (BWD ? 1 : 2) : 4;
         if (wave < nch) {
-            const int cls = wave & 1;
             const float* src = a.vp + ((size_t)qq * 4 + wave) * plane + (size_t)y * a.Wp;
-            const float hs = a.hsc[cls];
-            // the quantised row into the line at position R + x, in 16-byte
-            // buffer loads (lane offset in a register, the chunk in the
-            // instruction; the buffer ends at W rounded up to 4, so chunks past
-            // it read zero) and aligned 16-byte LDS stores; then the zero
-            // margins [0, R) and [R + W, end of the line)
+            // the row into the line at position R + x, raw, in 16-byte buffer
+            // loads (lane offset in a register, the chunk in the instruction;
+            // the buffer ends at W rounded up to 4, so chunks past it read zero)
+            // and aligned 16-byte LDS stores; then the zero margins [0, R) and
+            // [R + W, end of the line)
             const int W4 = (W + 3) & ~3;
             const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
                 const_cast<float*>(src), 0, W4 * (int)sizeof(float), kBufferWord3);
-            uint32_t* dst4 = line + R + 4 * lane;
+            float* dst4 = linef + R + 4 * lane;
+            float vmax = 0.0f;
             constexpr int NH = (NX + 1) / 2;   // two batches: half the staging registers
 #pragma unroll
             for (int b = 0; b < NX; b += NH) {
@@ -336,23 +418,26 @@ __global__ void __launch_bounds__(kSmThreads) bf_strm_h(const StrmHArgs a) {
 #pragma unroll
                 for (int i = 0; i < NH; ++i) {
                     if (b + i < NX) {
-                        uint4 o;
-                        o.x = (uint32_t)__float2int_rn(ld[i].x * hs);
-                        o.y = (uint32_t)__float2int_rn(ld[i].y * hs);
-                        o.z = (uint32_t)__float2int_rn(ld[i].z * hs);
-                        o.w = (uint32_t)__float2int_rn(ld[i].w * hs);
-                        *reinterpret_cast<uint4*>(dst4 + 256 * (b + i)) = o;
+                        const int x = 4 * lane + 256 * (b + i);
+                        // the max skips samples past W (row padding)
+                        vmax = fmaxf(vmax, fabsf(ld[i].x));
+                        vmax = fmaxf(vmax, x + 1 < W ? fabsf(ld[i].y) : 0.0f);
+                        vmax = fmaxf(vmax, x + 2 < W ? fabsf(ld[i].z) : 0.0f);
+                        vmax = fmaxf(vmax, x + 3 < W ? fabsf(ld[i].w) : 0.0f);
+                        *reinterpret_cast<float4*>(dst4 + 256 * (b + i)) = ld[i];
                     }
                 }
             }
             for (int p = lane; p < R; p += 64) line[p] = 0u;
             for (int p = R + W + lane; p < 64 * E; p += 64) line[p] = 0u;
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-            __builtin_amdgcn_wave_barrier();
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            wave_sync_lds();
+            // the grid: |q| L1 < 2^30 for the row's largest sample
+            vmax = wave_max(vmax);
+            const int e1 = vmax > 0.0f ? 30 - __builtin_amdgcn_frexp_expf(a.L1 * vmax) : 0;
             uint32_t v[E];
 #pragma unroll
-            for (int e = 0; e < E; ++e) v[e] = line[p0 + e];
+            for (int e = 0; e < E; ++e)
+                v[e] = (uint32_t)__float2int_rn(ldexpf(linef[p0 + e], e1));
             for (int k = 0; k < a.nb; ++k) {
                 const int r = a.r[k];
                 // inclusive prefix along the line: lane-local, then across lanes
@@ -365,9 +450,7 @@ __global__ void __launch_bounds__(kSmThreads) bf_strm_h(const StrmHArgs a) {
                 const uint32_t off = wave_excl_scan(tot, lane);
 #pragma unroll
                 for (int e = 0; e < E; ++e) line[p0 + e] = v[e] + off;
-                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-                __builtin_amdgcn_wave_barrier();
-                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+                wave_sync_lds();
                 // window sums: prefix at p + r minus prefix at p - r - 1, in
                 // blocks of 8 (a scheduling fence keeps the compiler from
                 // hoisting all 2 E reads, which would hold 2 E registers)
@@ -379,45 +462,54 @@ __global__ void __launch_bounds__(kSmThreads) bf_strm_h(const StrmHArgs a) {
                     for (int e = e0; e < (e0 + 8 < E ? e0 + 8 : E); ++e) v[e] = hi[e] - lo[e];
                     __builtin_amdgcn_sched_barrier(0);
                 }
-                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-                __builtin_amdgcn_wave_barrier();
-                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-                const int sh = a.sh[k][cls];
+                wave_sync_lds();
+                const int sh = a.sh[k];
                 if (k + 1 < a.nb && sh > 0) {   // uniform
                     const int rnd = 1 << (sh - 1);
 #pragma unroll
                     for (int e = 0; e < E; ++e) v[e] = (uint32_t)(((int32_t)v[e] + rnd) >> sh);
                 }
             }
-            // the filtered channel in place of the line, for the demodulation
+            // the filtered channel, as float, in place of the line
+            const int eo = a.shtot - e1;
 #pragma unroll
-            for (int e = 0; e < E; ++e) line[p0 + e] = v[e];
+            for (int e = 0; e < E; ++e) linef[p0 + e] = ldexpf((float)(int32_t)v[e], eo);
         }
         __syncthreads();
         const float c = a.chat[qq];
-        const float cc = c * a.hout[0], cg = c * a.hout[1];
         const float mh = a.mh[qq], ml = a.ml[qq];
-        const uint32_t* l0 = slds + a.padl + R;
-        const uint32_t* l1 = l0 + a.bufsz;
-        const uint32_t* l2 = l1 + a.bufsz;
-        const uint32_t* l3 = l2 + a.bufsz;
+        const float cm = c * (float)m;
+        const float* l0 = reinterpret_cast<const float*>(slds) + a.padl + R;
+        const float* l1 = l0 + a.bufsz;
+        const float* l2 = l1 + a.bufsz;
+        const float* l3 = l2 + a.bufsz;
         // every pixel slot (slots past W read inside the lines and are never stored)
 #pragma unroll
         for (int i = 0; i < NX; ++i) {
-            {
-                const int x = t + i * kSmThreads;
-                const float D0 = (float)(int32_t)l0[x];
-                const float D1 = (float)(int32_t)l1[x];
-                if (centre) {   // m = 0: channels 1 and g, C = 1, S = 0
-                    den[i] = fmaf(cc, D0, den[i]);
-                    num[i] = fmaf(cg, D1, num[i]);
+            const int x = t + i * kSmThreads;
+            const float D0 = l0[x];
+            if (centre) {   // m = 0: C = 1, S = 0
+                acc[0][i] = fmaf(c, D0, acc[0][i]);
+                if (!BWD) acc[1][i] = fmaf(c, l1[x], acc[1][i]);
+            } else {
+                const float D1 = l1[x], D2 = l2[x], D3 = l3[x];
+                float C, S;
+                cis_wide(mh, ml, gx[i], C, S);
+                if (!BWD) {
+                    acc[0][i] = fmaf(c * C, D0, fmaf(c * S, D2, acc[0][i]));
+                    acc[1][i] = fmaf(c * C, D1, fmaf(c * S, D3, acc[1][i]));
+                    if (AUX) {
+                        acc[2][i] = fmaf(cm * C, D3, fmaf(-cm * S, D1, acc[2][i]));
+                        acc[3][i] = fmaf(cm * C, D2, fmaf(-cm * S, D0, acc[3][i]));
+                    }
                 } else {
-                    const float D2 = (float)(int32_t)l2[x];
-                    const float D3 = (float)(int32_t)l3[x];
-                    float zr, zi;
-                    cis_wide(mh, ml, gx[i], zr, zi);
-                    den[i] = fmaf(cc * zr, D0, fmaf(cc * zi, D2, den[i]));
-                    num[i] = fmaf(cg * zr, D1, fmaf(cg * zi, D3, num[i]));
+                    // c {(C - ma g S) F[AC] + (S + ma g C) F[AS] + ma (S F[BC] - C F[BS])}
+                    const float u = mh * gx[i];
+                    float t2 = fmaf(C - u * S, D0, 0.0f);
+                    t2 = fmaf(S + u * C, D2, t2);
+                    t2 = fmaf(mh * S, D1, t2);
+                    t2 = fmaf(-mh * C, D3, t2);
+                    acc[0][i] = fmaf(c, t2, acc[0][i]);
                 }
             }
         }
@@ -428,12 +520,20 @@ __global__ void __launch_bounds__(kSmThreads) bf_strm_h(const StrmHArgs a) {
         const int x = t + i * kSmThreads;
         if (i < nx && x < W) {
             const size_t o = (size_t)y * W + x;
-            if (a.last) {
-                a.out[o] = (float)((double)a.center + (double)num[i] / (double)den[i]);
-                if (a.eta) a.eta[o] = den[i];
+            if (!a.last) {
+#pragma unroll
+                for (int c = 0; c < NACC; ++c) a.part[c * HW + o] = acc[c][i];
+            } else if (!BWD) {
+                a.out[o] = (float)((double)a.center + (double)acc[1][i] / (double)acc[0][i]);
+                if (a.eta) a.eta[o] = acc[0][i];
+                if (AUX) {
+                    a.aux[o] = acc[2][i];
+                    a.aux[HW + o] = acc[3][i];
+                }
             } else {
-                a.part[o] = den[i];
-                a.part[(size_t)a.H * W + o] = num[i];
+                const float A = a.ab[o], B = a.ab[HW + o];
+                const float P = a.faux[o], Q = a.faux[HW + o];
+                a.out[o] = fmaf(a.alpha, A * P - B * Q, acc[0][i]);
             }
         }
     }
@@ -495,17 +595,41 @@ double mass_1d(const SpatialParams& sp) {
     return m;
 }
 
-int floor_log2(double v) { return (int)std::floor(std::log2(v)); }
+// Plane rows start on 256-byte boundaries; narrow images keep 16-byte rows
+// (a 1-pixel-wide image would otherwise pad every row 64-fold).
+size_t plane_pitch(int64_t W) {
+    return W < 64 ? (size_t)((W + 3) / 4 * 4) : (size_t)((W + 63) / 64 * 64);
+}
+
+template <int NB, int MODE>
+void launch_v(const StrmVArgs& a, hipStream_t s, unsigned blocks, size_t lds) {
+    auto k = bf_strm_v<NB, sm_group(NB), MODE>;
+    (void)hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)lds);
+    hipLaunchKernelGGL(k, dim3(blocks), dim3(kSmThreads), lds, s, a);
+}
+
+template <int MODE, bool AUX, int I = 0>
+void launch_h(const StrmHArgs& a, int E, hipStream_t s, unsigned blocks, size_t lds) {
+    if constexpr (I < (int)(sizeof(kSmLines) / sizeof(kSmLines[0]))) {
+        if (E == kSmLines[I]) {
+            auto k = bf_strm_h<kSmLines[I], MODE, AUX>;
+            (void)hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                      (int)lds);
+            hipLaunchKernelGGL(k, dim3(blocks), dim3(kSmThreads), lds, s, a);
+            return;
+        }
+        launch_h<MODE, AUX, I + 1>(a, E, s, blocks, lds);
+    }
+}
 
 }  // namespace
-
-static size_t stream_plane_pitch(int64_t W) { return (size_t)((W + 63) / 64 * 64); }
 
 bool stream_supported(int64_t W, const SpatialParams& sp) {
     if (sp.nb < 1 || sp.nb > BF_MAX_BOXES) return false;
     if (line_lanes(W, sp.R) == 0) return false;   // W + 2R up to 64 x 81 samples
-    // FP64 integrators exact: mass * 2^22 < 2^53; row pass: a window of one
-    // stage must hold at least 2^8 quantisation levels of its input
+    // row pass: a window of one stage must hold 2^8 levels of its input
+    // within 2^30; column pass: the segment-start weights stay exact
     if (mass_1d(sp) >= 2147483648.0) return false;
     for (int k = 0; k < sp.nb; ++k)
         if (2 * sp.r[k] + 1 > (1 << 22)) return false;
@@ -513,66 +637,44 @@ bool stream_supported(int64_t W, const SpatialParams& sp) {
 }
 
 size_t stream_workspace_bytes(int64_t H, int64_t W, int pairs) {
-    return (size_t)16 * (size_t)pairs * (size_t)H * stream_plane_pitch(W) +
-           (size_t)8 * (size_t)H * (size_t)W;
+    return (size_t)16 * (size_t)pairs * (size_t)H * plane_pitch(W) +
+           (size_t)24 * (size_t)H * (size_t)W;
+}
+
+size_t stream_default_workspace(int64_t H, int64_t W, int npairs) {
+    const size_t per = (size_t)16 * H * plane_pitch(W);
+    const size_t budget = std::max<size_t>(kStreamBudget / per, kStreamChunkPairs);
+    const size_t pairs = std::min<size_t>(std::min<size_t>(budget, (size_t)npairs), kSmMaxChunk);
+    return stream_workspace_bytes(H, W, (int)pairs);
 }
 
 int stream_chunk_pairs(int64_t H, int64_t W, size_t ws_bytes, int npairs) {
-    const size_t part = (size_t)8 * H * W;
-    const size_t per = (size_t)16 * H * stream_plane_pitch(W);
-    if (ws_bytes < part + per) return 0;
-    size_t g = (ws_bytes - part) / per;
+    const size_t fixed = (size_t)24 * H * W;
+    const size_t per = (size_t)16 * H * plane_pitch(W);
+    if (ws_bytes < fixed + per) return 0;
+    size_t g = (ws_bytes - fixed) / per;
     g = std::min<size_t>(g, (size_t)kSmMaxChunk);
     return (int)std::min<size_t>(g, (size_t)npairs);
 }
 
-namespace {
-
-template <int NB>
-void launch_v(const StrmVArgs& a, hipStream_t s, unsigned blocks, size_t lds) {
-    (void)hipFuncSetAttribute((const void*)bf_strm_v<NB, sm_group(NB)>,
-                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    hipLaunchKernelGGL((bf_strm_v<NB, sm_group(NB)>), dim3(blocks), dim3(kSmThreads), lds, s, a);
-}
-
-template <int I = 0>
-void launch_h(const StrmHArgs& a, int E, hipStream_t s, unsigned blocks, size_t lds) {
-    if constexpr (I < (int)(sizeof(kSmLines) / sizeof(kSmLines[0]))) {
-        if (E == kSmLines[I]) {
-            (void)hipFuncSetAttribute((const void*)bf_strm_h<kSmLines[I]>,
-                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-            hipLaunchKernelGGL(bf_strm_h<kSmLines[I]>, dim3(blocks), dim3(kSmThreads), lds, s, a);
-            return;
-        }
-        launch_h<I + 1>(a, E, s, blocks, lds);
-    }
-}
-
-}  // namespace
-
-// Cost model per cosine pair, calibrated on MI355X: a round of fused tiles
-// (one workgroup per CU) against the streamed passes' time per pixel.  The
-// fused tiles shrink as R grows (the extended line is at most 128 samples);
-// the streamed passes cost the same for any R.
-constexpr double kFusedRoundUs = 16.0;        // per pair and round of fused tiles
-constexpr double kStreamPixUs = 2.0e-5;       // per pair and pixel, both passes
-constexpr double kStreamPairUs = 10.0;        // per pair: two launches, row-pass rounds
-
+// Which evaluation runs by default.  Measured on MI355X, the streamed passes
+// beat the fused tiles at every size tried, forward and adjoint: 64^2 to
+// 2048^2, radii 1 to 16 per box (2048^2, N = 66, boxes 9, 9, 10: forward with
+// the adjoint's sums 2.20 -> 1.67 ms, adjoint 2.27 -> 1.73 ms; 256^2, box
+// r = 5: 0.20 -> 0.067 ms).  The fused tiles pay a whole round per tile for
+// every pair and their halo work grows with R; the streamed passes pay
+// 32 bytes of device memory per pixel and pair, the same for any R.  So the
+// streamed passes run wherever they apply (W + 2R within their line), the
+// fused tiles elsewhere.
 bool prefer_stream(int64_t H, int64_t W, const SpatialParams& sp, bf_status fused_status,
                    const TileGeom& g) {
-    if (!stream_supported(W, sp)) return false;
-    if (fused_status != BF_OK) return true;
-    int dev = 0, cus = 0;
-    if (hipGetDevice(&dev) != hipSuccess ||
-        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
-        cus <= 0)
-        cus = 256;
-    const double fused_us = std::ceil((double)g.tiles_x * g.tiles_y / cus) * kFusedRoundUs;
-    const double stream_us = (double)H * (double)W * kStreamPixUs + kStreamPairUs;
-    return stream_us < fused_us;
+    (void)H;
+    (void)fused_status;
+    (void)g;
+    return stream_supported(W, sp);
 }
 
-bf_status launch_stream(const float* f, float* out, float* eta, int64_t H, int64_t W,
+bf_status launch_stream(int mode, const StreamIO& io, int64_t H, int64_t W,
                         const RangeParams& rp, const SpatialParams& sp, void* workspace,
                         size_t ws_bytes, hipStream_t stream) {
     if (!stream_supported(W, sp)) {
@@ -586,15 +688,23 @@ bf_status launch_stream(const float* f, float* out, float* eta, int64_t H, int64
                   ws_bytes, stream_workspace_bytes(H, W, 1));
         return BF_EINVAL;
     }
-    const int Wp = (int)stream_plane_pitch(W);
+    const bool bwd = mode == kSmBwd;
+    const bool aux = !bwd && io.aux != nullptr;
+    const int Wp = (int)plane_pitch(W);
+    const size_t HW = (size_t)H * (size_t)W;
     float* vp = static_cast<float*>(workspace);
     float* part = vp + (size_t)4 * chunk * H * Wp;
-    const double Tg = (double)rp.center;                  // |g| <= T/2
-    const double mass = mass_1d(sp);
+    float* ab = part + 4 * HW;
+    if (bwd) {
+        const unsigned nb = (unsigned)std::min<size_t>((HW + kSmThreads - 1) / kSmThreads, 4096);
+        hipLaunchKernelGGL(bf_strm_ab, dim3(nb), dim3(kSmThreads), 0, stream, io.gout, io.feta,
+                           io.fout, ab, HW, rp.center);
+    }
 
     // column pass: taps and the segment-start weights' extent
     StrmVArgs va = {};
-    va.f = f;
+    va.f = io.f;
+    va.ab = ab;
     va.vp = vp;
     va.H = (int)H;
     va.W = (int)W;
@@ -605,23 +715,46 @@ bf_status launch_stream(const float* f, float* out, float* eta, int64_t H, int64
     va.two_alpha = (float)(2.0 * rp.alpha);
     va.kinit = 2 * sp.R + sp.nb;
     const size_t lds_v = (size_t)va.kinit * sp.nb * sizeof(double);
-    // row pass scales: stage-1 samples |V| <= mass xmax; each stage's window
-    // sum must stay below 2^30
+
+    // row pass: the first stage's grid comes from each row's largest sample
+    // (|q| L1 < 2^30); the shifts after each stage keep the next window sum
+    // below 2^30 for that worst case
     StrmHArgs ha = {};
-    ha.f = f;
+    ha.f = io.f;
     ha.vp = vp;
-    ha.out = out;
-    ha.eta = eta;
+    ha.out = bwd ? io.gf : io.out;
+    ha.eta = io.eta;
+    ha.aux = io.aux;
+    ha.faux = io.faux;
+    ha.ab = ab;
     ha.part = part;
     ha.H = (int)H;
     ha.W = (int)W;
     ha.Wp = Wp;
     ha.R = sp.R;
     ha.nb = sp.nb;
+    ha.center = rp.center;
+    ha.alpha = (float)rp.alpha;
+    ha.L1 = (float)(2 * sp.r[0] + 1);
     int rmax = 0;
     for (int k = 0; k < sp.nb; ++k) {
         ha.r[k] = sp.r[k];
         rmax = std::max(rmax, sp.r[k]);
+    }
+    {
+        double qmax = 1073741824.0 / (2.0 * sp.r[0] + 1.0) + 1.0;
+        ha.shtot = 0;
+        for (int k = 0; k < sp.nb; ++k) {
+            const double smax = (2.0 * sp.r[k] + 1.0) * qmax;   // window sum of stage k
+            int sh = 0;
+            if (k + 1 < sp.nb) {
+                const double lim = 1073741824.0 / (2.0 * sp.r[k + 1] + 1.0);
+                while (smax / std::ldexp(1.0, sh) + 1.0 > lim) ++sh;
+                qmax = smax / std::ldexp(1.0, sh) + 1.0;
+                ha.shtot += sh;
+            }
+            ha.sh[k] = sh;
+        }
     }
     const int E = line_lanes(W, sp.R);
     ha.padl = ((rmax + 1 + sp.R + 3) & ~3) - sp.R;   // line + R is 16-byte aligned
@@ -631,28 +764,6 @@ bf_status launch_stream(const float* f, float* out, float* eta, int64_t H, int64
     const int nxs = (64 * E + kSmThreads - 1) / kSmThreads;
     const int tail = std::max(rmax + 1, sp.R + kSmThreads * nxs - 64 * E);
     ha.bufsz = (ha.padl + 64 * E + tail + 3) & ~3;
-    ha.center = rp.center;
-    const double xmax[2] = {1.0, Tg};
-    for (int c = 0; c < 2; ++c) {
-        // V samples are bounded by mass * xmax (plus the quantisation slack)
-        const double vmax = mass * xmax[c] * (1.0 + 1e-6) + 1.0;
-        const int e1 = floor_log2(1073741824.0 / ((2.0 * sp.r[0] + 1.0) * vmax));
-        ha.hsc[c] = std::ldexp(1.0f, e1);
-        double qmax = vmax * std::ldexp(1.0, e1) + 1.0;
-        int total = 0;
-        for (int k = 0; k < sp.nb; ++k) {
-            const double smax = (2.0 * sp.r[k] + 1.0) * qmax;   // window sum of stage k
-            int sh = 0;
-            if (k + 1 < sp.nb) {
-                const double lim = 1073741824.0 / (2.0 * sp.r[k + 1] + 1.0);
-                while (smax / std::ldexp(1.0, sh) + 1.0 > lim) ++sh;
-                qmax = smax / std::ldexp(1.0, sh) + 1.0;
-                total += sh;
-            }
-            ha.sh[k][c] = sh;
-        }
-        ha.hout[c] = (float)std::ldexp(1.0, total - e1);
-    }
     const size_t lds_h = (size_t)4 * ha.bufsz * sizeof(uint32_t);
     if (lds_h > 160 * 1024) {
         set_error("streamed path: row pass needs %zu bytes of LDS", lds_h);
@@ -660,8 +771,9 @@ bf_status launch_stream(const float* f, float* out, float* eta, int64_t H, int64
     }
 
     // the column pass's parallelism: 64-column groups x pair groups x row
-    // segments, with 2R warm-up rows per segment; pick the segment count
-    // with the least modelled time (waves in flight: 8 per CU)
+    // segments, each starting from the exact state summed over the 2R + nb
+    // rows above it; pick the segment count with the least modelled time
+    // (waves in flight: 8 per CU)
     int dev = 0, cus = 256;
     if (hipGetDevice(&dev) == hipSuccess)
         (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
@@ -682,11 +794,15 @@ bf_status launch_stream(const float* f, float* out, float* eta, int64_t H, int64
             va.mh[g] = (float)ma;
             va.ml[g] = (float)(ma - (double)va.mh[g]);
         }
-        int best = 1;
+        // segments of at most kSmSegMax rows: the FP64 integrators' rounding
+        // drifts roughly as the cube of the rows run (a 16384-row column
+        // reached 3e-2 gray); each segment starts from the exact state
+        const int ns0 = (int)((H + kSmSegMax - 1) / kSmSegMax);
+        int best = ns0;
         double best_cost = 1e300;
-        for (int ns = 1; ns <= 64; ++ns) {
+        for (int ns = ns0; ns <= ns0 + 64; ++ns) {
             const int seg = (int)((H + ns - 1) / ns);
-            if (ns > 1 && seg < 16) break;
+            if (ns > ns0 && seg < 16) break;
             const double waves = (double)ncolg * ngroups * ns;
             const double start = ns > 1 ? 0.25 * (2.0 * sp.R + sp.nb) : 0.25 * sp.R;
             const double cost = std::ceil(waves / slots) * (seg + start) +
@@ -700,14 +816,23 @@ bf_status launch_stream(const float* f, float* out, float* eta, int64_t H, int64
         va.seg = (int)((H + best - 1) / best);
         const long long waves = (long long)ncolg * ngroups * va.nseg;
         const unsigned vblocks = (unsigned)((waves + 3) / 4);
-        switch (sp.nb) {
-            case 1: launch_v<1>(va, stream, vblocks, lds_v); break;
-            case 2: launch_v<2>(va, stream, vblocks, lds_v); break;
-            case 3: launch_v<3>(va, stream, vblocks, lds_v); break;
-            default: launch_v<4>(va, stream, vblocks, lds_v); break;
+        if (bwd) {
+            switch (sp.nb) {
+                case 1: launch_v<1, kSmBwd>(va, stream, vblocks, lds_v); break;
+                case 2: launch_v<2, kSmBwd>(va, stream, vblocks, lds_v); break;
+                case 3: launch_v<3, kSmBwd>(va, stream, vblocks, lds_v); break;
+                default: launch_v<4, kSmBwd>(va, stream, vblocks, lds_v); break;
+            }
+        } else {
+            switch (sp.nb) {
+                case 1: launch_v<1, kSmFwd>(va, stream, vblocks, lds_v); break;
+                case 2: launch_v<2, kSmFwd>(va, stream, vblocks, lds_v); break;
+                case 3: launch_v<3, kSmFwd>(va, stream, vblocks, lds_v); break;
+                default: launch_v<4, kSmFwd>(va, stream, vblocks, lds_v); break;
+            }
         }
         ha.npairs = np;
-        ha.centre0 = (qb == 0 && rp.odd == 0) ? 1 : 0;
+        ha.m0 = rp.odd + 2 * qb;
         ha.first = ci == 0;
         ha.last = ci == nchunks - 1;
         for (int q = 0; q < np; ++q) {
@@ -716,7 +841,12 @@ bf_status launch_stream(const float* f, float* out, float* eta, int64_t H, int64
             ha.mh[q] = (float)ma;
             ha.ml[q] = (float)(ma - (double)ha.mh[q]);
         }
-        launch_h(ha, E, stream, (unsigned)H, lds_h);
+        if (bwd)
+            launch_h<kSmBwd, false>(ha, E, stream, (unsigned)H, lds_h);
+        else if (aux)
+            launch_h<kSmFwd, true>(ha, E, stream, (unsigned)H, lds_h);
+        else
+            launch_h<kSmFwd, false>(ha, E, stream, (unsigned)H, lds_h);
     }
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) {

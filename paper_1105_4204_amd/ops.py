@@ -29,15 +29,32 @@ def _ptr(x):
     return ctypes.c_void_p(x.data_ptr()) if x is not None else None
 
 
+def _stream_workspace(f, H, W, T, sigma_r, radii, N, path, tile, workspace):
+    """(tensor, bytes) of the streamed passes' workspace: the caller's, else
+    one of the size the library recommends for this degree from torch's
+    allocator (none where the fused kernel runs)."""
+    if tile is not None or path == nat.PATH_FUSED:
+        return None, 0
+    if workspace is not None:
+        return workspace, workspace.numel() * workspace.element_size()
+    if path == nat.PATH_AUTO:
+        nws = nat.workspace_bytes_ex(H, W, T, sigma_r, N, radii)
+    else:
+        n = N or nat.range_degree(T, sigma_r)
+        nws = nat.stream_workspace_bytes(H, W, min(n // 2 + 1, 256))
+    if not nws:
+        return None, 0
+    return torch.empty(nws, device=f.device, dtype=torch.uint8), nws
+
+
 def trig_forward(f: torch.Tensor, T: float, sigma_r: float, radii, N: int = 0,
                  return_eta: bool = False, tile=None, out: torch.Tensor | None = None,
                  return_aux: bool = False, trunc_tol: float = 0.0, path: int = nat.PATH_AUTO,
                  workspace: torch.Tensor | None = None):
     """O(1) raised-cosine bilateral filter of a 2-D image: the fused tile
-    kernel, or the streamed whole-line passes for wide spatial kernels (the
-    library's choice unless `path` forces one).  The streamed passes' workspace
-    comes from torch's allocator (`workspace`, else a fresh buffer of the
-    recommended size).
+    kernel, or the streamed whole-line passes (the library's choice unless
+    `path` forces one).  The streamed passes' workspace comes from torch's
+    allocator (`workspace`, else a fresh buffer of the recommended size).
 
     Returns out, or (out, eta) with return_eta, or (out, eta, aux) with
     return_aux, where aux (2 x H x W) holds the sums the backward needs."""
@@ -47,14 +64,7 @@ def trig_forward(f: torch.Tensor, T: float, sigma_r: float, radii, N: int = 0,
     eta = torch.empty_like(f) if (return_eta or return_aux) else None
     aux = torch.empty((2, H, W), device=f.device, dtype=f.dtype) if return_aux else None
     spec = nat.SpatialSpec.of(radii)
-    ws, nws = None, 0
-    if not return_aux and tile is None and path != nat.PATH_FUSED:
-        if workspace is not None:
-            ws, nws = workspace, workspace.numel() * workspace.element_size()
-        else:
-            nws = nat.workspace_bytes(H, W, radii) if path == nat.PATH_AUTO else \
-                nat.stream_workspace_bytes(H, W, 16)
-            ws = torch.empty(nws, device=f.device, dtype=torch.uint8) if nws else None
+    ws, nws = _stream_workspace(f, H, W, T, sigma_r, radii, N, path, tile, workspace)
     opts = nat.make_opts(_stream_ptr(), N, _ptr(eta), tile, _ptr(aux), _ptr(ws), nws, trunc_tol,
                          path)
     nat.check(nat.lib().bf_trig_forward_ex(_ptr(f), H, W, float(T), float(sigma_r),
@@ -137,8 +147,10 @@ def yvv_forward(f: torch.Tensor, T: float, sigma_r: float, sigma_s: float, N: in
 
 
 def trig_backward(f, out, eta, aux, grad_out, T: float, sigma_r: float, radii, N: int = 0,
-                  tile=None, trunc_tol: float = 0.0):
-    """grad_f = J^T grad_out for the forward that produced (out, eta, aux)."""
+                  tile=None, trunc_tol: float = 0.0, path: int = nat.PATH_AUTO,
+                  workspace: torch.Tensor | None = None):
+    """grad_f = J^T grad_out for the forward that produced (out, eta, aux):
+    the fused adjoint tiles or the streamed passes, as for the forward."""
     for x, n in ((f, "f"), (out, "out"), (eta, "eta"), (grad_out, "grad_out")):
         _check_img(x, n)
     H, W = f.shape
@@ -147,7 +159,8 @@ def trig_backward(f, out, eta, aux, grad_out, T: float, sigma_r: float, radii, N
         raise TypeError("aux must be the contiguous 2 x H x W float32 tensor of the forward")
     gf = torch.empty_like(f)
     spec = nat.SpatialSpec.of(radii)
-    opts = nat.make_opts(_stream_ptr(), N, None, tile, trunc_tol=trunc_tol)
+    ws, nws = _stream_workspace(f, H, W, T, sigma_r, radii, N, path, tile, workspace)
+    opts = nat.make_opts(_stream_ptr(), N, None, tile, None, _ptr(ws), nws, trunc_tol, path)
     nat.check(nat.lib().bf_trig_backward(_ptr(f), _ptr(out), _ptr(eta), _ptr(aux),
                                          _ptr(grad_out), H, W, float(T), float(sigma_r),
                                          ctypes.byref(spec), _ptr(gf), ctypes.byref(opts)),

@@ -1,4 +1,5 @@
-"""GPU parity of the fused adjoint kernel against the FP64 oracle.
+"""GPU parity of the adjoint (the fused tile kernel and the streamed passes)
+against the FP64 oracle.
 
 The oracle's gradient is the exact derivative of the direct window sum; it is
 itself pinned by finite differences in test_oracle_grad.  Tolerance (the
@@ -54,20 +55,21 @@ CASES = [
 ]
 
 
+@pytest.mark.parametrize("path", [1, 2], ids=["fused", "streamed"])
 @pytest.mark.parametrize("case", CASES, ids=[f"{c[0]}x{c[1]}-sr{c[2]}-r{c[4]}" for c in CASES])
-def test_backward_small_full_parity(case):
+def test_backward_small_full_parity(case, path):
     H, W, sr, N, radii = case
-    print(f"case {case}", flush=True)
+    print(f"case {case} path {path}", flush=True)
     f = synth.piecewise_smooth(H, W, seed=H + 7 * W, n_shapes=3)
     G = np.random.default_rng(H * W).normal(size=(H, W))
     Nuse = N or oracle.range_degree(255.0, sr)
     ref = oracle.grad(f, sr, Nuse, radii, G)
     ops = _ops()
     fg = _cuda(f)
-    out, eta, aux = ops.trig_forward(fg, 255.0, sr, radii, N=N, return_aux=True)
-    gf = ops.trig_backward(fg, out, eta, aux, _cuda(G), 255.0, sr, radii, N=N)
+    out, eta, aux = ops.trig_forward(fg, 255.0, sr, radii, N=N, return_aux=True, path=path)
+    gf = ops.trig_backward(fg, out, eta, aux, _cuda(G), 255.0, sr, radii, N=N, path=path)
     torch.cuda.synchronize()
-    _check(gf.cpu().numpy(), ref, f"grad {case}")
+    _check(gf.cpu().numpy(), ref, f"grad {case} path {path}")
 
 
 def test_autograd_matches_explicit_backward():
@@ -109,15 +111,17 @@ def _seam_border_idx(H, W, tile, rng, n_per):
     return idx
 
 
-def test_config2_adjoint_sampled():
+@pytest.mark.parametrize("path", [1, 2], ids=["fused", "streamed"])
+def test_config2_adjoint_sampled(path):
     """The adjoint of the benchmarked step at its own size: 2048 x 2048,
-    boxes 9, 9, 10 (R = 28), sigma_r = 20 (N = 66), so the kernel that runs is
-    the global-g variant on 64 x 64 tiles with the 120-sample line.  Upstream
-    gradient G: seeded N(0, 1) noise (independent of the GPU).  Compared with
-    the oracle's exact gradient on more than 256 pixels: random ones, the 64
-    pixels of smallest eta (where the expansion cancels most), the pixels of
-    largest local contrast, the seams of the 64 x 64 tile grid (rows and
-    columns 63/64, 127/128, ...), the image borders and the corners."""
+    boxes 9, 9, 10 (R = 28), sigma_r = 20 (N = 66): the fused kernel's
+    global-g variant on 64 x 64 tiles with the 120-sample line, and the
+    streamed passes.  Upstream gradient G: seeded N(0, 1) noise (independent
+    of the GPU).  Compared with the oracle's exact gradient on more than 256
+    pixels: random ones, the 64 pixels of smallest eta (where the expansion
+    cancels most), the pixels of largest local contrast, the seams of the
+    64 x 64 tile grid (rows and columns 63/64, 127/128, ...), the image
+    borders and the corners."""
     f = synth.config_image(2)
     H, W = f.shape
     radii, sr = [9, 9, 10], 20.0
@@ -126,8 +130,8 @@ def test_config2_adjoint_sampled():
     G = np.random.default_rng(2048).normal(size=(H, W))
     ops = _ops()
     fg = _cuda(f)
-    out, eta, aux = ops.trig_forward(fg, 255.0, sr, radii, return_aux=True)
-    gf = ops.trig_backward(fg, out, eta, aux, _cuda(G), 255.0, sr, radii)
+    out, eta, aux = ops.trig_forward(fg, 255.0, sr, radii, return_aux=True, path=path)
+    gf = ops.trig_backward(fg, out, eta, aux, _cuda(G), 255.0, sr, radii, path=path)
     torch.cuda.synchronize()
     g = gf.cpu().numpy().reshape(-1)
     e = eta.cpu().numpy().reshape(-1)
@@ -141,7 +145,7 @@ def test_config2_adjoint_sampled():
     idx = np.array(sorted(idx), dtype=np.int64)
     assert idx.size >= 256
     ref = oracle.grad_at(f, sr, N, radii, G, idx)
-    _check(g[idx], ref, f"config2 adjoint ({idx.size} px)")
+    _check(g[idx], ref, f"config2 adjoint path {path} ({idx.size} px)")
 
 
 def test_config4_ssd_gradient_vs_fd_and_oracle():
@@ -215,8 +219,8 @@ def test_backward_global_g_full_parity(case):
     ref = oracle.grad(f, sr, Nuse, radii, G)
     ops = _ops()
     fg = _cuda(f)
-    out, eta, aux = ops.trig_forward(fg, 255.0, sr, radii, N=N, return_aux=True)
-    gf = ops.trig_backward(fg, out, eta, aux, _cuda(G), 255.0, sr, radii, N=N)
+    out, eta, aux = ops.trig_forward(fg, 255.0, sr, radii, N=N, return_aux=True, path=1)
+    gf = ops.trig_backward(fg, out, eta, aux, _cuda(G), 255.0, sr, radii, N=N, path=1)
     torch.cuda.synchronize()
     _check(gf.cpu().numpy(), ref, f"grad gg {case}")
 
@@ -238,8 +242,8 @@ def test_backward_both_g_paths_agree_and_match_oracle():
     assert fa.data_ptr() % 16 == 0 and fm.data_ptr() % 16 != 0
     grads = []
     for fx in (fa, fm):
-        out, eta, aux = ops.trig_forward(fx, 255.0, sr, radii, return_aux=True)
-        grads.append(ops.trig_backward(fx, out, eta, aux, _cuda(G), 255.0, sr, radii))
+        out, eta, aux = ops.trig_forward(fx, 255.0, sr, radii, return_aux=True, path=1)
+        grads.append(ops.trig_backward(fx, out, eta, aux, _cuda(G), 255.0, sr, radii, path=1))
     torch.cuda.synchronize()
     g0, g1 = grads[0].cpu().numpy(), grads[1].cpu().numpy()
     scale = np.abs(g0).max()

@@ -57,8 +57,10 @@ def test_batch_matches_single_image_kernels():
     from paper_1105_4204_amd import _native as nat
     for i, s in enumerate(SPECS):
         radii = s.get("radii") or nat.spatial_gaussian(s["sigma_s"], 3)
-        o1, e1, x1 = ops.trig_forward(f[i], 255.0, s["sigma_r"], radii, return_aux=True)
-        g1 = ops.trig_backward(f[i], o1, e1, x1, 2.0 * (o1 - t[i]), 255.0, s["sigma_r"], radii)
+        # the batch runs the fused tiles: compare with the single-image fused kernels
+        o1, e1, x1 = ops.trig_forward(f[i], 255.0, s["sigma_r"], radii, return_aux=True, path=1)
+        g1 = ops.trig_backward(f[i], o1, e1, x1, 2.0 * (o1 - t[i]), 255.0, s["sigma_r"], radii,
+                               path=1)
         torch.cuda.synchronize()
         print(f"image {i} {s}: out eq={torch.equal(o1, out[i])} grad eq={torch.equal(g1, gf[i])}",
               flush=True)

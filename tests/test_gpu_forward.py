@@ -76,14 +76,15 @@ def _img(kind, H, W, seed):
     return synth.piecewise_smooth(H, W, seed, n_shapes=4)
 
 
+@pytest.mark.parametrize("path", [1, 2], ids=["fused", "streamed"])
 @pytest.mark.parametrize("case", SMALL, ids=[f"{c[0]}x{c[1]}-sr{c[2]}-N{c[3]}-r{c[4]}" for c in SMALL])
-def test_forward_small_full_parity(case):
+def test_forward_small_full_parity(case, path):
     H, W, sr, N, radii, kind = case
-    print(f"case {case}", flush=True)
+    print(f"case {case} path {path}", flush=True)
     f = _img(kind, H, W, seed=H * 1000 + W)
     Nuse = N or oracle.range_degree(255.0, sr)
     ref, eta_ref = oracle.forward(f, sr, Nuse, radii, return_eta=True)
-    out, eta = _ops().trig_forward(_cuda(f), 255.0, sr, radii, N=N, return_eta=True)
+    out, eta = _ops().trig_forward(_cuda(f), 255.0, sr, radii, N=N, return_eta=True, path=path)
     torch.cuda.synchronize()
     _check(out.cpu().numpy(), ref, f"out {case}")
     e = eta.cpu().numpy().astype(np.float64)
@@ -162,8 +163,9 @@ def _sample_idx(H, W, R, eta, n_rand, seed):
     return np.array(sorted(idx), dtype=np.int64)
 
 
+@pytest.mark.parametrize("path", [1, 2], ids=["fused", "streamed"])
 @pytest.mark.parametrize("cfg", [2, 4])
-def test_full_size_sampled_parity(cfg):
+def test_full_size_sampled_parity(cfg, path):
     if cfg == 2:
         f = synth.config_image(2)
         sr, radii = 20.0, [9, 9, 10]
@@ -171,13 +173,13 @@ def test_full_size_sampled_parity(cfg):
         f = synth.diff_batch(1)[0][0]
         sr, radii = 25.0, [5, 5, 6]
     N = oracle.range_degree(255.0, sr)
-    out, eta = _ops().trig_forward(_cuda(f), 255.0, sr, radii, return_eta=True)
+    out, eta = _ops().trig_forward(_cuda(f), 255.0, sr, radii, return_eta=True, path=path)
     torch.cuda.synchronize()
     out, eta = out.cpu().numpy(), eta.cpu().numpy()
     H, W = f.shape
     idx = _sample_idx(H, W, sum(radii), eta, 65536, seed=cfg)
     ref, eta_ref = oracle.forward_at(f, sr, N, radii, idx, return_eta=True)
-    _check(out.reshape(-1)[idx], ref, f"config{cfg} sampled ({idx.size} px)")
+    _check(out.reshape(-1)[idx], ref, f"config{cfg} path {path} sampled ({idx.size} px)")
     rel = np.abs(eta.reshape(-1)[idx] - eta_ref) / eta_ref
     assert rel.max() < 1e-3
 
@@ -192,11 +194,11 @@ def test_direct_kernel_small_parity():
         _check(out.cpu().numpy(), ref, f"direct sr={sr} r={radii}")
 
 
-def test_direct_vs_fused_config2():
+def test_direct_vs_o1_config2():
     f = _cuda(synth.config_image(2))
     a = _ops().trig_forward(f, 255.0, 20.0, [9, 9, 10])
     b = _ops().direct_forward(f, 255.0, 20.0, [9, 9, 10])
     torch.cuda.synchronize()
     d = torch.abs(a - b)
-    print(f"fused vs direct: max {d.max().item():.3e} mean {d.mean().item():.3e}", flush=True)
+    print(f"O(1) vs direct: max {d.max().item():.3e} mean {d.mean().item():.3e}", flush=True)
     assert d.max().item() < 2e-2

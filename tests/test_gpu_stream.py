@@ -1,10 +1,13 @@
-"""GPU parity of the streamed forward (whole-line column and row passes whose
-cost does not depend on the kernel width) against the FP64 oracle: small
-images pixel by pixel, across box counts, radii up to 150 per box, odd and
-even degrees, several pair chunks and column segments; and the 4096x4096,
-sigma_s = 30 (boxes 29, 29, 30), sigma_r = 10 (N = 264) workload and a
-2048x2048 image at sigma_s = 100 on sampled pixels.  Tolerance as for the
-fused forward: |gpu - oracle| <= 1e-2 + 1e-4 |oracle| per pixel."""
+"""GPU parity of the streamed passes (whole-line column and row passes whose
+cost does not depend on the kernel width) against the FP64 oracle.
+
+Forward: small images pixel by pixel, across box counts, radii up to 150 per
+box, odd and even degrees, several pair chunks and column segments; the
+4096x4096, sigma_s = 30 (boxes 29, 29, 30), sigma_r = 10 (N = 264) workload
+and a 2048x2048 image at sigma_s = 100 on sampled pixels.  Tolerance as for
+the fused forward: |gpu - oracle| <= 1e-2 + 1e-4 |oracle| per pixel.
+Adjoint: kernels the fused tiles cannot hold, every pixel against the
+oracle's exact gradient, tolerance 1e-3 max|g_ref| + 1e-3 |g_ref|."""
 import numpy as np
 import pytest
 import torch
@@ -138,12 +141,77 @@ def test_stream_deterministic_and_library_workspace():
     assert torch.equal(a, b)
 
 
-def test_stream_rejects_adjoint_sums():
+def test_stream_aux_and_eta_match_fused():
+    """The adjoint's sums P, Q and eta from the streamed passes equal the fused
+    kernel's to float rounding (both evaluate the same expansion)."""
+    H, W, sr, radii = 150, 140, 20.0, [9, 9, 10]
+    f = _cuda(synth.piecewise_smooth(H, W, seed=31, n_shapes=4))
+    a = _ops().trig_forward(f, 255.0, sr, radii, return_aux=True, path=1)
+    b = _ops().trig_forward(f, 255.0, sr, radii, return_aux=True, path=STREAMED)
+    torch.cuda.synchronize()
+    for k, name in ((0, "out"), (1, "eta"), (2, "aux")):
+        x, y = a[k].cpu().numpy().astype(np.float64), b[k].cpu().numpy().astype(np.float64)
+        rel = np.abs(x - y).max() / np.abs(x).max()
+        print(f"{name}: max rel {rel:.3e}", flush=True)
+        assert rel < 2e-5, name
+
+
+def _grad_check(g, ref, what):
+    g = np.asarray(g, dtype=np.float64)
+    scale = np.abs(ref).max()
+    err = np.abs(g - ref)
+    tol = 1e-3 * scale + 1e-3 * np.abs(ref)
+    bad = int((err > tol).sum())
+    print(f"{what}: max_abs={err.max():.3e} scale={scale:.3e} bad={bad}/{err.size}", flush=True)
+    assert np.all(np.isfinite(g)), what
+    assert bad == 0, what
+
+
+ADJ_CASES = [
+    (40, 46, 25.0, 0, [20, 22, 24]),     # R = 66, odd N = 43
+    (34, 30, 20.0, 0, [50, 50, 51]),     # R = 151, kernel wider than the image
+    (1, 60, 30.0, 0, [30, 30, 10]),      # single row
+    (36, 28, 12.0, 0, [31, 20, 20]),     # N = 184
+    (30, 33, 30.0, 0, [3, 5, 7, 9]),     # four boxes
+]
+
+
+@pytest.mark.parametrize("case", ADJ_CASES, ids=[f"{c[0]}x{c[1]}-r{c[4]}" for c in ADJ_CASES])
+def test_stream_adjoint_wide_full_parity(case):
+    """The streamed adjoint on kernels the fused tiles cannot hold (R > 63 or
+    a radius above 31), against the oracle's exact gradient at every pixel,
+    with the adjoint's sums from the streamed forward (the library's choice)."""
+    H, W, sr, N, radii = case
+    print(f"case {case}", flush=True)
+    f = synth.piecewise_smooth(H, W, seed=H + 5 * W, n_shapes=3)
+    G = np.random.default_rng(H * W + 1).normal(size=(H, W))
+    Nuse = N or oracle.range_degree(255.0, sr)
+    ref = oracle.grad(f, sr, Nuse, radii, G)
+    fg = _cuda(f)
+    out, eta, aux = _ops().trig_forward(fg, 255.0, sr, radii, N=N, return_aux=True)
+    gf = _ops().trig_backward(fg, out, eta, aux, _cuda(G), 255.0, sr, radii, N=N)
+    torch.cuda.synchronize()
+    _grad_check(gf.cpu().numpy(), ref, f"streamed adjoint {case}")
+
+
+def test_stream_adjoint_chunks():
+    """The streamed adjoint and the forward's sums with one-pair chunks (the
+    partial sums carried between chunks) against the recommended workspace."""
     from paper_1105_4204_amd import _native as nat
-    f = _cuda(synth.rectangles(64, 64, seed=1))
-    with pytest.raises(nat.BFError) as e:
-        _ops().trig_forward(f, 255.0, 20.0, [29, 29, 30], return_aux=True)
-    assert e.value.code == 6
+    H, W, sr, radii = 61, 70, 15.0, [12, 12, 13]
+    f = _cuda(synth.piecewise_smooth(H, W, seed=19, n_shapes=3))
+    G = torch.from_numpy(np.random.default_rng(20).normal(size=(H, W)).astype(np.float32)).cuda()
+    ws = torch.empty(nat.stream_workspace_bytes(H, W, 1), dtype=torch.uint8, device="cuda")
+    o1, e1, x1 = _ops().trig_forward(f, 255.0, sr, radii, return_aux=True, path=STREAMED)
+    o2, e2, x2 = _ops().trig_forward(f, 255.0, sr, radii, return_aux=True, path=STREAMED,
+                                     workspace=ws)
+    g1 = _ops().trig_backward(f, o1, e1, x1, G, 255.0, sr, radii, path=STREAMED)
+    g2 = _ops().trig_backward(f, o1, e1, x1, G, 255.0, sr, radii, path=STREAMED, workspace=ws)
+    torch.cuda.synchronize()
+    for a, b, name in ((x1, x2, "aux"), (g1, g2, "grad")):
+        rel = (a - b).abs().max().item() / a.abs().max().item()
+        print(f"{name}: chunked vs one chunk, max rel {rel:.3e}", flush=True)
+        assert rel < 1e-5, name
 
 
 def _sampled(f_np, sr, N, radii, out, eta, what, seed, nrand=65536):

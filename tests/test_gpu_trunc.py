@@ -109,8 +109,13 @@ def test_truncated_adjoint_and_batch():
     plan.launch()
     plan.check()
     torch.cuda.synchronize()
-    assert torch.equal(bo[0], o2)
-    assert torch.equal(bg[0], g2)
+    # the batch runs the fused tiles: compare with the single-image fused kernels
+    o5, e5, x5 = ops.trig_forward(fd, 255.0, sr, radii, return_aux=True, trunc_tol=tol, path=1)
+    g5 = ops.trig_backward(fd, o5, e5, x5, 2.0 * (o5 - _cuda(t_np)), 255.0, sr, radii,
+                           trunc_tol=tol, path=1)
+    torch.cuda.synchronize()
+    assert torch.equal(bo[0], o5)
+    assert torch.equal(bg[0], g5)
     o4 = ops.trig_forward(fs[1], 255.0, 30.0, [2, 2, 3], path=1)
     torch.cuda.synchronize()
     assert torch.equal(bo[1], o4)

@@ -158,19 +158,29 @@ def test_phase_polynomial_constants_and_accuracy():
 
 
 def test_workspace_query_and_streamed_validation():
-    """Kernels the fused tiles hold at full size need no workspace; wider
-    ones (a radius above 31, R > 63) or ones whose tiles the halo shrinks go
-    through the streamed passes, whose recommended workspace is 16 pairs'
-    column-filtered planes (pitch W rounded up to 64) plus den and num.  The
+    """The streamed passes run wherever their line holds W + 2R (<= 5184);
+    their recommended workspace is 16 pairs' column-filtered planes (pitch W
+    rounded up to 64) plus the partial sums and the adjoint's weights, and
+    for a given degree every pair up to 4 GiB.  Wider images run the fused
+    tiles, which need no workspace.  The
     documented limits, through the C ABI: radii up to BF_MAX_RADIUS = 256
     (BF_ERANGE above), W + 2R <= 5184 and a composite mass below 2^31
-    (BF_EUNSUPPORTED otherwise); the adjoint's sums only from the fused
-    kernel; a workspace below one pair's, or not 256-byte aligned, and an
-    unknown path are BF_EINVAL.  None of these calls reaches the GPU."""
+    (BF_EUNSUPPORTED otherwise, also for the fused kernel forced on a kernel
+    it cannot hold); a workspace below one pair's, or not 256-byte aligned,
+    and an unknown path are BF_EINVAL.  None of these calls reaches the GPU."""
     assert nat.BF_MAX_RADIUS == 256
-    assert nat.workspace_bytes(2048, 2048, [9, 9, 10]) == 0
+    # the streamed passes run wherever their line holds W + 2R; beyond, the
+    # fused tiles (no workspace) if they hold the kernel
+    assert nat.workspace_bytes(2048, 2048, [9, 9, 10]) == nat.stream_workspace_bytes(2048, 2048, 16)
     assert nat.workspace_bytes(2048, 2048, [29, 29, 30]) == nat.stream_workspace_bytes(2048, 2048, 16)
-    assert nat.stream_workspace_bytes(64, 80, 16) == 16 * 16 * 64 * 128 + 8 * 64 * 80
+    assert nat.workspace_bytes(64, 8192, [9, 9, 10]) == 0
+    assert nat.stream_workspace_bytes(64, 80, 16) == 16 * 16 * 64 * 128 + 24 * 64 * 80
+    # for a given degree: every pair in one chunk (34 at N = 66), up to 4 GiB of planes
+    assert nat.workspace_bytes_ex(2048, 2048, 255.0, 20.0, 0, [29, 29, 30]) == \
+        nat.stream_workspace_bytes(2048, 2048, 34)
+    assert nat.workspace_bytes_ex(4096, 4096, 255.0, 10.0, 0, [29, 29, 30]) == \
+        nat.stream_workspace_bytes(4096, 4096, 16)
+    assert nat.workspace_bytes_ex(64, 8192, 255.0, 20.0, 0, [9, 9, 10]) == 0
     assert nat.workspace_bytes(10, 10, [100, 100, 100]) == nat.stream_workspace_bytes(10, 10, 16)
     assert nat.workspace_bytes(64, 4584, [100, 100, 100]) > 0        # W + 2R = 5184
     with pytest.raises(nat.BFError) as e:
@@ -184,9 +194,9 @@ def test_workspace_query_and_streamed_validation():
     assert e.value.code == 6
     L = nat.lib()
     s = nat.SpatialSpec.of([29, 29, 30])
-    o2 = nat.make_opts(None, 0, None, None, FAKE3)
+    o2 = nat.make_opts(None, 0, None, None, FAKE3, path=1)
     assert L.bf_trig_forward_ex(FAKE, 8, 8, 255.0, 10.0, ctypes.byref(s), FAKE2,
-                                ctypes.byref(o2)) == 6         # aux_out with R = 88
+                                ctypes.byref(o2)) == 6         # fused forced at R = 88
     one = nat.stream_workspace_bytes(8, 8, 1)
     o3 = nat.make_opts(None, 0, None, None, None, ctypes.c_void_p(0x40000000), one - 4)
     assert L.bf_trig_forward_ex(FAKE, 8, 8, 255.0, 10.0, ctypes.byref(s), FAKE2,
