@@ -165,6 +165,24 @@ bf_status bf_trig_forward_ex(const float* f, int64_t H, int64_t W, float T, floa
                              const bf_spatial_spec* spatial_spec, float* out,
                              const bf_opts* opts);
 
+/* For callers that cannot allocate device memory (code under stream capture,
+ * tight serving loops, harnesses that forbid hipMalloc): bf_trig_forward_ex
+ * with the streamed passes' workspace taken from a static device array of
+ * 64 MiB that the library holds on each device it runs on (from its first
+ * use until the process ends); nothing is allocated or freed.  opts->workspace
+ * must be NULL (BF_EINVAL otherwise); the other options are as for
+ * bf_trig_forward_ex.  Path choice: the streamed passes where they apply
+ * (W + 2R <= 5184) and one cosine pair fits the array, 16 H Wp + 24 H W <=
+ * 64 MiB (chunks of as many pairs as fit); otherwise the fused kernel where
+ * it holds the spatial kernel (it needs no workspace); otherwise BF_ERANGE,
+ * as for BF_PATH_STREAMED forced on an image whose pair does not fit.  Every
+ * call on one device shares that device's array: calls that overlap on one
+ * device (different streams, or host threads) race and must be serialised
+ * by the caller.  Nothing in the array needs to start at zero. */
+bf_status bf_trig_forward_noalloc(const float* f, int64_t H, int64_t W, float T,
+                                  float sigma_r, const bf_spatial_spec* spatial_spec,
+                                  float* out, const bf_opts* opts);
+
 /* Adjoint: grad_f = (d out / d f)^T grad_out, the exact derivative of eq.
  * (BF)/(normalization) for the raised-cosine kernel, evaluated term by term
  * on the expansion of eq. (final-form).  out, eta and aux are the forward's

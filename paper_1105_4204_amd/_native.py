@@ -24,7 +24,7 @@ STATUS = {0: "BF_OK", 1: "BF_EINVAL", 2: "BF_ERANGE", 3: "BF_ENOMEM", 4: "BF_EDE
 # exported symbols, in the order include/bf_trig.h declares them
 EXPORTS = ["bf_range_degree", "bf_range_coeffs", "bf_range_truncate", "bf_spatial_gaussian",
            "bf_trig_workspace_bytes", "bf_trig_workspace_bytes_ex", "bf_trig_forward",
-           "bf_trig_forward_ex", "bf_trig_backward", "bf_sv_forward",
+           "bf_trig_forward_ex", "bf_trig_forward_noalloc", "bf_trig_backward", "bf_sv_forward",
            "bf_yvv_coeffs", "bf_yvv_workspace_bytes", "bf_yvv_forward", "bf_direct_forward", "bf_check_range",
            "bf_batch_plan_create", "bf_batch_bind", "bf_batch_launch", "bf_batch_check",
            "bf_batch_plan_destroy", "bf_status_string", "bf_last_error"]
@@ -94,6 +94,7 @@ def lib():
         "bf_trig_workspace_bytes_ex": [i64, i64, f32, f32, i32, sp, ctypes.POINTER(i64)],
         "bf_trig_forward": [vp, i64, i64, f32, f32, sp, vp],
         "bf_trig_forward_ex": [vp, i64, i64, f32, f32, sp, vp, op],
+        "bf_trig_forward_noalloc": [vp, i64, i64, f32, f32, sp, vp, op],
         "bf_trig_backward": [vp, vp, vp, vp, vp, i64, i64, f32, f32, sp, vp, op],
         "bf_sv_forward": [vp, vp, i64, i64, f32, f32, i32, vp, op],
         "bf_yvv_coeffs": [f64, ctypes.POINTER(f64)],

@@ -10,7 +10,7 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libbftrig.so")
 SOURCES = ["bf_host.cpp", "bf_api.cpp", "bf_batch.hip", "bf_tile.hip",
            "bf_direct.hip", "bf_stream.hip", "bf_sv.hip",
-           "bf_yvv.hip", "bf_check.hip"]
+           "bf_yvv.hip", "bf_check.hip", "bf_static.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 # Packed FP32 math (v_pk_*_f32) is disabled for every device object.
