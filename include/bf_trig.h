@@ -285,6 +285,18 @@ typedef struct {
 typedef struct bf_batch_plan bf_batch_plan;
 
 bf_status bf_batch_plan_create(const bf_image_desc* descs, int32_t n, bf_batch_plan** plan);
+/* path: BF_PATH_AUTO (bf_batch_plan_create) runs the batch through the
+ * streamed passes when every image is within their limits (W + 2R <= 5184,
+ * at most 256 cosine pairs), else through the persistent fused-tile kernel;
+ * BF_PATH_FUSED and BF_PATH_STREAMED force one (BF_EUNSUPPORTED if an image
+ * is outside the streamed passes' limits).  The streamed batch enqueues a
+ * short sequence of kernels instead of one persistent kernel: the column
+ * pass and then the row pass over all images (one launch per box count and
+ * per line length), the loss and the adjoint's weights, then the adjoint's
+ * two passes; it owns the column-filtered planes of every pair of every
+ * image (16 bytes per pixel and pair) and ignores the tile fields. */
+bf_status bf_batch_plan_create_ex(const bf_image_desc* descs, int32_t n, int32_t path,
+                                  bf_batch_plan** plan);
 bf_status bf_batch_bind(bf_batch_plan* plan, const float* const* f, const float* const* target,
                         float* const* out, float* const* eta, float* const* grad_f,
                         float* loss /* device, n floats, or NULL */);

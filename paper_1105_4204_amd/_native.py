@@ -26,7 +26,7 @@ EXPORTS = ["bf_range_degree", "bf_range_coeffs", "bf_range_truncate", "bf_spatia
            "bf_trig_workspace_bytes", "bf_trig_workspace_bytes_ex", "bf_trig_forward",
            "bf_trig_forward_ex", "bf_trig_forward_noalloc", "bf_trig_backward", "bf_sv_forward",
            "bf_yvv_coeffs", "bf_yvv_workspace_bytes", "bf_yvv_forward", "bf_direct_forward", "bf_check_range",
-           "bf_batch_plan_create", "bf_batch_bind", "bf_batch_launch", "bf_batch_check",
+           "bf_batch_plan_create", "bf_batch_plan_create_ex", "bf_batch_bind", "bf_batch_launch", "bf_batch_check",
            "bf_batch_plan_destroy", "bf_status_string", "bf_last_error"]
 
 
@@ -103,6 +103,7 @@ def lib():
         "bf_direct_forward": [vp, i64, i64, f32, f32, sp, vp, op],
         "bf_check_range": [vp, i64, i64, f32, vp, vp],
         "bf_batch_plan_create": [ctypes.POINTER(ImageDesc), i32, ctypes.POINTER(vp)],
+        "bf_batch_plan_create_ex": [ctypes.POINTER(ImageDesc), i32, i32, ctypes.POINTER(vp)],
         "bf_batch_bind": [vp, ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(vp),
                           ctypes.POINTER(vp), ctypes.POINTER(vp), vp],
         "bf_batch_launch": [vp, vp],

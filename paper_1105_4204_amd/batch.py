@@ -35,7 +35,10 @@ def _spec_desc(s) -> nat.ImageDesc:
 class BatchPlan:
     """A plan for one fixed list of images; see include/bf_trig.h."""
 
-    def __init__(self, specs, tuner=None):
+    def __init__(self, specs, tuner=None, path=nat.PATH_AUTO):
+        """path: PATH_AUTO (the streamed passes when every image is within
+        their limits, else the persistent fused-tile kernel), PATH_FUSED or
+        PATH_STREAMED.  The tuner's tiles apply to the fused kernel only."""
         specs = [dict(s) for s in specs]
         if tuner is not None:
             for s in specs:
@@ -45,8 +48,9 @@ class BatchPlan:
         arr = (nat.ImageDesc * len(specs))(*[_spec_desc(s) for s in specs])
         self._descs = arr
         h = ctypes.c_void_p()
-        nat.check(nat.lib().bf_batch_plan_create(arr, len(specs), ctypes.byref(h)),
-                  "bf_batch_plan_create")
+        nat.check(nat.lib().bf_batch_plan_create_ex(arr, len(specs), int(path), ctypes.byref(h)),
+                  "bf_batch_plan_create_ex")
+        self.path = path
         self._h = h
         self._bound = None
 
@@ -123,18 +127,18 @@ def capture(plan: BatchPlan, warmup: int = 1) -> torch.cuda.CUDAGraph:
 
 
 def trig_forward_channels(img: torch.Tensor, T: float, sigma_r: float, radii, N: int = 0,
-                          trunc_tol: float = 0.0) -> torch.Tensor:
+                          trunc_tol: float = 0.0, path: int = nat.PATH_AUTO) -> torch.Tensor:
     """Channel-wise filter of a C x H x W image (e.g. RGB, each channel filtered
     on its own as in the paper's colour experiments), run as the C items of one
-    batched persistent launch.  Returns a C x H x W tensor; synchronises the
-    current stream before it returns (the plan is released)."""
+    batched launch (`path` as for BatchPlan).  Returns a C x H x W tensor;
+    synchronises the current stream before it returns (the plan is released)."""
     if img.dim() != 3 or not img.is_cuda or img.dtype != torch.float32:
         raise TypeError("img must be a C x H x W float32 CUDA tensor")
     img = img.contiguous()
     C, H, W = img.shape
     spec = dict(H=H, W=W, T=float(T), sigma_r=float(sigma_r), N=int(N),
                 radii=[int(r) for r in radii], trunc_tol=float(trunc_tol))
-    plan = BatchPlan([spec] * C)
+    plan = BatchPlan([spec] * C, path=path)
     out = torch.empty_like(img)
     plan.bind([img[c] for c in range(C)], out=[out[c] for c in range(C)])
     plan.launch()

@@ -117,10 +117,12 @@ struct bf_batch_plan {
     unsigned* counters_d = nullptr;
     float* aux_d = nullptr;        // forward -> adjoint sums P, Q of every image
     float* loss = nullptr;
+    StreamBatch* sb = nullptr;     // the streamed passes instead of the persistent kernel
 };
 
 static void free_plan(bf_batch_plan* p) {
     if (!p) return;
+    stream_batch_destroy(p->sb);
     (void)hipFree(p->jobs_d);
     (void)hipFree(p->items_d);
     (void)hipFree(p->fwd_tiles_d);
@@ -150,6 +152,11 @@ static bool capturing() {
 extern "C" {
 
 bf_status bf_batch_plan_create(const bf_image_desc* descs, int32_t n, bf_batch_plan** plan) {
+    return bf_batch_plan_create_ex(descs, n, BF_PATH_AUTO, plan);
+}
+
+bf_status bf_batch_plan_create_ex(const bf_image_desc* descs, int32_t n, int32_t path,
+                                  bf_batch_plan** plan) {
     if (!plan) {
         set_error("plan is NULL");
         return BF_EINVAL;
@@ -158,6 +165,51 @@ bf_status bf_batch_plan_create(const bf_image_desc* descs, int32_t n, bf_batch_p
     if (!descs || n <= 0) {
         set_error("need n > 0 image descriptors");
         return BF_EINVAL;
+    }
+    if (path != BF_PATH_AUTO && path != BF_PATH_FUSED && path != BF_PATH_STREAMED) {
+        set_error("path=%d is not one of BF_PATH_AUTO, BF_PATH_FUSED, BF_PATH_STREAMED", path);
+        return BF_EINVAL;
+    }
+    if (path != BF_PATH_FUSED) {
+        // the streamed passes: every image within their limits (AUTO), or
+        // forced; tile overrides are ignored on this path
+        std::vector<RangeParams> rp(n);
+        std::vector<SpatialParams> sp(n);
+        std::vector<int64_t> H(n), W(n);
+        bool all = true;
+        for (int i = 0; i < n; ++i) {
+            const bf_image_desc& d = descs[i];
+            bf_status st = BF_OK;
+            if (d.H <= 0 || d.W <= 0 || d.H > (1 << 20) || d.W > (1 << 20)) {
+                set_error("image %d: bad size %lld x %lld", i, (long long)d.H, (long long)d.W);
+                st = BF_EINVAL;
+            } else if ((st = make_spatial(&d.spatial, &sp[i])) == BF_OK &&
+                       (st = make_range((double)d.T, (double)d.sigma_r, d.N, &rp[i])) == BF_OK &&
+                       d.trunc_tol != 0.0f) {
+                st = truncate_pairs(&rp[i], sp[i], (double)d.T, (double)d.trunc_tol, nullptr);
+            }
+            if (st != BF_OK) return st;
+            H[i] = d.H;
+            W[i] = d.W;
+            all = all && stream_batch_supported(d.H, d.W, sp[i], rp[i].npairs);
+        }
+        if (all) {
+            bf_batch_plan* p = new bf_batch_plan();
+            p->n = n;
+            p->desc.assign(descs, descs + n);
+            const bf_status st = stream_batch_create(n, H.data(), W.data(), rp.data(), sp.data(),
+                                                     &p->sb);
+            if (st != BF_OK) {
+                free_plan(p);
+                return st;
+            }
+            *plan = p;
+            return BF_OK;
+        }
+        if (path == BF_PATH_STREAMED) {
+            set_error("an image of the batch is outside the streamed passes' limits");
+            return BF_EUNSUPPORTED;
+        }
     }
     bf_batch_plan* p = new bf_batch_plan();
     p->n = n;
@@ -249,6 +301,21 @@ bf_status bf_batch_bind(bf_batch_plan* p, const float* const* f, const float* co
         return BF_EINVAL;
     }
     const int n = p->n;
+    if (p->sb) {
+        for (int i = 0; i < n; ++i) {
+            const bf_image_desc& d = p->desc[i];
+            const int64_t bytes = d.H * d.W * (int64_t)sizeof(float);
+            if (!f[i] || !out[i] || (bwd && (!grad_f[i] || !target[i] || !eta[i])) ||
+                overlaps(f[i], out[i], bytes) || (eta && overlaps(out[i], eta[i], bytes)) ||
+                (bwd && (overlaps(grad_f[i], f[i], bytes) || overlaps(grad_f[i], out[i], bytes)))) {
+                set_error("image %d: missing or overlapping buffers", i);
+                return BF_EINVAL;
+            }
+        }
+        const bf_status st = stream_batch_bind(p->sb, f, target, out, eta, grad_f, loss);
+        p->bound = st == BF_OK;
+        return st;
+    }
     std::vector<TileArgs> jobs(2 * (size_t)n);
     struct Cost {
         double c;
@@ -324,6 +391,7 @@ bf_status bf_batch_launch(bf_batch_plan* p, void* stream) {
         return BF_EINVAL;
     }
     hipStream_t s = (hipStream_t)stream;
+    if (p->sb) return stream_batch_launch(p->sb, s);
     const int nc = kBatchCounters0 + p->n;
     hipLaunchKernelGGL(bf_batch_reset, dim3((nc + 255) / 256), dim3(256), 0, s, p->counters_d, nc);
     BatchDev d;
@@ -354,6 +422,13 @@ bf_status bf_batch_check(bf_batch_plan* p) {
         return BF_EINVAL;
     }
     unsigned flags[2] = {0, 0};
+    if (p->sb) {   // no bounded waits on this path
+        if (hipDeviceSynchronize() != hipSuccess) {
+            set_error("device error: %s", hipGetErrorString(hipGetLastError()));
+            return BF_EDEVICE;
+        }
+        return BF_OK;
+    }
     if (hipDeviceSynchronize() != hipSuccess ||
         hipMemcpy(flags, p->counters_d, sizeof(flags), hipMemcpyDeviceToHost) != hipSuccess) {
         set_error("device error: %s", hipGetErrorString(hipGetLastError()));

@@ -99,6 +99,17 @@ bool prefer_stream(int64_t H, int64_t W, const SpatialParams& sp, bf_status fuse
 bf_status launch_stream(int mode, const StreamIO& io, int64_t H, int64_t W,
                         const RangeParams& rp, const SpatialParams& sp, void* workspace,
                         size_t ws_bytes, hipStream_t stream);
+// A batch through the streamed passes: every pass over every image in one
+// launch per box count or line length (plan-owned planes for all pairs of
+// all images, the adjoint's sums and weights, task tables).
+struct StreamBatch;
+bool stream_batch_supported(int64_t H, int64_t W, const SpatialParams& sp, int npairs);
+bf_status stream_batch_create(int n, const int64_t* H, const int64_t* W, const RangeParams* rp,
+                              const SpatialParams* sp, StreamBatch** out);
+bf_status stream_batch_bind(StreamBatch* b, const float* const* f, const float* const* target,
+                            float* const* out, float* const* eta, float* const* gf, float* loss);
+bf_status stream_batch_launch(const StreamBatch* b, hipStream_t s);
+void stream_batch_destroy(StreamBatch* b);
 // Pairs per chunk of the workspace bf_trig_workspace_bytes recommends; the
 // library's own workspace and bf_trig_workspace_bytes_ex hold every pair up
 // to a budget of 4 GiB of planes (but at least this many pairs).

@@ -117,17 +117,15 @@ __device__ __forceinline__ void channels(float zr, float zi, float g, float av, 
     }
 }
 
-template <int NB, int G, int MODE>
-__global__ void __launch_bounds__(kSmThreads) bf_strm_v(const StrmVArgs a) {
-    constexpr int NT = 1 << NB;
-    constexpr bool BWD = MODE == kSmBwd;
-    extern __shared__ double wtab[];   // [k][s]: integrator weights of the segment start
-    const int lane = threadIdx.x & 63;
-    const int H = a.H;
-    // I_s[t] = sum_k w_s[k] x[t - k] with sum_k w_s[k] z^-k = D(z) / (1 - z^-1)^s,
-    // D the taps' polynomial: w_s[k] = sum_j c_j C(k - o_j + s - 1, s - 1) over
-    // o_j <= k (integers, exact in FP64); zero past k = 2R + nb - s.
-    for (int k = threadIdx.x; k < a.kinit; k += kSmThreads) {
+// The integrator weights of a segment start, wtab[k][s] for k < kinit:
+// I_s[t] = sum_k w_s[k] x[t - k] with sum_k w_s[k] z^-k = D(z) / (1 - z^-1)^s,
+// D the taps' polynomial: w_s[k] = sum_j c_j C(k - o_j + s - 1, s - 1) over
+// o_j <= k (integers, exact in FP64); zero past k = 2R + nb - s.  Threads
+// tid, tid + nthr, ... fill the table.
+template <int NB>
+__device__ __forceinline__ void strm_weights(const StrmVArgs& a, double* wtab, int tid,
+                                             int nthr) {
+    for (int k = tid; k < a.kinit; k += nthr) {
         double w[NB];
 #pragma unroll
         for (int s = 0; s < NB; ++s) w[s] = 0.0;
@@ -146,13 +144,21 @@ __global__ void __launch_bounds__(kSmThreads) bf_strm_v(const StrmVArgs a) {
 #pragma unroll
         for (int s = 0; s < NB; ++s) wtab[k * NB + s] = w[s];
     }
-    __syncthreads();
-    const int gw = blockIdx.x * (kSmThreads / 64) + (threadIdx.x >> 6);
+}
+
+// One wave of the column pass: wave gw of the image's (pair group, column
+// group, segment) space walks its segment down its 64 columns.
+template <int NB, int G, int MODE>
+__device__ __forceinline__ void strm_v_body(const StrmVArgs& a, int gw, const double* wtab) {
+    constexpr int NT = 1 << NB;
+    constexpr bool BWD = MODE == kSmBwd;
+    const int lane = threadIdx.x & 63;
+    const int H = a.H;
     const int pg = gw % a.ngroups;
     const int rest = gw / a.ngroups;
     const int cg = rest % a.ncolg;
     const int sg = rest / a.ncolg;
-    if (sg >= a.nseg) return;   // after the only barrier
+    if (sg >= a.nseg) return;
     const int x = cg * 64 + lane;
     if (x >= a.W) return;
     const int n0 = sg * a.seg, n1 = min(H, n0 + a.seg);
@@ -292,6 +298,14 @@ __global__ void __launch_bounds__(kSmThreads) bf_strm_v(const StrmVArgs a) {
     }
 }
 
+template <int NB, int G, int MODE>
+__global__ void __launch_bounds__(kSmThreads) bf_strm_v(const StrmVArgs a) {
+    extern __shared__ double wtab[];   // [k][s]: integrator weights of the segment start
+    strm_weights<NB>(a, wtab, threadIdx.x, kSmThreads);
+    __syncthreads();
+    strm_v_body<NB, G, MODE>(a, blockIdx.x * (kSmThreads / 64) + (threadIdx.x >> 6), wtab);
+}
+
 // A = G / eta and B = A (out - T/2), the adjoint's per-pixel weights.
 __global__ void __launch_bounds__(kSmThreads) bf_strm_ab(const float* gout, const float* feta,
                                                           const float* fout, float* ab,
@@ -355,7 +369,7 @@ __device__ __forceinline__ void wave_sync_lds() {
 // the line covers 64 E >= W + 2R positions.  MODE: forward (AUX: also the
 // adjoint's sums P and Q) or adjoint.
 template <int E, int MODE, bool AUX>
-__global__ void __launch_bounds__(kSmThreads) bf_strm_h(const StrmHArgs a) {
+__device__ __forceinline__ void strm_h_body(const StrmHArgs& a, int y) {
     constexpr int NX = (64 * E + kSmThreads - 1) / kSmThreads;   // pixels per thread at most
     constexpr bool BWD = MODE == kSmBwd;
     constexpr int NACC = BWD ? 1 : (AUX ? 4 : 2);   // sums per pixel
@@ -363,7 +377,6 @@ __global__ void __launch_bounds__(kSmThreads) bf_strm_h(const StrmHArgs a) {
     const int t = threadIdx.x;
     const int wave = __builtin_amdgcn_readfirstlane(t >> 6);
     const int lane = t & 63;
-    const int y = blockIdx.x;
     const int W = a.W, R = a.R;
     const size_t HW = (size_t)a.H * W;
     uint32_t* buf = slds + wave * a.bufsz;
@@ -539,6 +552,100 @@ __global__ void __launch_bounds__(kSmThreads) bf_strm_h(const StrmHArgs a) {
     }
 }
 
+template <int E, int MODE, bool AUX>
+__global__ void __launch_bounds__(kSmThreads) bf_strm_h(const StrmHArgs a) {
+    strm_h_body<E, MODE, AUX>(a, blockIdx.x);
+}
+
+// ---- batches: the same passes over many images, one launch per pass ---------
+
+struct SbTask {
+    int img;     // image of the batch
+    int unit;    // column pass: wave in the image's space; row pass: image row
+};
+
+// Column pass over a batch: wave gw takes task gw (its image's arguments are
+// read from device memory; the segment-start weights go to a wave-private
+// slice of LDS of kinit_max * NB doubles).
+template <int NB, int G, int MODE>
+__global__ void __launch_bounds__(kSmThreads) bf_sb_v(const StrmVArgs* args, const SbTask* tasks,
+                                                      int ntasks, int wslice) {
+    extern __shared__ double wt[];
+    const int wave = threadIdx.x >> 6;
+    const int gw = blockIdx.x * (kSmThreads / 64) + wave;
+    if (gw >= ntasks) return;   // no block barriers in this kernel
+    const int img = __builtin_amdgcn_readfirstlane(tasks[gw].img);
+    const int unit = __builtin_amdgcn_readfirstlane(tasks[gw].unit);
+    const StrmVArgs& a = args[img];
+    double* wtab = wt + (size_t)wave * wslice;
+    strm_weights<NB>(a, wtab, threadIdx.x & 63, 64);
+    wave_sync_lds();
+    strm_v_body<NB, G, MODE>(a, unit, wtab);
+}
+
+// Row pass over a batch: workgroup b filters row tasks[b].unit of image
+// tasks[b].img (all images of one launch share the line length E).
+template <int E, int MODE, bool AUX>
+__global__ void __launch_bounds__(kSmThreads) bf_sb_h(const StrmHArgs* args, const SbTask* tasks) {
+    const int img = __builtin_amdgcn_readfirstlane(tasks[blockIdx.x].img);
+    const int y = __builtin_amdgcn_readfirstlane(tasks[blockIdx.x].unit);
+    strm_h_body<E, MODE, AUX>(args[img], y);
+}
+
+struct SbLossImg {
+    const float* out;
+    const float* eta;
+    const float* target;
+    float* ab;          // A, B planes of the image
+    int H, W;
+    float center;
+};
+
+// Per row of every image: the SSD loss gradient G = 2 (out - target), the
+// adjoint's weights A = G / eta and B = A (out - T/2), and the row's partial
+// sum of squared differences (a fixed-order block reduction).
+__global__ void __launch_bounds__(kSmThreads) bf_sb_lossab(const SbLossImg* imgs,
+                                                           const SbTask* tasks, float* row_part) {
+    __shared__ float red[kSmThreads];
+    const SbTask tk = tasks[blockIdx.x];
+    const SbLossImg& m = imgs[tk.img];
+    const size_t HW = (size_t)m.H * m.W;
+    float acc = 0.0f;
+    for (int x = threadIdx.x; x < m.W; x += kSmThreads) {
+        const size_t o = (size_t)tk.unit * m.W + x;
+        const float d = m.out[o] - m.target[o];
+        const float A = 2.0f * d / m.eta[o];
+        m.ab[o] = A;
+        m.ab[HW + o] = A * (m.out[o] - m.center);
+        acc = fmaf(d, d, acc);
+    }
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int w = kSmThreads / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) row_part[blockIdx.x] = red[0];
+}
+
+// loss[i] = the sum of image i's row partials (rows row_first[i] ..
+// row_first[i] + H_i - 1 of the row task list), in a fixed order.
+__global__ void __launch_bounds__(kSmThreads) bf_sb_lossred(const float* row_part,
+                                                            const int* row_first,
+                                                            const int* row_count, float* loss) {
+    __shared__ float red[kSmThreads];
+    const int i = blockIdx.x;
+    float acc = 0.0f;
+    for (int r = threadIdx.x; r < row_count[i]; r += kSmThreads) acc += row_part[row_first[i] + r];
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int w = kSmThreads / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) loss[i] = red[0];
+}
+
 // ---- host side -----------------------------------------------------------
 
 namespace {
@@ -674,35 +781,27 @@ bool prefer_stream(int64_t H, int64_t W, const SpatialParams& sp, bf_status fuse
     return stream_supported(W, sp);
 }
 
-bf_status launch_stream(int mode, const StreamIO& io, int64_t H, int64_t W,
-                        const RangeParams& rp, const SpatialParams& sp, void* workspace,
-                        size_t ws_bytes, hipStream_t stream) {
-    if (!stream_supported(W, sp)) {
-        set_error("streamed path: W + 2R = %lld exceeds %d samples, or the kernel's mass is "
-                  "too large", (long long)(W + 2 * sp.R), 64 * kSmLineMax);
-        return BF_EUNSUPPORTED;
-    }
-    const int chunk = stream_chunk_pairs(H, W, ws_bytes, rp.npairs);
-    if (chunk <= 0) {
-        set_error("streamed path: workspace of %zu bytes is below the %zu bytes one pair needs",
-                  ws_bytes, stream_workspace_bytes(H, W, 1));
-        return BF_EINVAL;
-    }
-    const bool bwd = mode == kSmBwd;
-    const bool aux = !bwd && io.aux != nullptr;
-    const int Wp = (int)plane_pitch(W);
-    const size_t HW = (size_t)H * (size_t)W;
-    float* vp = static_cast<float*>(workspace);
-    float* part = vp + (size_t)4 * chunk * H * Wp;
-    float* ab = part + 4 * HW;
-    if (bwd) {
-        const unsigned nb = (unsigned)std::min<size_t>((HW + kSmThreads - 1) / kSmThreads, 4096);
-        hipLaunchKernelGGL(bf_strm_ab, dim3(nb), dim3(kSmThreads), 0, stream, io.gout, io.feta,
-                           io.fout, ab, HW, rp.center);
-    }
+namespace {
 
-    // column pass: taps and the segment-start weights' extent
-    StrmVArgs va = {};
+// Everything of one image's two passes but the pair chunk.
+struct StreamSetup {
+    StrmVArgs va;
+    StrmHArgs ha;
+    int E;            // row-pass samples per lane
+    size_t lds_v;     // column pass: the segment-start weights
+    size_t lds_h;     // row pass: four line buffers
+};
+
+// row pass: the first stage's grid comes from each row's largest sample
+// (|q| L1 < 2^30); the shifts after each stage keep the next window sum below
+// 2^30 for that worst case
+bf_status stream_setup(int mode, const StreamIO& io, int64_t H, int64_t W,
+                       const RangeParams& rp, const SpatialParams& sp, float* vp, float* part,
+                       float* ab, StreamSetup* o) {
+    const bool bwd = mode == kSmBwd;
+    const int Wp = (int)plane_pitch(W);
+    StrmVArgs& va = o->va;
+    va = StrmVArgs{};
     va.f = io.f;
     va.ab = ab;
     va.vp = vp;
@@ -714,12 +813,10 @@ bf_status launch_stream(int mode, const StreamIO& io, int64_t H, int64_t W,
     va.center = rp.center;
     va.two_alpha = (float)(2.0 * rp.alpha);
     va.kinit = 2 * sp.R + sp.nb;
-    const size_t lds_v = (size_t)va.kinit * sp.nb * sizeof(double);
+    o->lds_v = (size_t)va.kinit * sp.nb * sizeof(double);
 
-    // row pass: the first stage's grid comes from each row's largest sample
-    // (|q| L1 < 2^30); the shifts after each stage keep the next window sum
-    // below 2^30 for that worst case
-    StrmHArgs ha = {};
+    StrmHArgs& ha = o->ha;
+    ha = StrmHArgs{};
     ha.f = io.f;
     ha.vp = vp;
     ha.out = bwd ? io.gf : io.out;
@@ -741,116 +838,498 @@ bf_status launch_stream(int mode, const StreamIO& io, int64_t H, int64_t W,
         ha.r[k] = sp.r[k];
         rmax = std::max(rmax, sp.r[k]);
     }
-    {
-        double qmax = 1073741824.0 / (2.0 * sp.r[0] + 1.0) + 1.0;
-        ha.shtot = 0;
-        for (int k = 0; k < sp.nb; ++k) {
-            const double smax = (2.0 * sp.r[k] + 1.0) * qmax;   // window sum of stage k
-            int sh = 0;
-            if (k + 1 < sp.nb) {
-                const double lim = 1073741824.0 / (2.0 * sp.r[k + 1] + 1.0);
-                while (smax / std::ldexp(1.0, sh) + 1.0 > lim) ++sh;
-                qmax = smax / std::ldexp(1.0, sh) + 1.0;
-                ha.shtot += sh;
-            }
-            ha.sh[k] = sh;
+    double qmax = 1073741824.0 / (2.0 * sp.r[0] + 1.0) + 1.0;
+    ha.shtot = 0;
+    for (int k = 0; k < sp.nb; ++k) {
+        const double smax = (2.0 * sp.r[k] + 1.0) * qmax;   // window sum of stage k
+        int sh = 0;
+        if (k + 1 < sp.nb) {
+            const double lim = 1073741824.0 / (2.0 * sp.r[k + 1] + 1.0);
+            while (smax / std::ldexp(1.0, sh) + 1.0 > lim) ++sh;
+            qmax = smax / std::ldexp(1.0, sh) + 1.0;
+            ha.shtot += sh;
         }
+        ha.sh[k] = sh;
     }
-    const int E = line_lanes(W, sp.R);
+    o->E = line_lanes(W, sp.R);
     ha.padl = ((rmax + 1 + sp.R + 3) & ~3) - sp.R;   // line + R is 16-byte aligned
     // after the line: rmax + 1 for the window reads of unused outputs, and
     // room for the row's 16-byte stores and the demodulation's pixel slots,
     // which run to R + 256 ceil(64 E / 256)
-    const int nxs = (64 * E + kSmThreads - 1) / kSmThreads;
-    const int tail = std::max(rmax + 1, sp.R + kSmThreads * nxs - 64 * E);
-    ha.bufsz = (ha.padl + 64 * E + tail + 3) & ~3;
-    const size_t lds_h = (size_t)4 * ha.bufsz * sizeof(uint32_t);
-    if (lds_h > 160 * 1024) {
-        set_error("streamed path: row pass needs %zu bytes of LDS", lds_h);
+    const int nxs = (64 * o->E + kSmThreads - 1) / kSmThreads;
+    const int tail = std::max(rmax + 1, sp.R + kSmThreads * nxs - 64 * o->E);
+    ha.bufsz = (ha.padl + 64 * o->E + tail + 3) & ~3;
+    o->lds_h = (size_t)4 * ha.bufsz * sizeof(uint32_t);
+    if (o->lds_h > 160 * 1024) {
+        set_error("streamed path: row pass needs %zu bytes of LDS", o->lds_h);
         return BF_EUNSUPPORTED;
     }
+    return BF_OK;
+}
 
-    // the column pass's parallelism: 64-column groups x pair groups x row
-    // segments, each starting from the exact state summed over the 2R + nb
-    // rows above it; pick the segment count with the least modelled time
-    // (waves in flight: 8 per CU)
+// The pair chunk qb .. qb + np - 1 (chunk ci of nchunks) and nseg column
+// segments.
+void stream_chunk(StreamSetup& s, const RangeParams& rp, const SpatialParams& sp, int qb, int np,
+                  int ci, int nchunks, int nseg) {
+    const int G = sm_group(sp.nb);
+    const int ngroups = (np + G - 1) / G;
+    StrmVArgs& va = s.va;
+    va.npairs = np;
+    va.ngroups = ngroups;
+    va.ncolg = (va.W + 63) / 64;
+    for (int g = 0; g < ngroups; ++g) {
+        const double ma = (double)(rp.odd + 2 * (qb + g * G)) * rp.alpha;
+        va.mh[g] = (float)ma;
+        va.ml[g] = (float)(ma - (double)va.mh[g]);
+    }
+    va.nseg = nseg;
+    va.seg = (va.H + nseg - 1) / nseg;
+    StrmHArgs& ha = s.ha;
+    ha.npairs = np;
+    ha.m0 = rp.odd + 2 * qb;
+    ha.first = ci == 0;
+    ha.last = ci == nchunks - 1;
+    for (int q = 0; q < np; ++q) {
+        ha.chat[q] = rp.chat[qb + q];
+        const double ma = (double)(rp.odd + 2 * (qb + q)) * rp.alpha;
+        ha.mh[q] = (float)ma;
+        ha.ml[q] = (float)(ma - (double)ha.mh[q]);
+    }
+}
+
+// The fewest segments of at most kSmSegMax rows (the FP64 integrators'
+// rounding drifts roughly as the cube of the rows run: a 16384-row column
+// reached 3e-2 gray; each segment starts from the exact state).
+int min_segments(int64_t H) { return (int)((H + kSmSegMax - 1) / kSmSegMax); }
+
+// Segment count of a single image's column pass: the least modelled time with
+// `slots` waves in flight, a segment start costing about a quarter of a step
+// per row above it.
+int image_segments(int64_t H, int64_t W, const SpatialParams& sp, int ngroups, double slots) {
+    const int ncolg = (int)((W + 63) / 64);
+    const int ns0 = min_segments(H);
+    int best = ns0;
+    double best_cost = 1e300;
+    for (int ns = ns0; ns <= ns0 + 64; ++ns) {
+        const int seg = (int)((H + ns - 1) / ns);
+        if (ns > ns0 && seg < 16) break;
+        const double waves = (double)ncolg * ngroups * ns;
+        const double start = ns > 1 ? 0.25 * (2.0 * sp.R + sp.nb) : 0.25 * sp.R;
+        const double cost = std::ceil(waves / slots) * (seg + start) +
+                            0.05 * waves / slots * (seg + start);
+        if (cost < best_cost) {
+            best_cost = cost;
+            best = ns;
+        }
+    }
+    return best;
+}
+
+double device_slots() {
     int dev = 0, cus = 256;
     if (hipGetDevice(&dev) == hipSuccess)
         (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-    const int ncolg = (int)((W + 63) / 64);
-    const double slots = 8.0 * cus;
+    return 8.0 * std::max(cus, 1);   // two waves per SIMD
+}
 
+void launch_v_mode(int mode, int nb, const StrmVArgs& va, hipStream_t stream, unsigned blocks,
+                   size_t lds) {
+    if (mode == kSmBwd) {
+        switch (nb) {
+            case 1: launch_v<1, kSmBwd>(va, stream, blocks, lds); break;
+            case 2: launch_v<2, kSmBwd>(va, stream, blocks, lds); break;
+            case 3: launch_v<3, kSmBwd>(va, stream, blocks, lds); break;
+            default: launch_v<4, kSmBwd>(va, stream, blocks, lds); break;
+        }
+    } else {
+        switch (nb) {
+            case 1: launch_v<1, kSmFwd>(va, stream, blocks, lds); break;
+            case 2: launch_v<2, kSmFwd>(va, stream, blocks, lds); break;
+            case 3: launch_v<3, kSmFwd>(va, stream, blocks, lds); break;
+            default: launch_v<4, kSmFwd>(va, stream, blocks, lds); break;
+        }
+    }
+}
+
+void launch_h_mode(int mode, bool aux, const StrmHArgs& ha, int E, hipStream_t stream,
+                   unsigned blocks, size_t lds) {
+    if (mode == kSmBwd)
+        launch_h<kSmBwd, false>(ha, E, stream, blocks, lds);
+    else if (aux)
+        launch_h<kSmFwd, true>(ha, E, stream, blocks, lds);
+    else
+        launch_h<kSmFwd, false>(ha, E, stream, blocks, lds);
+}
+
+}  // namespace
+
+bf_status launch_stream(int mode, const StreamIO& io, int64_t H, int64_t W,
+                        const RangeParams& rp, const SpatialParams& sp, void* workspace,
+                        size_t ws_bytes, hipStream_t stream) {
+    if (!stream_supported(W, sp)) {
+        set_error("streamed path: W + 2R = %lld exceeds %d samples, or the kernel's mass is "
+                  "too large", (long long)(W + 2 * sp.R), 64 * kSmLineMax);
+        return BF_EUNSUPPORTED;
+    }
+    const int chunk = stream_chunk_pairs(H, W, ws_bytes, rp.npairs);
+    if (chunk <= 0) {
+        set_error("streamed path: workspace of %zu bytes is below the %zu bytes one pair needs",
+                  ws_bytes, stream_workspace_bytes(H, W, 1));
+        return BF_EINVAL;
+    }
+    const bool bwd = mode == kSmBwd;
+    const bool aux = !bwd && io.aux != nullptr;
+    const int Wp = (int)plane_pitch(W);
+    const size_t HW = (size_t)H * (size_t)W;
+    float* vp = static_cast<float*>(workspace);
+    float* part = vp + (size_t)4 * chunk * H * Wp;
+    float* ab = part + 4 * HW;
+    StreamSetup su;
+    bf_status st = stream_setup(mode, io, H, W, rp, sp, vp, part, ab, &su);
+    if (st != BF_OK) return st;
+    if (bwd) {
+        const unsigned nb = (unsigned)std::min<size_t>((HW + kSmThreads - 1) / kSmThreads, 4096);
+        hipLaunchKernelGGL(bf_strm_ab, dim3(nb), dim3(kSmThreads), 0, stream, io.gout, io.feta,
+                           io.fout, ab, HW, rp.center);
+    }
+    const double slots = device_slots();
     const int nchunks = (rp.npairs + chunk - 1) / chunk;
     for (int ci = 0; ci < nchunks; ++ci) {
         const int qb = ci * chunk;
         const int np = std::min(chunk, rp.npairs - qb);
         const int G = sm_group(sp.nb);
-        const int ngroups = (np + G - 1) / G;
-        va.npairs = np;
-        va.ngroups = ngroups;
-        va.ncolg = ncolg;
-        for (int g = 0; g < ngroups; ++g) {
-            const double ma = (double)(rp.odd + 2 * (qb + g * G)) * rp.alpha;
-            va.mh[g] = (float)ma;
-            va.ml[g] = (float)(ma - (double)va.mh[g]);
-        }
-        // segments of at most kSmSegMax rows: the FP64 integrators' rounding
-        // drifts roughly as the cube of the rows run (a 16384-row column
-        // reached 3e-2 gray); each segment starts from the exact state
-        const int ns0 = (int)((H + kSmSegMax - 1) / kSmSegMax);
-        int best = ns0;
-        double best_cost = 1e300;
-        for (int ns = ns0; ns <= ns0 + 64; ++ns) {
-            const int seg = (int)((H + ns - 1) / ns);
-            if (ns > ns0 && seg < 16) break;
-            const double waves = (double)ncolg * ngroups * ns;
-            const double start = ns > 1 ? 0.25 * (2.0 * sp.R + sp.nb) : 0.25 * sp.R;
-            const double cost = std::ceil(waves / slots) * (seg + start) +
-                                0.05 * waves / slots * (seg + start);
-            if (cost < best_cost) {
-                best_cost = cost;
-                best = ns;
-            }
-        }
-        va.nseg = best;
-        va.seg = (int)((H + best - 1) / best);
-        const long long waves = (long long)ncolg * ngroups * va.nseg;
-        const unsigned vblocks = (unsigned)((waves + 3) / 4);
-        if (bwd) {
-            switch (sp.nb) {
-                case 1: launch_v<1, kSmBwd>(va, stream, vblocks, lds_v); break;
-                case 2: launch_v<2, kSmBwd>(va, stream, vblocks, lds_v); break;
-                case 3: launch_v<3, kSmBwd>(va, stream, vblocks, lds_v); break;
-                default: launch_v<4, kSmBwd>(va, stream, vblocks, lds_v); break;
-            }
-        } else {
-            switch (sp.nb) {
-                case 1: launch_v<1, kSmFwd>(va, stream, vblocks, lds_v); break;
-                case 2: launch_v<2, kSmFwd>(va, stream, vblocks, lds_v); break;
-                case 3: launch_v<3, kSmFwd>(va, stream, vblocks, lds_v); break;
-                default: launch_v<4, kSmFwd>(va, stream, vblocks, lds_v); break;
-            }
-        }
-        ha.npairs = np;
-        ha.m0 = rp.odd + 2 * qb;
-        ha.first = ci == 0;
-        ha.last = ci == nchunks - 1;
-        for (int q = 0; q < np; ++q) {
-            ha.chat[q] = rp.chat[qb + q];
-            const double ma = (double)(rp.odd + 2 * (qb + q)) * rp.alpha;
-            ha.mh[q] = (float)ma;
-            ha.ml[q] = (float)(ma - (double)ha.mh[q]);
-        }
-        if (bwd)
-            launch_h<kSmBwd, false>(ha, E, stream, (unsigned)H, lds_h);
-        else if (aux)
-            launch_h<kSmFwd, true>(ha, E, stream, (unsigned)H, lds_h);
-        else
-            launch_h<kSmFwd, false>(ha, E, stream, (unsigned)H, lds_h);
+        const int nseg = image_segments(H, W, sp, (np + G - 1) / G, slots);
+        stream_chunk(su, rp, sp, qb, np, ci, nchunks, nseg);
+        const long long waves = (long long)su.va.ncolg * su.va.ngroups * nseg;
+        launch_v_mode(mode, sp.nb, su.va, stream, (unsigned)((waves + 3) / 4), su.lds_v);
+        launch_h_mode(mode, aux, su.ha, su.E, stream, (unsigned)H, su.lds_h);
     }
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) {
         set_error("streamed path launch: %s", hipGetErrorString(e));
+        return BF_EDEVICE;
+    }
+    return BF_OK;
+}
+
+// ---- batches ----------------------------------------------------------------
+
+struct StreamBatch {
+    int n = 0;
+    bool bwd = false;               // bound with targets: loss and adjoint too
+    std::vector<RangeParams> rp;
+    std::vector<SpatialParams> sp;
+    std::vector<StreamSetup> fw, bw;   // per image: forward and adjoint arguments
+    std::vector<int64_t> H, W;
+    std::vector<size_t> vp_off, hw_off;   // per image: plane and pixel-plane offsets
+    std::vector<SbLossImg> li;
+    struct Group {
+        int key;        // column pass: nb; row pass: E
+        int off, count; // slice of the task list
+        size_t lds;
+    };
+    std::vector<Group> vgroups, hgroups;
+    int nrows = 0;
+    float* loss = nullptr;
+    // device memory (owned)
+    float* planes = nullptr;        // column-filtered channels of every image, all pairs
+    float* aux = nullptr;           // forward -> adjoint sums P, Q
+    float* ab = nullptr;            // adjoint weights A, B
+    StrmVArgs* va_f = nullptr;
+    StrmVArgs* va_b = nullptr;
+    StrmHArgs* ha_f = nullptr;
+    StrmHArgs* ha_b = nullptr;
+    SbLossImg* li_d = nullptr;
+    SbTask* vtasks = nullptr;
+    SbTask* htasks = nullptr;
+    SbTask* rows = nullptr;         // every row of every image, image by image
+    float* row_part = nullptr;
+    int* row_first = nullptr;
+    int* row_count = nullptr;
+    int nvtasks = 0, nhtasks = 0;
+};
+
+namespace {
+
+template <typename T>
+bf_status sb_alloc(T** p, size_t count) {
+    if (hipMalloc((void**)p, std::max<size_t>(count, 1) * sizeof(T)) != hipSuccess) {
+        *p = nullptr;
+        (void)hipGetLastError();
+        set_error("hipMalloc of %zu bytes for the streamed batch failed", count * sizeof(T));
+        return BF_ENOMEM;
+    }
+    return BF_OK;
+}
+
+template <typename T>
+bf_status sb_upload(T* d, const std::vector<T>& h) {
+    if (h.empty()) return BF_OK;
+    if (hipMemcpy(d, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice) != hipSuccess) {
+        set_error("upload of the streamed batch tables failed");
+        return BF_EDEVICE;
+    }
+    return BF_OK;
+}
+
+}  // namespace
+
+bool stream_batch_supported(int64_t H, int64_t W, const SpatialParams& sp, int npairs) {
+    (void)H;
+    return stream_supported(W, sp) && npairs <= kSmMaxGroups * sm_group(sp.nb) &&
+           npairs <= kSmMaxChunk;
+}
+
+void stream_batch_destroy(StreamBatch* b) {
+    if (!b) return;
+    (void)hipFree(b->planes);
+    (void)hipFree(b->aux);
+    (void)hipFree(b->ab);
+    (void)hipFree(b->va_f);
+    (void)hipFree(b->va_b);
+    (void)hipFree(b->ha_f);
+    (void)hipFree(b->ha_b);
+    (void)hipFree(b->li_d);
+    (void)hipFree(b->vtasks);
+    (void)hipFree(b->htasks);
+    (void)hipFree(b->rows);
+    (void)hipFree(b->row_part);
+    (void)hipFree(b->row_first);
+    (void)hipFree(b->row_count);
+    delete b;
+}
+
+bf_status stream_batch_create(int n, const int64_t* H, const int64_t* W, const RangeParams* rp,
+                              const SpatialParams* sp, StreamBatch** out) {
+    StreamBatch* b = new StreamBatch();
+    b->n = n;
+    b->rp.assign(rp, rp + n);
+    b->sp.assign(sp, sp + n);
+    b->H.assign(H, H + n);
+    b->W.assign(W, W + n);
+    b->fw.resize(n);
+    b->bw.resize(n);
+    b->vp_off.resize(n);
+    b->hw_off.resize(n);
+    size_t planes = 0, pix = 0;
+    for (int i = 0; i < n; ++i) {
+        if (!stream_batch_supported(H[i], W[i], sp[i], rp[i].npairs)) {
+            set_error("image %d: outside the streamed passes' limits", i);
+            stream_batch_destroy(b);
+            return BF_EUNSUPPORTED;
+        }
+        b->vp_off[i] = planes;
+        planes += (size_t)4 * rp[i].npairs * H[i] * plane_pitch(W[i]);
+        b->hw_off[i] = pix;
+        pix += (size_t)H[i] * W[i];
+        b->nrows += (int)H[i];
+    }
+    bf_status st;
+    if ((st = sb_alloc(&b->planes, planes)) != BF_OK || (st = sb_alloc(&b->aux, 2 * pix)) != BF_OK ||
+        (st = sb_alloc(&b->ab, 2 * pix)) != BF_OK || (st = sb_alloc(&b->va_f, n)) != BF_OK ||
+        (st = sb_alloc(&b->va_b, n)) != BF_OK || (st = sb_alloc(&b->ha_f, n)) != BF_OK ||
+        (st = sb_alloc(&b->ha_b, n)) != BF_OK || (st = sb_alloc(&b->li_d, n)) != BF_OK ||
+        (st = sb_alloc(&b->rows, b->nrows)) != BF_OK ||
+        (st = sb_alloc(&b->row_part, b->nrows)) != BF_OK ||
+        (st = sb_alloc(&b->row_first, n)) != BF_OK || (st = sb_alloc(&b->row_count, n)) != BF_OK) {
+        stream_batch_destroy(b);
+        return st;
+    }
+    // task lists: column waves grouped by box count, longest first; rows
+    // grouped by line length, image by image
+    struct VT {
+        double cost;
+        int nb;
+        SbTask t;
+    };
+    std::vector<VT> vt;
+    std::vector<SbTask> rows;
+    std::vector<int> row_first(n), row_count(n);
+    for (int i = 0; i < n; ++i) {
+        const int G = sm_group(sp[i].nb);
+        const int ngroups = (rp[i].npairs + G - 1) / G;
+        const int nseg = min_segments(H[i]);
+        const int ncolg = (int)((W[i] + 63) / 64);
+        const int seg = (int)((H[i] + nseg - 1) / nseg);
+        const double cost = (seg + 0.25 * (2.0 * sp[i].R + sp[i].nb)) * (1 << sp[i].nb);
+        for (int u = 0; u < ncolg * ngroups * nseg; ++u) vt.push_back({cost, sp[i].nb, {i, u}});
+        row_first[i] = (int)rows.size();
+        row_count[i] = (int)H[i];
+        for (int y = 0; y < (int)H[i]; ++y) rows.push_back({i, y});
+    }
+    std::stable_sort(vt.begin(), vt.end(), [](const VT& a, const VT& c) {
+        return a.nb < c.nb || (a.nb == c.nb && a.cost > c.cost);
+    });
+    std::vector<SbTask> vtasks;
+    for (size_t k = 0; k < vt.size(); ++k) {
+        if (b->vgroups.empty() || b->vgroups.back().key != vt[k].nb)
+            b->vgroups.push_back({vt[k].nb, (int)k, 0, 0});
+        b->vgroups.back().count++;
+        vtasks.push_back(vt[k].t);
+    }
+    std::vector<int> E(n);
+    for (int i = 0; i < n; ++i) E[i] = line_lanes(W[i], sp[i].R);
+    std::vector<SbTask> htasks;
+    std::vector<int> keys(E.begin(), E.end());
+    std::sort(keys.begin(), keys.end());
+    keys.erase(std::unique(keys.begin(), keys.end()), keys.end());
+    for (int e : keys) {
+        b->hgroups.push_back({e, (int)htasks.size(), 0, 0});
+        for (int i = 0; i < n; ++i)
+            if (E[i] == e)
+                for (int y = 0; y < (int)H[i]; ++y) htasks.push_back({i, y});
+        b->hgroups.back().count = (int)htasks.size() - b->hgroups.back().off;
+    }
+    b->nvtasks = (int)vtasks.size();
+    b->nhtasks = (int)htasks.size();
+    if ((st = sb_alloc(&b->vtasks, vtasks.size())) != BF_OK ||
+        (st = sb_alloc(&b->htasks, htasks.size())) != BF_OK ||
+        (st = sb_upload(b->vtasks, vtasks)) != BF_OK || (st = sb_upload(b->htasks, htasks)) != BF_OK ||
+        (st = sb_upload(b->rows, rows)) != BF_OK || (st = sb_upload(b->row_first, row_first)) != BF_OK ||
+        (st = sb_upload(b->row_count, row_count)) != BF_OK) {
+        stream_batch_destroy(b);
+        return st;
+    }
+    *out = b;
+    return BF_OK;
+}
+
+bf_status stream_batch_bind(StreamBatch* b, const float* const* f, const float* const* target,
+                            float* const* out, float* const* eta, float* const* gf, float* loss) {
+    const int n = b->n;
+    b->bwd = gf != nullptr;
+    std::vector<StrmVArgs> vaf(n), vab(n);
+    std::vector<StrmHArgs> haf(n), hab(n);
+    b->li.assign(n, SbLossImg{});
+    for (auto& g : b->vgroups) g.lds = 0;
+    for (auto& g : b->hgroups) g.lds = 0;
+    for (int i = 0; i < n; ++i) {
+        const int64_t H = b->H[i], W = b->W[i];
+        float* vp = b->planes + b->vp_off[i];
+        float* aux = b->aux + 2 * b->hw_off[i];
+        float* ab = b->ab + 2 * b->hw_off[i];
+        StreamIO io = {};
+        io.f = f[i];
+        io.out = out[i];
+        io.eta = eta ? eta[i] : nullptr;
+        io.aux = b->bwd ? aux : nullptr;
+        bf_status st = stream_setup(kSmFwd, io, H, W, b->rp[i], b->sp[i], vp, nullptr, ab,
+                                    &b->fw[i]);
+        if (st != BF_OK) return st;
+        const int nseg = min_segments(H);
+        stream_chunk(b->fw[i], b->rp[i], b->sp[i], 0, b->rp[i].npairs, 0, 1, nseg);
+        vaf[i] = b->fw[i].va;
+        haf[i] = b->fw[i].ha;
+        if (b->bwd) {
+            StreamIO jo = {};
+            jo.f = f[i];
+            jo.fout = out[i];
+            jo.feta = eta[i];
+            jo.faux = aux;
+            jo.gf = gf[i];
+            st = stream_setup(kSmBwd, jo, H, W, b->rp[i], b->sp[i], vp, nullptr, ab, &b->bw[i]);
+            if (st != BF_OK) return st;
+            stream_chunk(b->bw[i], b->rp[i], b->sp[i], 0, b->rp[i].npairs, 0, 1, nseg);
+            vab[i] = b->bw[i].va;
+            hab[i] = b->bw[i].ha;
+            b->li[i] = SbLossImg{out[i], eta[i], target[i], ab, (int)H, (int)W, b->rp[i].center};
+        }
+        for (auto& g : b->vgroups)
+            if (g.key == b->sp[i].nb)
+                g.lds = std::max(g.lds, (size_t)(kSmThreads / 64) * b->fw[i].lds_v);
+        for (auto& g : b->hgroups)
+            if (g.key == b->fw[i].E) g.lds = std::max(g.lds, b->fw[i].lds_h);
+    }
+    bf_status st;
+    if ((st = sb_upload(b->va_f, vaf)) != BF_OK || (st = sb_upload(b->ha_f, haf)) != BF_OK)
+        return st;
+    if (b->bwd && ((st = sb_upload(b->va_b, vab)) != BF_OK ||
+                   (st = sb_upload(b->ha_b, hab)) != BF_OK || (st = sb_upload(b->li_d, b->li)) != BF_OK))
+        return st;
+    for (const auto& g : b->vgroups)
+        if (g.lds > 160 * 1024) {
+            set_error("streamed batch: the segment-start weights need %zu bytes of LDS", g.lds);
+            return BF_EUNSUPPORTED;
+        }
+    b->loss = loss;
+    return BF_OK;
+}
+
+namespace {
+
+template <int NB, int MODE>
+void launch_sb_v(const StrmVArgs* args, const SbTask* tasks, int count, size_t lds,
+                 hipStream_t s) {
+    auto k = bf_sb_v<NB, sm_group(NB), MODE>;
+    (void)hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)lds);
+    const int wslice = (int)(lds / sizeof(double) / (kSmThreads / 64));
+    hipLaunchKernelGGL(k, dim3((unsigned)((count + 3) / 4)), dim3(kSmThreads), lds, s, args,
+                       tasks, count, wslice);
+}
+
+template <int MODE, bool AUX, int I = 0>
+void launch_sb_h(const StrmHArgs* args, const SbTask* tasks, int count, int E, size_t lds,
+                 hipStream_t s) {
+    if constexpr (I < (int)(sizeof(kSmLines) / sizeof(kSmLines[0]))) {
+        if (E == kSmLines[I]) {
+            auto k = bf_sb_h<kSmLines[I], MODE, AUX>;
+            (void)hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                      (int)lds);
+            hipLaunchKernelGGL(k, dim3((unsigned)count), dim3(kSmThreads), lds, s, args, tasks);
+            return;
+        }
+        launch_sb_h<MODE, AUX, I + 1>(args, tasks, count, E, lds, s);
+    }
+}
+
+void sb_passes(const StreamBatch* b, int mode, bool aux, hipStream_t s) {
+    const StrmVArgs* va = mode == kSmBwd ? b->va_b : b->va_f;
+    const StrmHArgs* ha = mode == kSmBwd ? b->ha_b : b->ha_f;
+    for (const auto& g : b->vgroups) {
+        const SbTask* t = b->vtasks + g.off;
+        if (mode == kSmBwd) {
+            switch (g.key) {
+                case 1: launch_sb_v<1, kSmBwd>(va, t, g.count, g.lds, s); break;
+                case 2: launch_sb_v<2, kSmBwd>(va, t, g.count, g.lds, s); break;
+                case 3: launch_sb_v<3, kSmBwd>(va, t, g.count, g.lds, s); break;
+                default: launch_sb_v<4, kSmBwd>(va, t, g.count, g.lds, s); break;
+            }
+        } else {
+            switch (g.key) {
+                case 1: launch_sb_v<1, kSmFwd>(va, t, g.count, g.lds, s); break;
+                case 2: launch_sb_v<2, kSmFwd>(va, t, g.count, g.lds, s); break;
+                case 3: launch_sb_v<3, kSmFwd>(va, t, g.count, g.lds, s); break;
+                default: launch_sb_v<4, kSmFwd>(va, t, g.count, g.lds, s); break;
+            }
+        }
+    }
+    for (const auto& g : b->hgroups) {
+        const SbTask* t = b->htasks + g.off;
+        if (mode == kSmBwd)
+            launch_sb_h<kSmBwd, false>(ha, t, g.count, g.key, g.lds, s);
+        else if (aux)
+            launch_sb_h<kSmFwd, true>(ha, t, g.count, g.key, g.lds, s);
+        else
+            launch_sb_h<kSmFwd, false>(ha, t, g.count, g.key, g.lds, s);
+    }
+}
+
+}  // namespace
+
+bf_status stream_batch_launch(const StreamBatch* b, hipStream_t s) {
+    sb_passes(b, kSmFwd, b->bwd, s);
+    if (b->bwd) {
+        hipLaunchKernelGGL(bf_sb_lossab, dim3((unsigned)b->nrows), dim3(kSmThreads), 0, s,
+                           b->li_d, b->rows, b->row_part);
+        if (b->loss)
+            hipLaunchKernelGGL(bf_sb_lossred, dim3((unsigned)b->n), dim3(kSmThreads), 0, s,
+                               b->row_part, b->row_first, b->row_count, b->loss);
+        sb_passes(b, kSmBwd, false, s);
+    }
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) {
+        set_error("streamed batch launch: %s", hipGetErrorString(e));
         return BF_EDEVICE;
     }
     return BF_OK;

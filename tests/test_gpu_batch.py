@@ -1,12 +1,16 @@
-"""GPU tests of the batched persistent launch (ragged images, per-image
-sigma_s, sigma_r and N) and of its capture into a HIP graph.
+"""GPU tests of the batched launch (ragged images, per-image sigma_s,
+sigma_r and N) through its two evaluations, the persistent fused-tile kernel
+and the streamed passes over all images, and of its capture into a HIP graph.
 
-Each image of a batch must equal the single-image forward and adjoint kernels
-bit for bit (the batch runs the same tile code with the same tile shapes), the
-per-image SSD loss must equal the sum of squared differences of its outputs,
-and a sample of the ragged workload is checked against the FP64 oracle.
-Graph replays are compared with the eager result after each replay, with
-eager work on the stream between replays.
+With the fused tiles each image of a batch must equal the single-image fused
+forward and adjoint bit for bit (the batch runs the same tile code with the
+same tile shapes); with the streamed passes it must equal the single-image
+streamed evaluation to 1e-5 of the image's largest value (the batch may cut
+the column pass into other segments, which moves the last bits of its FP64
+running sums).  The per-image SSD loss must equal the sum of squared
+differences of its outputs, and a sample of the ragged workload is checked
+against the FP64 oracle.  Graph replays are compared with the eager result
+after each replay, with eager work on the stream between replays.
 """
 import numpy as np
 import pytest
@@ -37,13 +41,23 @@ SPECS = [
 ]
 
 
-def _run_batch(specs, seed0=100):
+FUSED, STREAMED = 1, 2
+PATHS = pytest.mark.parametrize("path", [FUSED, STREAMED], ids=["fused", "streamed"])
+
+
+def _same(a, b, path):
+    if path == FUSED:
+        return torch.equal(a, b)
+    return (a - b).abs().max().item() <= 1e-5 * max(a.abs().max().item(), 1e-30)
+
+
+def _run_batch(specs, seed0=100, path=FUSED):
     batch, ops = _mods()
     f = [_cuda(synth.piecewise_smooth(s["H"], s["W"], seed=seed0 + i, n_shapes=3))
          for i, s in enumerate(specs)]
     t = [_cuda(synth.piecewise_smooth(s["H"], s["W"], seed=seed0 + 50 + i, n_shapes=3))
          for i, s in enumerate(specs)]
-    plan = batch.BatchPlan(specs)
+    plan = batch.BatchPlan(specs, path=path)
     out, eta, gf, loss = plan.allocate()
     plan.bind(f, t, out, eta, gf, loss)
     plan.launch()
@@ -51,29 +65,31 @@ def _run_batch(specs, seed0=100):
     return plan, f, t, out, eta, gf, loss
 
 
-def test_batch_matches_single_image_kernels():
+@PATHS
+def test_batch_matches_single_image_kernels(path):
     batch, ops = _mods()
-    plan, f, t, out, eta, gf, loss = _run_batch(SPECS)
+    plan, f, t, out, eta, gf, loss = _run_batch(SPECS, path=path)
     from paper_1105_4204_amd import _native as nat
     for i, s in enumerate(SPECS):
         radii = s.get("radii") or nat.spatial_gaussian(s["sigma_s"], 3)
-        # the batch runs the fused tiles: compare with the single-image fused kernels
-        o1, e1, x1 = ops.trig_forward(f[i], 255.0, s["sigma_r"], radii, return_aux=True, path=1)
+        o1, e1, x1 = ops.trig_forward(f[i], 255.0, s["sigma_r"], radii, return_aux=True,
+                                      path=path)
         g1 = ops.trig_backward(f[i], o1, e1, x1, 2.0 * (o1 - t[i]), 255.0, s["sigma_r"], radii,
-                               path=1)
+                               path=path)
         torch.cuda.synchronize()
-        print(f"image {i} {s}: out eq={torch.equal(o1, out[i])} grad eq={torch.equal(g1, gf[i])}",
+        print(f"image {i} {s}: out {_same(o1, out[i], path)} grad {_same(g1, gf[i], path)}",
               flush=True)
-        assert torch.equal(o1, out[i]), i
-        assert torch.equal(e1, eta[i]), i
-        assert torch.equal(g1, gf[i]), i
+        assert _same(o1, out[i], path), i
+        assert _same(e1, eta[i], path), i
+        assert _same(g1, gf[i], path), i
         ssd = float(((out[i].double() - t[i].double()) ** 2).sum())
         assert abs(float(loss[i]) - ssd) <= 1e-5 * ssd + 1e-3, (i, float(loss[i]), ssd)
 
 
-def test_batch_forward_only_and_rebind():
+@PATHS
+def test_batch_forward_only_and_rebind(path):
     batch, ops = _mods()
-    plan = batch.BatchPlan(SPECS[:3])
+    plan = batch.BatchPlan(SPECS[:3], path=path)
     f = [_cuda(synth.rectangles(s["H"], s["W"], seed=7 + i)) for i, s in enumerate(SPECS[:3])]
     out, eta, _, _ = plan.allocate(backward=False)
     plan.bind(f, out=out)
@@ -82,7 +98,7 @@ def test_batch_forward_only_and_rebind():
     from paper_1105_4204_amd import _native as nat
     for i, s in enumerate(SPECS[:3]):
         radii = s.get("radii") or nat.spatial_gaussian(s["sigma_s"], 3)
-        assert torch.equal(ops.trig_forward(f[i], 255.0, s["sigma_r"], radii, path=1), out[i])
+        assert _same(ops.trig_forward(f[i], 255.0, s["sigma_r"], radii, path=path), out[i], path)
     # rebind to new buffers
     f2 = [x.flip(0).contiguous() for x in f]
     out2 = [torch.empty_like(x) for x in out]
@@ -91,12 +107,14 @@ def test_batch_forward_only_and_rebind():
     plan.check()
     for i, s in enumerate(SPECS[:3]):
         radii = s.get("radii") or nat.spatial_gaussian(s["sigma_s"], 3)
-        assert torch.equal(ops.trig_forward(f2[i], 255.0, s["sigma_r"], radii, path=1), out2[i])
+        assert _same(ops.trig_forward(f2[i], 255.0, s["sigma_r"], radii, path=path), out2[i],
+                     path)
 
 
-def test_batch_graph_replay():
+@PATHS
+def test_batch_graph_replay(path):
     batch, ops = _mods()
-    plan, f, t, out, eta, gf, loss = _run_batch(SPECS, seed0=300)
+    plan, f, t, out, eta, gf, loss = _run_batch(SPECS, seed0=300, path=path)
     torch.cuda.synchronize()
     ref_out = [o.clone() for o in out]
     ref_gf = [g.clone() for g in gf]
@@ -116,7 +134,8 @@ def test_batch_graph_replay():
         assert torch.equal(loss, ref_loss), rep
 
 
-def test_ragged_workload_sample_vs_oracle():
+@PATHS
+def test_ragged_workload_sample_vs_oracle(path):
     """The first 64 images of the 256-image ragged workload (H, W in
     [64,1024], sigma_s in [2,16], sigma_r in [10,60], per-image N), run as one
     batch; per image 8 random pixels of the forward and 2 of the SSD gradient
@@ -125,7 +144,7 @@ def test_ragged_workload_sample_vs_oracle():
     batch, ops = _mods()
     specs = synth.ragged_batch_specs(64, seed=5)
     fs, ts = synth.ragged_batch_images(specs)
-    plan = batch.BatchPlan(specs)
+    plan = batch.BatchPlan(specs, path=path)
     out, eta, gf, loss = plan.allocate()
     plan.bind([_cuda(x) for x in fs], [_cuda(x) for x in ts], out, eta, gf, loss)
     plan.launch()
@@ -152,21 +171,22 @@ def test_ragged_workload_sample_vs_oracle():
         assert np.all(gerr <= 1e-3 * scale + 1e-3 * np.abs(gref)), (i, gg, gref)
 
 
-def test_colour_channels_as_batch_items():
+@PATHS
+def test_colour_channels_as_batch_items(path):
     """A 3-channel image filtered channel by channel through one batched launch
-    equals three single-image forwards bit for bit, and matches the oracle on
-    sampled pixels of each channel."""
+    equals three single-image forwards (bit for bit with the fused tiles), and
+    matches the oracle on sampled pixels of each channel."""
     batch, ops = _mods()
     img = synth.colour(120, 150, seed=9)
     x = _cuda(img)
-    out = batch.trig_forward_channels(x, 255.0, 25.0, [3, 3, 4])
+    out = batch.trig_forward_channels(x, 255.0, 25.0, [3, 3, 4], path=path)
     torch.cuda.synchronize()
     N = oracle.range_degree(255.0, 25.0)
     rng = np.random.default_rng(4)
     for c in range(3):
-        single = ops.trig_forward(x[c].contiguous(), 255.0, 25.0, [3, 3, 4], path=1)
+        single = ops.trig_forward(x[c].contiguous(), 255.0, 25.0, [3, 3, 4], path=path)
         torch.cuda.synchronize()
-        assert torch.equal(single, out[c]), c
+        assert _same(single, out[c], path), c
         idx = rng.integers(0, 120 * 150, size=20)
         ref = oracle.forward_at(img[c], 25.0, N, [3, 3, 4], idx)
         got = out[c].cpu().numpy().reshape(-1)[idx].astype(np.float64)
@@ -199,7 +219,7 @@ def test_autotuner_picks_valid_tiles_for_a_batch(tmp_path):
           for i, s in enumerate(specs)]
     ts = [_cuda(synth.piecewise_smooth(s["H"], s["W"], seed=80 + i, n_shapes=3))
           for i, s in enumerate(specs)]
-    plan = batch.BatchPlan(specs, tuner=again)
+    plan = batch.BatchPlan(specs, tuner=again, path=FUSED)
     out, eta, gf, loss = plan.allocate()
     plan.bind(fs, ts, out, eta, gf, loss)
     plan.launch()

@@ -103,7 +103,7 @@ def test_truncated_adjoint_and_batch():
              dict(H=50, W=70, radii=[2, 2, 3], sigma_r=30.0)]
     fs = [fd, _cuda(synth.rectangles(50, 70, seed=5))]
     ts = [_cuda(t_np), _cuda(synth.rectangles(50, 70, seed=6))]
-    plan = batch.BatchPlan(specs)
+    plan = batch.BatchPlan(specs, path=1)   # the fused tiles: bit-equal to the single image
     bo, be, bg, bl = plan.allocate()
     plan.bind(fs, ts, bo, be, bg, bl)
     plan.launch()
