@@ -301,6 +301,16 @@ bf_status bf_batch_bind(bf_batch_plan* plan, const float* const* f, const float*
                         float* const* out, float* const* eta, float* const* grad_f,
                         float* loss /* device, n floats, or NULL */);
 bf_status bf_batch_launch(bf_batch_plan* plan, void* stream);
+/* One stage of bf_batch_launch, for timing each of them on its own: on the
+ * streamed passes 0 = forward column pass, 1 = forward row pass, 2 = loss and
+ * the adjoint's weights, 3 = adjoint column pass, 4 = adjoint row pass
+ * (stages without work for this binding enqueue nothing); the persistent
+ * fused kernel has the single stage 0.  The stages of one step must be
+ * enqueued in this order on one stream. */
+bf_status bf_batch_launch_stage(bf_batch_plan* plan, int32_t stage, void* stream);
+/* The evaluation the plan chose: BF_PATH_FUSED or BF_PATH_STREAMED (-1 for a
+ * NULL plan). */
+int32_t bf_batch_plan_path(const bf_batch_plan* plan);
 bf_status bf_batch_check(bf_batch_plan* plan);
 void bf_batch_plan_destroy(bf_batch_plan* plan);
 

@@ -26,7 +26,7 @@ EXPORTS = ["bf_range_degree", "bf_range_coeffs", "bf_range_truncate", "bf_spatia
            "bf_trig_workspace_bytes", "bf_trig_workspace_bytes_ex", "bf_trig_forward",
            "bf_trig_forward_ex", "bf_trig_forward_noalloc", "bf_trig_backward", "bf_sv_forward",
            "bf_yvv_coeffs", "bf_yvv_workspace_bytes", "bf_yvv_forward", "bf_direct_forward", "bf_check_range",
-           "bf_batch_plan_create", "bf_batch_plan_create_ex", "bf_batch_bind", "bf_batch_launch", "bf_batch_check",
+           "bf_batch_plan_create", "bf_batch_plan_create_ex", "bf_batch_bind", "bf_batch_launch", "bf_batch_launch_stage", "bf_batch_plan_path", "bf_batch_check",
            "bf_batch_plan_destroy", "bf_status_string", "bf_last_error"]
 
 
@@ -107,6 +107,8 @@ def lib():
         "bf_batch_bind": [vp, ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(vp),
                           ctypes.POINTER(vp), ctypes.POINTER(vp), vp],
         "bf_batch_launch": [vp, vp],
+        "bf_batch_launch_stage": [vp, i32, vp],
+        "bf_batch_plan_path": [vp],
         "bf_batch_check": [vp],
         "bf_batch_plan_destroy": [vp],
     }

@@ -97,6 +97,17 @@ class BatchPlan:
         nat.check(nat.lib().bf_batch_launch(self._h, ctypes.c_void_p(s.cuda_stream)),
                   "bf_batch_launch")
 
+    def launch_stage(self, stage: int, stream=None):
+        """One stage of launch() (bf_batch_launch_stage), for per-stage timing."""
+        s = stream if stream is not None else torch.cuda.current_stream()
+        nat.check(nat.lib().bf_batch_launch_stage(self._h, int(stage),
+                                                  ctypes.c_void_p(s.cuda_stream)),
+                  "bf_batch_launch_stage")
+
+    def streamed(self) -> bool:
+        """Whether the plan runs the streamed passes (else the fused tiles)."""
+        return nat.lib().bf_batch_plan_path(self._h) == nat.PATH_STREAMED
+
     def check(self):
         nat.check(nat.lib().bf_batch_check(self._h), "bf_batch_check")
 

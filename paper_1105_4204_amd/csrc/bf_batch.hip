@@ -416,6 +416,26 @@ bf_status bf_batch_launch(bf_batch_plan* p, void* stream) {
     return BF_OK;
 }
 
+bf_status bf_batch_launch_stage(bf_batch_plan* p, int32_t stage, void* stream) {
+    if (!p || !p->bound) {
+        set_error("plan missing or not bound");
+        return BF_EINVAL;
+    }
+    if (!p->sb) {
+        if (stage != 0) {
+            set_error("the persistent fused-tile batch has the single stage 0");
+            return BF_EINVAL;
+        }
+        return bf_batch_launch(p, stream);
+    }
+    return stream_batch_stage(p->sb, stage, (hipStream_t)stream);
+}
+
+int32_t bf_batch_plan_path(const bf_batch_plan* p) {
+    if (!p) return -1;
+    return p->sb ? BF_PATH_STREAMED : BF_PATH_FUSED;
+}
+
 bf_status bf_batch_check(bf_batch_plan* p) {
     if (!p) {
         set_error("plan is NULL");

@@ -109,6 +109,7 @@ bf_status stream_batch_create(int n, const int64_t* H, const int64_t* W, const R
 bf_status stream_batch_bind(StreamBatch* b, const float* const* f, const float* const* target,
                             float* const* out, float* const* eta, float* const* gf, float* loss);
 bf_status stream_batch_launch(const StreamBatch* b, hipStream_t s);
+bf_status stream_batch_stage(const StreamBatch* b, int stage, hipStream_t s);
 void stream_batch_destroy(StreamBatch* b);
 // Pairs per chunk of the workspace bf_trig_workspace_bytes recommends; the
 // library's own workspace and bf_trig_workspace_bytes_ex hold every pair up

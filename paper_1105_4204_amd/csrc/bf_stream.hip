@@ -1283,10 +1283,11 @@ void launch_sb_h(const StrmHArgs* args, const SbTask* tasks, int count, int E, s
     }
 }
 
-void sb_passes(const StreamBatch* b, int mode, bool aux, hipStream_t s) {
+void sb_passes(const StreamBatch* b, int mode, bool aux, hipStream_t s, bool col, bool row) {
     const StrmVArgs* va = mode == kSmBwd ? b->va_b : b->va_f;
     const StrmHArgs* ha = mode == kSmBwd ? b->ha_b : b->ha_f;
     for (const auto& g : b->vgroups) {
+        if (!col) break;
         const SbTask* t = b->vtasks + g.off;
         if (mode == kSmBwd) {
             switch (g.key) {
@@ -1305,6 +1306,7 @@ void sb_passes(const StreamBatch* b, int mode, bool aux, hipStream_t s) {
         }
     }
     for (const auto& g : b->hgroups) {
+        if (!row) break;
         const SbTask* t = b->htasks + g.off;
         if (mode == kSmBwd)
             launch_sb_h<kSmBwd, false>(ha, t, g.count, g.key, g.lds, s);
@@ -1317,15 +1319,41 @@ void sb_passes(const StreamBatch* b, int mode, bool aux, hipStream_t s) {
 
 }  // namespace
 
+bf_status stream_batch_stage(const StreamBatch* b, int stage, hipStream_t s) {
+    switch (stage) {
+        case 0: sb_passes(b, kSmFwd, b->bwd, s, true, false); break;
+        case 1: sb_passes(b, kSmFwd, b->bwd, s, false, true); break;
+        case 2:
+            if (b->bwd) {
+                hipLaunchKernelGGL(bf_sb_lossab, dim3((unsigned)b->nrows), dim3(kSmThreads), 0, s,
+                                   b->li_d, b->rows, b->row_part);
+                if (b->loss)
+                    hipLaunchKernelGGL(bf_sb_lossred, dim3((unsigned)b->n), dim3(kSmThreads), 0,
+                                       s, b->row_part, b->row_first, b->row_count, b->loss);
+            }
+            break;
+        case 3:
+            if (b->bwd) sb_passes(b, kSmBwd, false, s, true, false);
+            break;
+        case 4:
+            if (b->bwd) sb_passes(b, kSmBwd, false, s, false, true);
+            break;
+        default:
+            set_error("stage %d is not one of 0..4", stage);
+            return BF_EINVAL;
+    }
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) {
+        set_error("streamed batch launch: %s", hipGetErrorString(e));
+        return BF_EDEVICE;
+    }
+    return BF_OK;
+}
+
 bf_status stream_batch_launch(const StreamBatch* b, hipStream_t s) {
-    sb_passes(b, kSmFwd, b->bwd, s);
-    if (b->bwd) {
-        hipLaunchKernelGGL(bf_sb_lossab, dim3((unsigned)b->nrows), dim3(kSmThreads), 0, s,
-                           b->li_d, b->rows, b->row_part);
-        if (b->loss)
-            hipLaunchKernelGGL(bf_sb_lossred, dim3((unsigned)b->n), dim3(kSmThreads), 0, s,
-                               b->row_part, b->row_first, b->row_count, b->loss);
-        sb_passes(b, kSmBwd, false, s);
+    for (int stage = 0; stage < 5; ++stage) {
+        const bf_status st = stream_batch_stage(b, stage, s);
+        if (st != BF_OK) return st;
     }
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) {

@@ -232,3 +232,25 @@ def test_autotuner_picks_valid_tiles_for_a_batch(tmp_path):
         ref = oracle.forward(fs[i].cpu().numpy(), s["sigma_r"], N, radii)
         err = np.abs(out[i].cpu().numpy().astype(np.float64) - ref)
         assert np.all(err <= 1e-2 + 1e-4 * np.abs(ref)), (i, err.max())
+
+
+@PATHS
+def test_batch_stages_equal_one_launch(path):
+    """Enqueuing the stages one by one gives the same result as one launch,
+    bit for bit, and the plan reports the evaluation it chose."""
+    batch, ops = _mods()
+    plan, f, t, out, eta, gf, loss = _run_batch(SPECS, seed0=500, path=path)
+    assert plan.streamed() == (path == STREAMED)
+    torch.cuda.synchronize()
+    ref = ([o.clone() for o in out], [g.clone() for g in gf], loss.clone())
+    for o in out:
+        o.fill_(-1.0)
+    loss.fill_(0.0)
+    for k in range(5 if path == STREAMED else 1):
+        plan.launch_stage(k)
+    plan.check()
+    torch.cuda.synchronize()
+    for i in range(len(SPECS)):
+        assert torch.equal(out[i], ref[0][i]), i
+        assert torch.equal(gf[i], ref[1][i]), i
+    assert torch.equal(loss, ref[2])

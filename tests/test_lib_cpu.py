@@ -20,7 +20,7 @@ GOLD = os.path.join(ROOT, "tests", "golden")
 def _declared_functions():
     src = open(HEADER).read()
     src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
-    return sorted(set(re.findall(r"^\s*(?:bf_status|void|const char\*)\s+(bf_\w+)\s*\(", src, re.M)))
+    return sorted(set(re.findall(r"^\s*(?:bf_status|void|int32_t|const char\*)\s+(bf_\w+)\s*\(", src, re.M)))
 
 
 def test_library_exports_every_declared_symbol():
@@ -339,3 +339,20 @@ def test_check_range_validation():
     assert L.bf_check_range(FAKE, 0, 8, 255.0, FAKE2, None) == 1      # empty image
     assert L.bf_check_range(FAKE, 8, 8, 0.0, FAKE2, None) == 1        # T not positive
     assert L.bf_check_range(FAKE, 8, 8, float("inf"), FAKE2, None) == 1
+
+
+def test_batch_api_validation():
+    """The batch entry points reject missing plans, empty descriptor lists and
+    unknown paths or stages before touching the device."""
+    L = nat.lib()
+    h = ctypes.c_void_p()
+    desc = (nat.ImageDesc * 1)()
+    assert L.bf_batch_plan_create_ex(None, 1, 0, ctypes.byref(h)) == 1
+    assert L.bf_batch_plan_create_ex(desc, 0, 0, ctypes.byref(h)) == 1
+    assert L.bf_batch_plan_create_ex(desc, 1, 3, ctypes.byref(h)) == 1
+    assert L.bf_batch_plan_create_ex(desc, 1, 0, None) == 1
+    assert L.bf_batch_plan_path(None) == -1
+    assert L.bf_batch_launch_stage(None, 0, None) == 1
+    assert L.bf_batch_launch(None, None) == 1
+    assert L.bf_batch_check(None) == 1
+    L.bf_batch_plan_destroy(None)
