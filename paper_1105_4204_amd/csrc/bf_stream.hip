@@ -57,6 +57,7 @@ constexpr int kSmMaxGroups = 64;      // pair groups per chunk
 constexpr int kSmMaxChunk = 256;      // pairs per chunk
 constexpr int kSmLineMax = 81;        // row pass: samples per lane at most (odd)
 constexpr int kSmSegMax = 2048;       // column pass: rows per segment at most
+constexpr int kSmPhaseSync = 8;       // row pass: pairs between direct phase evaluations
 enum SmMode { kSmFwd = 0, kSmBwd = 1 };
 
 // Cody-Waite split of pi/2: two 12-bit parts (exact products with |k| < 2^12)
@@ -83,6 +84,18 @@ __device__ __forceinline__ void cis_wide(float mh, float ml, float g, float& c, 
     s = q == 0 ? sx : q == 1 ? cx : q == 2 ? -sx : -cx;
 }
 
+// Image pointers read from device memory (the batch kernels' per-image
+// arguments) are generic to the compiler, which then emits flat accesses that
+// it can only wait for all at once; these casts make them global.
+template <typename T>
+__device__ __forceinline__ const __attribute__((address_space(1))) T* gload_ptr(const T* p) {
+    return (const __attribute__((address_space(1))) T*)p;
+}
+template <typename T>
+__device__ __forceinline__ __attribute__((address_space(1))) T* gstore_ptr(T* p) {
+    return (__attribute__((address_space(1))) T*)p;
+}
+
 struct StrmVArgs {
     const float* f;
     const float* ab;        // adjoint: A and B planes (2 H W)
@@ -99,22 +112,11 @@ struct StrmVArgs {
     float mh[kSmMaxGroups], ml[kSmMaxGroups];   // m a of each group's first pair, hi + lo
 };
 
-// The four channels of a pair at one pixel: forward C, gC, S, gS (g = f -
-// T/2); adjoint A C, B C, A S, B S.
-template <int MODE>
-__device__ __forceinline__ void channels(float zr, float zi, float g, float av, float bv,
-                                         float (&c)[4]) {
-    if (MODE == kSmFwd) {
-        c[0] = zr;
-        c[1] = g * zr;
-        c[2] = zi;
-        c[3] = g * zi;
-    } else {
-        c[0] = av * zr;
-        c[1] = bv * zr;
-        c[2] = av * zi;
-        c[3] = bv * zi;
-    }
+// Z <- Z U, complex, in FP64 (the next pair's phase).
+__device__ __forceinline__ void rotate(double& zr, double& zi, double ur, double ui) {
+    const double nr = fma(zr, ur, -zi * ui);
+    zi = fma(zr, ui, zi * ur);
+    zr = nr;
 }
 
 // The integrator weights of a segment start, wtab[k][s] for k < kinit:
@@ -168,6 +170,9 @@ __device__ __forceinline__ void strm_v_body(const StrmVArgs& a, int gw, const do
     const int q0 = pg * G;
     const int nq = min(G, a.npairs - q0);
     const size_t HW = (size_t)H * a.W;
+    const auto* F = gload_ptr(a.f);
+    const auto* AB = gload_ptr(a.ab);
+    auto* VP = gstore_ptr(a.vp);
     double I[G][4][NB];
 #pragma unroll
     for (int q = 0; q < G; ++q)
@@ -180,14 +185,14 @@ __device__ __forceinline__ void strm_v_body(const StrmVArgs& a, int gw, const do
     {
         const int kb = max(0, t0 - H), ke = min(a.kinit - 1, t0 - 1);
         size_t o = (size_t)min(max(t0 - 1 - kb, 0), H - 1) * a.W + x;
-        float gpre = a.f[o], apre = BWD ? a.ab[o] : 0.0f, bpre = BWD ? a.ab[HW + o] : 0.0f;
+        float gpre = F[o], apre = BWD ? AB[o] : 0.0f, bpre = BWD ? AB[HW + o] : 0.0f;
         for (int k = kb; k <= ke; ++k) {
             const float g = gpre - a.center, av = apre, bv = bpre;
             o = (size_t)max(t0 - 2 - k, 0) * a.W + x;
-            gpre = a.f[o];
+            gpre = F[o];
             if (BWD) {
-                apre = a.ab[o];
-                bpre = a.ab[HW + o];
+                apre = AB[o];
+                bpre = AB[HW + o];
             }
             float ur, ui, zr, zi;
             cis_small(a.two_alpha * g, ur, ui);
@@ -195,20 +200,17 @@ __device__ __forceinline__ void strm_v_body(const StrmVArgs& a, int gw, const do
             double w[NB];
 #pragma unroll
             for (int s = 0; s < NB; ++s) w[s] = wtab[k * NB + s];
+            const double v0 = BWD ? (double)av : 1.0, v1 = BWD ? (double)bv : (double)g;
+            const double Ur = ur, Ui = ui;
+            double Zr = zr, Zi = zi;
 #pragma unroll
             for (int q = 0; q < G; ++q) {
-                float c[4];
-                channels<MODE>(zr, zi, g, av, bv, c);
+                const double c[4] = {v0 * Zr, v1 * Zr, v0 * Zi, v1 * Zi};
 #pragma unroll
                 for (int ch = 0; ch < 4; ++ch)
 #pragma unroll
-                    for (int s = 0; s < NB; ++s)
-                        I[q][ch][s] = fma(w[s], (double)c[ch], I[q][ch][s]);
-                if (q + 1 < G) {
-                    const float nr = zr * ur - zi * ui;
-                    zi = zr * ui + zi * ur;
-                    zr = nr;
-                }
+                    for (int s = 0; s < NB; ++s) I[q][ch][s] = fma(w[s], c[ch], I[q][ch][s]);
+                if (q + 1 < G) rotate(Zr, Zi, Ur, Ui);
             }
         }
     }
@@ -218,10 +220,10 @@ __device__ __forceinline__ void strm_v_body(const StrmVArgs& a, int gw, const do
 #pragma unroll
     for (int j = 0; j < NT; ++j) {
         const size_t o = (size_t)min(max(t0 - a.toff[j], 0), H - 1) * a.W;
-        gnext[j] = (a.f + o)[x];
+        gnext[j] = (F + o)[x];
         if (BWD) {
-            anext[j] = (a.ab + o)[x];
-            bnext[j] = (a.ab + HW + o)[x];
+            anext[j] = (AB + o)[x];
+            bnext[j] = (AB + HW + o)[x];
         }
     }
     for (int t = t0; t < te; ++t) {
@@ -238,13 +240,16 @@ __device__ __forceinline__ void strm_v_body(const StrmVArgs& a, int gw, const do
 #pragma unroll
         for (int j = 0; j < NT; ++j) {
             const size_t o = (size_t)min(max(t + 1 - a.toff[j], 0), H - 1) * a.W;
-            gnext[j] = (a.f + o)[x];
+            gnext[j] = (F + o)[x];
             if (BWD) {
-                anext[j] = (a.ab + o)[x];
-                bnext[j] = (a.ab + HW + o)[x];
+                anext[j] = (AB + o)[x];
+                bnext[j] = (AB + HW + o)[x];
             }
         }
-        // d = sum_j c_j x[t - o_j], the float samples summed in FP64
+        // d = sum_j c_j x[t - o_j] in FP64: the channels of a sample are
+        // v0 Z and v1 Z (forward v = (1, g), adjoint v = (A, B)) with Z the
+        // pair's phase carried in FP64 from the group's first pair; c_j v
+        // is exact, so each tap adds the sample's exact products
         double d[G][4];
 #pragma unroll
         for (int q = 0; q < G; ++q)
@@ -259,21 +264,18 @@ __device__ __forceinline__ void strm_v_body(const StrmVArgs& a, int gw, const do
                 float ur, ui, zr, zi;
                 cis_small(a.two_alpha * g, ur, ui);
                 cis_wide(mh, ml, g, zr, zi);
-                zr = in ? zr : 0.0f;
-                zi = in ? zi : 0.0f;
-                const float av = BWD ? acur[j] : 0.0f, bv = BWD ? bcur[j] : 0.0f;
-                const double cj = (double)a.tcoef[j];
+                const double cj = in ? (double)a.tcoef[j] : 0.0;
+                const double w0 = BWD ? cj * (double)acur[j] : cj;
+                const double w1 = BWD ? cj * (double)bcur[j] : cj * (double)g;
+                const double Ur = ur, Ui = ui;
+                double Zr = zr, Zi = zi;
 #pragma unroll
                 for (int q = 0; q < G; ++q) {
-                    float c[4];
-                    channels<MODE>(zr, zi, g, av, bv, c);
-#pragma unroll
-                    for (int ch = 0; ch < 4; ++ch) d[q][ch] = fma(cj, (double)c[ch], d[q][ch]);
-                    if (q + 1 < G) {
-                        const float nr = zr * ur - zi * ui;
-                        zi = zr * ui + zi * ur;
-                        zr = nr;
-                    }
+                    d[q][0] = fma(w0, Zr, d[q][0]);
+                    d[q][1] = fma(w1, Zr, d[q][1]);
+                    d[q][2] = fma(w0, Zi, d[q][2]);
+                    d[q][3] = fma(w1, Zi, d[q][3]);
+                    if (q + 1 < G) rotate(Zr, Zi, Ur, Ui);
                 }
             }
         }
@@ -285,7 +287,7 @@ __device__ __forceinline__ void strm_v_body(const StrmVArgs& a, int gw, const do
 #pragma unroll
                 for (int s = 1; s < NB; ++s) I[q][k][s] += I[q][k][s - 1];
             }
-        float* dst = a.vp + (size_t)(t - a.R) * a.Wp + x;
+        auto* dst = VP + (size_t)(t - a.R) * a.Wp + x;
         const size_t plane = (size_t)H * a.Wp;
 #pragma unroll
         for (int q = 0; q < G; ++q) {
@@ -303,7 +305,8 @@ __global__ void __launch_bounds__(kSmThreads) bf_strm_v(const StrmVArgs a) {
     extern __shared__ double wtab[];   // [k][s]: integrator weights of the segment start
     strm_weights<NB>(a, wtab, threadIdx.x, kSmThreads);
     __syncthreads();
-    strm_v_body<NB, G, MODE>(a, blockIdx.x * (kSmThreads / 64) + (threadIdx.x >> 6), wtab);
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    strm_v_body<NB, G, MODE>(a, blockIdx.x * (kSmThreads / 64) + wave, wtab);
 }
 
 // A = G / eta and B = A (out - T/2), the adjoint's per-pixel weights.
@@ -385,17 +388,24 @@ __device__ __forceinline__ void strm_h_body(const StrmHArgs& a, int y) {
     float* linef = reinterpret_cast<float*>(line);
     const int nx = (W + kSmThreads - 1) / kSmThreads;
 
-    // demodulation state of pixels x = t + 256 i: g and the sums (the phase
-    // of each pair is evaluated directly, so none is carried)
+    // demodulation state of pixels x = t + 256 i: g and the sums; on short
+    // lines also the phase of the current pair and the step to the next
+    // (exp(j 2 a g)), evaluated directly every kSmPhaseSync pairs and
+    // rotated in between; on long lines (registers) every pair directly
+    constexpr bool CARRY = NX <= 9;
+    constexpr int NP = CARRY ? NX : 1;
     float gx[NX], acc[NACC][NX];
-    const float* frow = a.f + (size_t)y * W;
+    float pc[NP], ps[NP], ur[NP], ui[NP];
+    const auto* frow = gload_ptr(a.f) + (size_t)y * W;
+    const auto* PART = gload_ptr(a.part);
 #pragma unroll
     for (int i = 0; i < NX; ++i) {
         const int x = min(t + i * kSmThreads, W - 1);
         gx[i] = frow[x] - a.center;
+        if (CARRY) cis_small(2.0f * a.alpha * gx[i], ur[i % NP], ui[i % NP]);
 #pragma unroll
         for (int c = 0; c < NACC; ++c)
-            acc[c][i] = a.first ? 0.0f : a.part[c * HW + (size_t)y * W + x];
+            acc[c][i] = a.first ? 0.0f : PART[c * HW + (size_t)y * W + x];
     }
     __syncthreads();
 
@@ -496,6 +506,7 @@ __device__ __forceinline__ void strm_h_body(const StrmHArgs& a, int y) {
         const float* l1 = l0 + a.bufsz;
         const float* l2 = l1 + a.bufsz;
         const float* l3 = l2 + a.bufsz;
+        const bool direct = !CARRY || qq % kSmPhaseSync == 0;   // uniform
         // every pixel slot (slots past W read inside the lines and are never stored)
 #pragma unroll
         for (int i = 0; i < NX; ++i) {
@@ -504,10 +515,24 @@ __device__ __forceinline__ void strm_h_body(const StrmHArgs& a, int y) {
             if (centre) {   // m = 0: C = 1, S = 0
                 acc[0][i] = fmaf(c, D0, acc[0][i]);
                 if (!BWD) acc[1][i] = fmaf(c, l1[x], acc[1][i]);
+                if (CARRY) {
+                    pc[i % NP] = 1.0f;
+                    ps[i % NP] = 0.0f;
+                }
             } else {
                 const float D1 = l1[x], D2 = l2[x], D3 = l3[x];
                 float C, S;
-                cis_wide(mh, ml, gx[i], C, S);
+                if (direct) {
+                    cis_wide(mh, ml, gx[i], C, S);
+                } else {
+                    const int k = i % NP;
+                    C = pc[k] * ur[k] - ps[k] * ui[k];
+                    S = pc[k] * ui[k] + ps[k] * ur[k];
+                }
+                if (CARRY) {
+                    pc[i % NP] = C;
+                    ps[i % NP] = S;
+                }
                 if (!BWD) {
                     acc[0][i] = fmaf(c * C, D0, fmaf(c * S, D2, acc[0][i]));
                     acc[1][i] = fmaf(c * C, D1, fmaf(c * S, D3, acc[1][i]));
@@ -528,6 +553,12 @@ __device__ __forceinline__ void strm_h_body(const StrmHArgs& a, int y) {
         }
         __syncthreads();
     }
+    auto* part = gstore_ptr(a.part);
+    auto* out = gstore_ptr(a.out);
+    auto* eta = gstore_ptr(a.eta);
+    auto* aux = gstore_ptr(a.aux);
+    const auto* ab = gload_ptr(a.ab);
+    const auto* faux = gload_ptr(a.faux);
 #pragma unroll
     for (int i = 0; i < NX; ++i) {
         const int x = t + i * kSmThreads;
@@ -535,18 +566,18 @@ __device__ __forceinline__ void strm_h_body(const StrmHArgs& a, int y) {
             const size_t o = (size_t)y * W + x;
             if (!a.last) {
 #pragma unroll
-                for (int c = 0; c < NACC; ++c) a.part[c * HW + o] = acc[c][i];
+                for (int c = 0; c < NACC; ++c) part[c * HW + o] = acc[c][i];
             } else if (!BWD) {
-                a.out[o] = (float)((double)a.center + (double)acc[1][i] / (double)acc[0][i]);
-                if (a.eta) a.eta[o] = acc[0][i];
+                out[o] = (float)((double)a.center + (double)acc[1][i] / (double)acc[0][i]);
+                if (a.eta) eta[o] = acc[0][i];
                 if (AUX) {
-                    a.aux[o] = acc[2][i];
-                    a.aux[HW + o] = acc[3][i];
+                    aux[o] = acc[2][i];
+                    aux[HW + o] = acc[3][i];
                 }
             } else {
-                const float A = a.ab[o], B = a.ab[HW + o];
-                const float P = a.faux[o], Q = a.faux[HW + o];
-                a.out[o] = fmaf(a.alpha, A * P - B * Q, acc[0][i]);
+                const float A = ab[o], B = ab[HW + o];
+                const float P = faux[o], Q = faux[HW + o];
+                out[o] = fmaf(a.alpha, A * P - B * Q, acc[0][i]);
             }
         }
     }
@@ -568,10 +599,11 @@ struct SbTask {
 // read from device memory; the segment-start weights go to a wave-private
 // slice of LDS of kinit_max * NB doubles).
 template <int NB, int G, int MODE>
-__global__ void __launch_bounds__(kSmThreads) bf_sb_v(const StrmVArgs* args, const SbTask* tasks,
+__global__ void __launch_bounds__(kSmThreads) bf_sb_v(const StrmVArgs* __restrict__ args,
+                                                      const SbTask* __restrict__ tasks,
                                                       int ntasks, int wslice) {
     extern __shared__ double wt[];
-    const int wave = threadIdx.x >> 6;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int gw = blockIdx.x * (kSmThreads / 64) + wave;
     if (gw >= ntasks) return;   // no block barriers in this kernel
     const int img = __builtin_amdgcn_readfirstlane(tasks[gw].img);
@@ -586,7 +618,8 @@ __global__ void __launch_bounds__(kSmThreads) bf_sb_v(const StrmVArgs* args, con
 // Row pass over a batch: workgroup b filters row tasks[b].unit of image
 // tasks[b].img (all images of one launch share the line length E).
 template <int E, int MODE, bool AUX>
-__global__ void __launch_bounds__(kSmThreads) bf_sb_h(const StrmHArgs* args, const SbTask* tasks) {
+__global__ void __launch_bounds__(kSmThreads) bf_sb_h(const StrmHArgs* __restrict__ args,
+                                                      const SbTask* __restrict__ tasks) {
     const int img = __builtin_amdgcn_readfirstlane(tasks[blockIdx.x].img);
     const int y = __builtin_amdgcn_readfirstlane(tasks[blockIdx.x].unit);
     strm_h_body<E, MODE, AUX>(args[img], y);
