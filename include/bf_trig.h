@@ -82,15 +82,16 @@ typedef struct {
     float* aux_out;      /* forward only: optional 2*H*W device buffer for the
                             two auxiliary sums the backward needs (see
                             bf_trig_backward); NULL = not computed */
-    void* workspace;     /* forward only: device scratch of the streamed passes
-                            (see bf_trig_workspace_bytes), 256-byte aligned, not
-                            overlapping the images; NULL = the library's own */
+    void* workspace;     /* device scratch of the streamed passes (forward and
+                            backward; see bf_trig_workspace_bytes), 256-byte
+                            aligned, not overlapping the images; NULL = the
+                            library's own */
     int64_t workspace_bytes;
     float trunc_tol;     /* 0 = every cosine pair; > 0 = drop the outer pairs
                             while the bound of bf_range_truncate stays <= this
                             many gray levels (forward and backward must agree) */
-    int32_t path;        /* forward only: BF_PATH_AUTO (0), BF_PATH_FUSED or
-                            BF_PATH_STREAMED */
+    int32_t path;        /* forward and backward: BF_PATH_AUTO (0),
+                            BF_PATH_FUSED or BF_PATH_STREAMED */
 } bf_opts;
 
 /* Algorithm 1 steps 1-2: N = ceil((gamma sigma_r)^-2), gamma = pi/(2T).
@@ -122,9 +123,9 @@ bf_status bf_range_truncate(int32_t N, double T, const bf_spatial_spec* spatial_
  * the narrower ones first, ties to the narrower. */
 bf_status bf_spatial_gaussian(double sigma_s, int32_t n_boxes, bf_spatial_spec* out);
 
-/* Device workspace of the forward's streamed passes for image size H x W and
- * this spatial kernel: 0 when the library evaluates this geometry with the
- * fused tile kernel (no workspace), otherwise the recommended size,
+/* Device workspace of the streamed passes for image size H x W and this
+ * spatial kernel: 0 when the library evaluates this geometry with the fused
+ * tile kernel (no workspace), otherwise the recommended size,
  * 16 P H Wp + 24 H W bytes for P = 16 cosine pairs, Wp = W rounded up to a
  * multiple of 64 (of 4 for W < 64).  The streamed passes (Sec. 2.1, eq. (final-form)) filter
  * the four channels of each pair along whole columns and then whole rows;
@@ -132,9 +133,11 @@ bf_status bf_spatial_gaussian(double sigma_s, int32_t n_boxes, bf_spatial_spec* 
  * between the two passes, the partial sums between chunks (and the adjoint's
  * per-pixel weights).  Any size from one pair's (P = 1) up works: smaller
  * workspaces only mean more chunks.
- * They run where the fused kernel cannot hold the kernel width (a radius
- * above 31 or R > 63) or where its tiles, shrunken by the halo, cost more.
- * BF_EUNSUPPORTED when neither evaluation handles the kernel. */
+ * The library's choice (BF_PATH_AUTO) is the streamed passes wherever they
+ * apply (W + 2R <= 5184 and a kernel mass prod(2 radius + 1) below 2^31):
+ * they are faster than the fused tiles at every size measured and their cost
+ * does not grow with the radii.  The fused kernel takes the other images its
+ * limits allow.  BF_EUNSUPPORTED when neither evaluation handles the kernel. */
 bf_status bf_trig_workspace_bytes(int64_t H, int64_t W, const bf_spatial_spec* spatial_spec,
                                   int64_t* bytes_out);
 
@@ -149,15 +152,16 @@ bf_status bf_trig_workspace_bytes_ex(int64_t H, int64_t W, float T, float sigma_
  * f: H*W input; out: H*W output (must not overlap f).  sigma_r > 0, T > 0.
  * Equivalent to bf_trig_forward_ex with opts == NULL: every kernel width the
  * limits above allow runs; where the streamed passes run, the library uses a
- * workspace of its own (bf_trig_workspace_bytes with P = min(pairs, 16)),
- * allocated on first need per device and kept until the process ends, so
- * such a call may not be captured (BF_ECAPTURE) and may return BF_ENOMEM.
- * Calls that share it are ordered on the device, whatever their streams.
+ * workspace of its own (the size bf_trig_workspace_bytes_ex recommends: every
+ * pair in one chunk up to 4 GiB of planes), allocated on first need per
+ * device and kept until the process ends, so such a call may not be captured
+ * (BF_ECAPTURE) and may return BF_ENOMEM.  Calls that share it are ordered on
+ * the device, whatever their streams.
  *
- * bf_trig_forward_ex: opts->aux_out (the adjoint's sums) forces the fused
- * kernel (BF_EUNSUPPORTED for kernels it cannot hold), as does a tile
- * override; opts->path forces either evaluation; a caller workspace smaller
- * than one pair's returns BF_EINVAL. */
+ * bf_trig_forward_ex: opts->path forces either evaluation, and a tile
+ * override forces the fused kernel; opts->eta_out and opts->aux_out (the
+ * adjoint's sums) work on both; a caller workspace smaller than one pair's
+ * returns BF_EINVAL. */
 bf_status bf_trig_forward(const float* f, int64_t H, int64_t W, float T, float sigma_r,
                           const bf_spatial_spec* spatial_spec, float* out);
 
@@ -189,13 +193,20 @@ bf_status bf_trig_forward_noalloc(const float* f, int64_t H, int64_t W, float T,
  * outputs for the same f and parameters (opts->N must match): aux holds the
  * planes P = sum_m c_m m (C_m F[g S_m] - S_m F[g C_m]) and
  * Q = sum_m c_m m (C_m F[S_m] - S_m F[C_m]) (g = f - T/2, C_m + j S_m =
- * exp(j m alpha g)), which the forward writes to opts->aux_out.  f, out, eta,
- * grad_out and grad_f are H*W, aux 2*H*W; grad_f must not overlap the
+ * exp(j m alpha g)), which the forward writes to opts->aux_out.  aux may be
+ * NULL: the library then recomputes P and Q with a forward of its own (one
+ * forward more, written into the library's workspace, allocated on first
+ * need and kept; not allowed during stream capture: BF_ECAPTURE).  f, out,
+ * eta, grad_out and grad_f are H*W, aux 2*H*W; grad_f must not overlap the
  * inputs.  opts->aux_out is ignored.  When W and the kernel half-width R are
  * multiples of 4, f is 16-byte aligned and 4 H W < 2^31, the adjoint reads g
  * from global memory and fits tiles up to 64 x 64 (widths a multiple of 4);
  * otherwise it stages g in LDS and fits smaller tiles.  An explicit
- * opts->tile_h x tile_w that fits neither returns BF_EINVAL. */
+ * opts->tile_h x tile_w that fits neither returns BF_EINVAL.  Path choice,
+ * opts->path and the workspace are as for the forward: by default the
+ * streamed passes wherever they apply, which filter the four channels A C,
+ * B C, A S, B S of each pair (A = grad_out / eta, B = A (out - T/2)) and
+ * demodulate with the adjoint's coefficients. */
 bf_status bf_trig_backward(const float* f, const float* out, const float* eta,
                            const float* aux, const float* grad_out, int64_t H, int64_t W,
                            float T, float sigma_r, const bf_spatial_spec* spatial_spec,
@@ -265,13 +276,18 @@ bf_status bf_check_range(const float* f, int64_t H, int64_t W, float T, uint32_t
  * image, out = BF(f), the SSD loss sum((out - target)^2) (into loss[i] if loss
  * is non-NULL) and grad_f = d loss / d f; eta must then be non-NULL.  With
  * grad_f NULL only the forward runs.  bf_batch_launch enqueues the whole batch
- * as one persistent work-queue kernel (plus a tiny counter-reset kernel) on
- * stream: forward tiles first, longest first, then the per-image loss
+ * on stream, in one of two evaluations (bf_batch_plan_create_ex): the
+ * streamed passes over all images (a short fixed sequence of kernels), or one
+ * persistent work-queue kernel of fused tiles (plus a tiny counter-reset
+ * kernel): forward tiles first, longest first, then the per-image loss
  * reductions, then the adjoint tiles, each of which waits (bounded) until all
  * forward tiles of its image are done.  It allocates and synchronises
  * nothing, so it may be captured into a hipGraph and replayed.
  * bf_batch_check synchronises the device and reports BF_EDEVICE if a wait in
- * the last launch hit its bound (the results are then invalid). */
+ * the last launch hit its bound (the results are then invalid).  Tile shapes
+ * of the fused evaluation come from the descriptors; the timing-based tile
+ * tuner that fills them (with a per-device cache file) is part of the Python
+ * layer only, not of this ABI. */
 typedef struct {
     int64_t H, W;
     float T, sigma_r;

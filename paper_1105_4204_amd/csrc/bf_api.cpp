@@ -368,10 +368,15 @@ bf_status bf_yvv_forward(const float* f, int64_t H, int64_t W, float T, float si
                       opts ? (hipStream_t)opts->stream : nullptr);
 }
 
-bf_status bf_trig_backward(const float* f, const float* out, const float* eta,
-                           const float* aux, const float* grad_out, int64_t H, int64_t W,
-                           float T, float sigma_r, const bf_spatial_spec* spatial_spec,
-                           float* grad_f, const bf_opts* opts) {
+}  // extern "C"
+
+namespace {
+
+// The adjoint given the forward's sums P and Q (aux).
+bf_status backward_with_sums(const float* f, const float* out, const float* eta,
+                             const float* aux, const float* grad_out, int64_t H, int64_t W,
+                             float T, float sigma_r, const bf_spatial_spec* spatial_spec,
+                             float* grad_f, const bf_opts* opts) {
     Common c;
     bf_status st = prepare(f, H, W, T, sigma_r, spatial_spec, opts, &c);
     if (st != BF_OK) return st;
@@ -418,6 +423,69 @@ bf_status bf_trig_backward(const float* f, const float* out, const float* eta,
     io.gout = grad_out;
     io.gf = grad_f;
     return run_stream(kStreamBwd, io, H, W, c, opts, bytes);
+}
+
+}  // namespace
+
+extern "C" {
+
+bf_status bf_trig_backward(const float* f, const float* out, const float* eta,
+                           const float* aux, const float* grad_out, int64_t H, int64_t W,
+                           float T, float sigma_r, const bf_spatial_spec* spatial_spec,
+                           float* grad_f, const bf_opts* opts) {
+    if (aux)
+        return backward_with_sums(f, out, eta, aux, grad_out, H, W, T, sigma_r, spatial_spec,
+                                  grad_f, opts);
+    // The caller kept only out and eta: P and Q come from a forward of the
+    // library's own (they depend on f and the parameters alone), written with
+    // a scratch copy of out into the library workspace, followed by the
+    // streamed passes' planes unless the caller brings a workspace.
+    Common c;
+    bf_status st = prepare(f, H, W, T, sigma_r, spatial_spec, opts, &c);
+    if (st != BF_OK) return st;
+    const void* bufs[4] = {out, eta, grad_out, grad_f};
+    const char* names[4] = {"out", "eta", "grad_out", "grad_f"};
+    for (int i = 0; i < 4; ++i) {
+        st = check_image(bufs[i], H, W, names[i]);
+        if (st != BF_OK) return st;
+    }
+    const int64_t bytes = H * W * (int64_t)sizeof(float);
+    const void* ins[4] = {f, out, eta, grad_out};
+    for (int i = 0; i < 4; ++i) {
+        if (overlaps(ins[i], bytes, grad_f, bytes)) {
+            set_error("grad_f must not overlap the inputs");
+            return BF_EINVAL;
+        }
+    }
+    const int path = opts ? opts->path : BF_PATH_AUTO;
+    if (path != BF_PATH_AUTO && path != BF_PATH_FUSED && path != BF_PATH_STREAMED) {
+        set_error("opts->path=%d is not one of BF_PATH_AUTO, BF_PATH_FUSED, BF_PATH_STREAMED",
+                  path);
+        return BF_EINVAL;
+    }
+    const size_t plane = (size_t)bytes;
+    const size_t sums = (3 * plane + 255) & ~(size_t)255;   // P, Q, scratch out
+    const bool own_planes = !(opts && opts->workspace) && stream_supported(W, c.sp);
+    const size_t planes = own_planes ? stream_default_workspace(H, W, c.rp.npairs) : 0;
+    void* base = nullptr;
+    st = library_workspace(sums + planes, c.stream, &base);
+    if (st != BF_OK) return st;
+    float* pq = static_cast<float*>(base);
+    float* out2 = pq + 2 * (size_t)H * (size_t)W;
+    bf_opts o = {};
+    if (opts) o = *opts;
+    o.eta_out = nullptr;
+    o.aux_out = pq;
+    if (own_planes) {
+        o.workspace = static_cast<unsigned char*>(base) + sums;
+        o.workspace_bytes = (int64_t)planes;
+    }
+    st = bf_trig_forward_ex(f, H, W, T, sigma_r, spatial_spec, out2, &o);
+    if (st == BF_OK)
+        st = backward_with_sums(f, out, eta, pq, grad_out, H, W, T, sigma_r, spatial_spec,
+                                grad_f, &o);
+    const bf_status st2 = library_workspace_done(c.stream);   // releases the lock
+    return st == BF_OK ? st2 : st;
 }
 
 }  // extern "C"

@@ -8,8 +8,10 @@
 //     b * x = S^nb d,   d[t] = sum_{A subset of boxes} (-1)^|A| x[t - sum_{k in A} L_k],
 // with S the running sum (integrator).  A lane owns one image column and G
 // consecutive cosine pairs and walks down the column: at each row it
-// recomputes the channels at the 2^nb tap rows from f (phase, channel), forms
-// d from the float samples in FP64 and runs the nb integrators in FP64.  No
+// recomputes the channels at the 2^nb tap rows from f (the first pair's phase
+// directly, the others by an FP64 rotation), forms d with FP64 fused
+// multiply-adds (tap coefficient times g, A or B exact) and runs the nb
+// integrators in FP64.  No
 // history of the filtered signal is kept, and nothing depends on the radii
 // but the tap offsets.  Integrators never damp their rounding errors; in FP64
 // the drift stays far below the float32 resolution of the outputs over
@@ -30,9 +32,10 @@
 // modulo 2^32; the window sums do not).  Between stages the sums are shifted
 // right so that the next window sum fits again.  The four filtered channels
 // then meet in LDS and every thread demodulates its pixels with C and S
-// evaluated directly for each pair, accumulating den and num (and, for the
-// adjoint's sake, P and Q) across the pairs; the last pair chunk divides in
-// FP64.
+// (evaluated directly every kSmPhaseSync pairs and rotated in between where
+// the line is short enough to keep the phases in registers, else directly for
+// each pair), accumulating den and num (and, for the adjoint's sake, P and Q)
+// across the pairs; the last pair chunk divides in FP64.
 //
 // The adjoint (see the fused kernel's header for its formula) runs the same
 // two passes on the channels A C, B C, A S, B S (A = G / eta, B = A (out -

@@ -150,12 +150,15 @@ def trig_backward(f, out, eta, aux, grad_out, T: float, sigma_r: float, radii, N
                   tile=None, trunc_tol: float = 0.0, path: int = nat.PATH_AUTO,
                   workspace: torch.Tensor | None = None):
     """grad_f = J^T grad_out for the forward that produced (out, eta, aux):
-    the fused adjoint tiles or the streamed passes, as for the forward."""
+    the fused adjoint tiles or the streamed passes, as for the forward.  With
+    aux None the library recomputes the forward's sums itself (one more
+    forward, in its own workspace)."""
     for x, n in ((f, "f"), (out, "out"), (eta, "eta"), (grad_out, "grad_out")):
         _check_img(x, n)
     H, W = f.shape
-    if (not isinstance(aux, torch.Tensor) or not aux.is_cuda or aux.dtype != torch.float32
-            or tuple(aux.shape) != (2, H, W) or not aux.is_contiguous()):
+    if aux is not None and (not isinstance(aux, torch.Tensor) or not aux.is_cuda
+                            or aux.dtype != torch.float32 or tuple(aux.shape) != (2, H, W)
+                            or not aux.is_contiguous()):
         raise TypeError("aux must be the contiguous 2 x H x W float32 tensor of the forward")
     gf = torch.empty_like(f)
     spec = nat.SpatialSpec.of(radii)

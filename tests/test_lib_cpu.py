@@ -126,8 +126,15 @@ def test_backward_and_direct_validation():
                               FAKE2, ctypes.byref(o)) == 1
     assert L.bf_trig_backward(FAKE, FAKE2, FAKE, FAKE3, FAKE, 8, 8, 255.0, 30.0, ctypes.byref(s),
                               FAKE2, ctypes.byref(o)) == 1   # grad_f aliases out
+    # aux may be NULL (the library recomputes the sums), but the arguments
+    # are still checked before anything is allocated or enqueued
+    assert L.bf_trig_backward(FAKE, FAKE2, FAKE, None, FAKE, 8, 8, 255.0, 30.0, ctypes.byref(s),
+                              FAKE2, ctypes.byref(o)) == 1   # grad_f aliases out
+    assert L.bf_trig_backward(FAKE, FAKE3, FAKE, None, None, 8, 8, 255.0, 30.0, ctypes.byref(s),
+                              FAKE2, ctypes.byref(o)) == 1   # grad_out missing
+    bad = nat.make_opts(None, 0, path=7)
     assert L.bf_trig_backward(FAKE, FAKE3, FAKE, None, FAKE, 8, 8, 255.0, 30.0, ctypes.byref(s),
-                              FAKE2, ctypes.byref(o)) == 1   # aux missing
+                              FAKE2, ctypes.byref(bad)) == 1   # unknown path
     assert L.bf_trig_backward(FAKE, FAKE3, FAKE, ctypes.c_void_p(0x20000000 - 256), FAKE, 8, 8, 255.0, 30.0,
                               ctypes.byref(s), FAKE2, ctypes.byref(o)) == 1   # aux runs into grad_f
     assert L.bf_direct_forward(FAKE, 8, 8, 255.0, -2.0, ctypes.byref(s), FAKE2,
