@@ -348,21 +348,41 @@ struct StrmHArgs {
     float mh[kSmMaxChunk], ml[kSmMaxChunk];   // m a of each pair, hi + lo
 };
 
-// Exclusive prefix sum of v over the 64 lanes of a wave (modulo 2^32).
-__device__ __forceinline__ uint32_t wave_excl_scan(uint32_t v, int lane) {
-    uint32_t incl = v;
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-        const uint32_t n = (uint32_t)__shfl_up((int)incl, o, 64);
-        incl += lane >= o ? n : 0u;
-    }
-    return incl - v;
+// Lane moves within the wave through DPP (no LDS round trip): row_shr:n
+// (0x110 + n) takes the value n lanes below within each row of 16 lanes,
+// row_bcast:15 (0x142) the last lane of the row below, row_bcast:31 (0x143)
+// lane 31; lanes without a source, and rows outside ROWS, read 0.
+template <int CTRL, int ROWS>
+__device__ __forceinline__ uint32_t dpp_move(uint32_t v) {
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, CTRL, ROWS, 0xf, false);
 }
 
-__device__ __forceinline__ float wave_max(float v) {
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) v = fmaxf(v, __shfl_xor(v, o, 64));
+// Inclusive prefix over the 64 lanes of a wave of the values combined by op
+// (addition modulo 2^32, or the maximum of non-negative floats' bits): a
+// scan within each row of 16 lanes, then row 0's total into row 1 and row
+// 2's into row 3, then rows 0-1's total into rows 2 and 3.
+template <typename Op>
+__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v, Op op) {
+    v = op(v, dpp_move<0x111, 0xf>(v));
+    v = op(v, dpp_move<0x112, 0xf>(v));
+    v = op(v, dpp_move<0x114, 0xf>(v));
+    v = op(v, dpp_move<0x118, 0xf>(v));
+    v = op(v, dpp_move<0x142, 0xa>(v));
+    v = op(v, dpp_move<0x143, 0xc>(v));
     return v;
+}
+
+// Exclusive prefix sum of v over the 64 lanes of a wave (modulo 2^32).
+__device__ __forceinline__ uint32_t wave_excl_scan(uint32_t v, int lane) {
+    (void)lane;
+    return wave_incl_scan(v, [](uint32_t a, uint32_t b) { return a + b; }) - v;
+}
+
+// The largest of v >= 0 over the wave (non-negative floats order as their bits).
+__device__ __forceinline__ float wave_max(float v) {
+    const uint32_t m = wave_incl_scan(__float_as_uint(v),
+                                      [](uint32_t a, uint32_t b) { return a > b ? a : b; });
+    return __uint_as_float((uint32_t)__builtin_amdgcn_readlane((int)m, 63));
 }
 
 __device__ __forceinline__ void wave_sync_lds() {
