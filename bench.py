@@ -153,7 +153,8 @@ def measured_traffic(kernel, workload):
     return None, None
 
 
-ROW_LINES = (9, 17, 25, 33, 37, 41, 45, 49, 57, 65, 69, 73, 81)
+ROW_LINES = (3, 5, 7, 9, 11, 13, 15, 17, 19, 21, 23, 25, 27, 29, 31, 33, 37, 41, 45, 49, 57, 65,
+             69, 73, 81)
 
 
 def line_lanes(W: int, R: int) -> int:

@@ -61,6 +61,7 @@ constexpr int kSmMaxChunk = 256;      // pairs per chunk
 constexpr int kSmLineMax = 81;        // row pass: samples per lane at most (odd)
 constexpr int kSmSegMax = 2048;       // column pass: rows per segment at most
 constexpr int kSmPhaseSync = 8;       // row pass: pairs between direct phase evaluations
+constexpr int kSmAhead = 1;           // column pass: rows of tap loads in flight
 enum SmMode { kSmFwd = 0, kSmBwd = 1 };
 
 // Cody-Waite split of pi/2: two 12-bit parts (exact products with |k| < 2^12)
@@ -99,9 +100,15 @@ __device__ __forceinline__ __attribute__((address_space(1))) T* gstore_ptr(T* p)
     return (__attribute__((address_space(1))) T*)p;
 }
 
+// The adjoint's per-pixel weights A = G / eta and B = A (out - T/2), stored
+// interleaved so that one 8-byte load brings both.
+struct __attribute__((aligned(8))) AbPair {
+    float a, b;
+};
+
 struct StrmVArgs {
     const float* f;
-    const float* ab;        // adjoint: A and B planes (2 H W)
+    const float* ab;        // adjoint: A and B, interleaved per pixel (2 H W)
     float* vp;              // planes [pair][4][H][Wp]
     int H, W, Wp;
     int ntaps;
@@ -174,7 +181,7 @@ __device__ __forceinline__ void strm_v_body(const StrmVArgs& a, int gw, const do
     const int nq = min(G, a.npairs - q0);
     const size_t HW = (size_t)H * a.W;
     const auto* F = gload_ptr(a.f);
-    const auto* AB = gload_ptr(a.ab);
+    const auto* AB = gload_ptr(reinterpret_cast<const AbPair*>(a.ab));
     auto* VP = gstore_ptr(a.vp);
     double I[G][4][NB];
 #pragma unroll
@@ -188,14 +195,14 @@ __device__ __forceinline__ void strm_v_body(const StrmVArgs& a, int gw, const do
     {
         const int kb = max(0, t0 - H), ke = min(a.kinit - 1, t0 - 1);
         size_t o = (size_t)min(max(t0 - 1 - kb, 0), H - 1) * a.W + x;
-        float gpre = F[o], apre = BWD ? AB[o] : 0.0f, bpre = BWD ? AB[HW + o] : 0.0f;
+        float gpre = F[o], apre = BWD ? AB[o].a : 0.0f, bpre = BWD ? AB[o].b : 0.0f;
         for (int k = kb; k <= ke; ++k) {
             const float g = gpre - a.center, av = apre, bv = bpre;
             o = (size_t)max(t0 - 2 - k, 0) * a.W + x;
             gpre = F[o];
             if (BWD) {
-                apre = AB[o];
-                bpre = AB[HW + o];
+                apre = AB[o].a;
+                bpre = AB[o].b;
             }
             float ur, ui, zr, zi;
             cis_small(a.two_alpha * g, ur, ui);
@@ -218,35 +225,49 @@ __device__ __forceinline__ void strm_v_body(const StrmVArgs& a, int gw, const do
         }
     }
 
-    // tap rows are wave-uniform: row base in SGPRs, the lane's column as offset
-    float gnext[NT], anext[NT], bnext[NT];
+    // tap rows are wave-uniform: row base in SGPRs, the lane's column as
+    // offset; the taps of the next kSmAhead rows are in flight (clamped,
+    // unconditional loads) while a row is computed
+    constexpr int PF = kSmAhead;
+    float gq[PF][NT], aq[PF][NT], bq[PF][NT];
 #pragma unroll
-    for (int j = 0; j < NT; ++j) {
-        const size_t o = (size_t)min(max(t0 - a.toff[j], 0), H - 1) * a.W;
-        gnext[j] = (F + o)[x];
-        if (BWD) {
-            anext[j] = (AB + o)[x];
-            bnext[j] = (AB + HW + o)[x];
+    for (int p = 0; p < PF; ++p)
+#pragma unroll
+        for (int j = 0; j < NT; ++j) {
+            const size_t o = (size_t)min(max(t0 + p - a.toff[j], 0), H - 1) * a.W;
+            gq[p][j] = (F + o)[x];
+            if (BWD) {
+                aq[p][j] = (AB + o)[x].a;
+                bq[p][j] = (AB + o)[x].b;
+            }
         }
-    }
     for (int t = t0; t < te; ++t) {
         float gcur[NT], acur[NT], bcur[NT];
 #pragma unroll
         for (int j = 0; j < NT; ++j) {
-            gcur[j] = gnext[j];
+            gcur[j] = gq[0][j];
             if (BWD) {
-                acur[j] = anext[j];
-                bcur[j] = bnext[j];
+                acur[j] = aq[0][j];
+                bcur[j] = bq[0][j];
             }
         }
-        // next step's taps: clamped unconditional loads, in flight during this step
+#pragma unroll
+        for (int p = 0; p + 1 < PF; ++p)
+#pragma unroll
+            for (int j = 0; j < NT; ++j) {
+                gq[p][j] = gq[p + 1][j];
+                if (BWD) {
+                    aq[p][j] = aq[p + 1][j];
+                    bq[p][j] = bq[p + 1][j];
+                }
+            }
 #pragma unroll
         for (int j = 0; j < NT; ++j) {
-            const size_t o = (size_t)min(max(t + 1 - a.toff[j], 0), H - 1) * a.W;
-            gnext[j] = (F + o)[x];
+            const size_t o = (size_t)min(max(t + PF - a.toff[j], 0), H - 1) * a.W;
+            gq[PF - 1][j] = (F + o)[x];
             if (BWD) {
-                anext[j] = (AB + o)[x];
-                bnext[j] = (AB + HW + o)[x];
+                aq[PF - 1][j] = (AB + o)[x].a;
+                bq[PF - 1][j] = (AB + o)[x].b;
             }
         }
         // d = sum_j c_j x[t - o_j] in FP64: the channels of a sample are
@@ -319,8 +340,8 @@ __global__ void __launch_bounds__(kSmThreads) bf_strm_ab(const float* gout, cons
     for (size_t i = (size_t)blockIdx.x * kSmThreads + threadIdx.x; i < n;
          i += (size_t)gridDim.x * kSmThreads) {
         const float A = gout[i] / feta[i];
-        ab[i] = A;
-        ab[n + i] = A * (fout[i] - center);
+        ab[2 * i] = A;
+        ab[2 * i + 1] = A * (fout[i] - center);
     }
 }
 
@@ -331,7 +352,7 @@ struct StrmHArgs {
     float* eta;             // forward: optional eta
     float* aux;             // forward: optional P and Q planes (2 H W)
     const float* faux;      // adjoint: P and Q of the forward
-    const float* ab;        // adjoint: A and B planes
+    const float* ab;        // adjoint: A and B, interleaved per pixel (2 H W)
     float* part;            // partial sums between chunks (den, num, P, Q; adjoint: one)
     int H, W, Wp;
     int R, nb;
@@ -580,7 +601,7 @@ __device__ __forceinline__ void strm_h_body(const StrmHArgs& a, int y) {
     auto* out = gstore_ptr(a.out);
     auto* eta = gstore_ptr(a.eta);
     auto* aux = gstore_ptr(a.aux);
-    const auto* ab = gload_ptr(a.ab);
+    const auto* ab = gload_ptr(reinterpret_cast<const AbPair*>(a.ab));
     const auto* faux = gload_ptr(a.faux);
 #pragma unroll
     for (int i = 0; i < NX; ++i) {
@@ -598,7 +619,7 @@ __device__ __forceinline__ void strm_h_body(const StrmHArgs& a, int y) {
                     aux[HW + o] = acc[3][i];
                 }
             } else {
-                const float A = ab[o], B = ab[HW + o];
+                const float A = ab[o].a, B = ab[o].b;
                 const float P = faux[o], Q = faux[HW + o];
                 out[o] = fmaf(a.alpha, A * P - B * Q, acc[0][i]);
             }
@@ -652,7 +673,7 @@ struct SbLossImg {
     const float* out;
     const float* eta;
     const float* target;
-    float* ab;          // A, B planes of the image
+    float* ab;          // A, B of the image, interleaved per pixel
     int H, W;
     float center;
 };
@@ -671,8 +692,8 @@ __global__ void __launch_bounds__(kSmThreads) bf_sb_lossab(const SbLossImg* imgs
         const size_t o = (size_t)tk.unit * m.W + x;
         const float d = m.out[o] - m.target[o];
         const float A = 2.0f * d / m.eta[o];
-        m.ab[o] = A;
-        m.ab[HW + o] = A * (m.out[o] - m.center);
+        m.ab[2 * o] = A;
+        m.ab[2 * o + 1] = A * (m.out[o] - m.center);
         acc = fmaf(d, d, acc);
     }
     red[threadIdx.x] = acc;
@@ -711,7 +732,8 @@ namespace {
 constexpr int sm_group(int nb) { return nb <= 2 ? 6 : (nb == 3 ? 4 : 3); }
 
 // Row-pass instantiations: samples per lane (odd).
-constexpr int kSmLines[] = {9, 17, 25, 33, 37, 41, 45, 49, 57, 65, 69, 73, 81};
+constexpr int kSmLines[] = {3,  5,  7,  9,  11, 13, 15, 17, 19, 21, 23, 25, 27, 29,
+                            31, 33, 37, 41, 45, 49, 57, 65, 69, 73, 81};
 
 int line_lanes(int64_t W, int R) {
     // the row lands at R + x in 16-byte pieces, so the line spans W rounded
