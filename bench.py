@@ -61,7 +61,12 @@ WORKLOADS = {
 # for a 512 MiB copy); valid only for the kernel sources they were taken on
 # (hash of STREAM_SOURCES).  Record: profiles/bf_sb_kernels_ragged256_hbm_traffic.md.
 _SB_PROFILE = "profiles/bf_sb_kernels_ragged256_hbm_traffic.md"
-MEASURED_TRAFFIC = {}
+MEASURED_TRAFFIC = {
+    ("bf_sb_v<3,4,1> (adjoint column pass)", "ragged256"):
+        {"bytes": 46638893662, "src": "48d2c590da1a", "profile": _SB_PROFILE},
+    ("bf_sb_v<3,4,0> (forward column pass)", "ragged256"):
+        {"bytes": 32933543302, "src": "48d2c590da1a", "profile": _SB_PROFILE},
+}
 STREAM_SOURCES = ("bf_stream.hip", "bf_tile.h")
 
 
