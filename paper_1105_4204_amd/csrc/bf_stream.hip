@@ -118,8 +118,9 @@ struct StrmVArgs {
     int R;
     int npairs;             // pairs of this chunk
     int ngroups, ncolg, seg, nseg;
-    float center, two_alpha;
-    float mh[kSmMaxGroups], ml[kSmMaxGroups];   // m a of each group's first pair, hi + lo
+    float center;
+    double two_alpha;       // 2 a
+    double ma[kSmMaxGroups];   // m a of each group's first pair
 };
 
 // Z <- Z U, complex, in FP64 (the next pair's phase).
@@ -128,6 +129,44 @@ __device__ __forceinline__ void rotate(double& zr, double& zi, double ur, double
     zi = fma(zr, ui, zi * ur);
     zr = nr;
 }
+
+constexpr double kPiD = 3.14159265358979323846;
+constexpr double kInvPiD = 0.31830988618379067154;
+
+// The phase of a sample for a group's first pair, in FP64: theta = m0 a g
+// splits as k pi + r with |r| <= pi/2, exp(j theta) = (-1)^k exp(j r), and
+// the step to the next pair u = exp(j 2 a g).  Returns whether k is odd:
+// the caller folds that sign into its weights instead of into Z.
+__device__ __forceinline__ bool group_phase(double ma, double two_alpha, double g, double& zr,
+                                            double& zi, double& ur, double& ui) {
+    const double th = ma * g;
+    const double k = rint(th * kInvPiD);
+    cis_small_t<double>(fma(-k, kPiD, th), zr, zi);
+    cis_small_t<double>(two_alpha * g, ur, ui);
+    return ((int)k) & 1;
+}
+
+// The phases of a group's G pairs, Z_0, Z_1 = Z_0 U, then the three-term
+// recurrence Z_{q+1} = 2 Re(U) Z_q - Z_{q-1} (two FP64 operations a pair
+// instead of a complex product's four).
+template <int G>
+struct PairSteps {
+    double zr, zi, pr, pi, ur, ui;
+    __device__ __forceinline__ PairSteps(double zr0, double zi0, double ur0, double ui0)
+        : zr(zr0), zi(zi0), pr(0.0), pi(0.0), ur(ur0), ui(ui0) {}
+    __device__ __forceinline__ void next(int q) {
+        if (q + 1 >= G) return;
+        const double cr = zr, ci = zi;
+        if (q == 0) {
+            rotate(zr, zi, ur, ui);
+        } else {
+            zr = fma(2.0 * ur, zr, -pr);
+            zi = fma(2.0 * ur, zi, -pi);
+        }
+        pr = cr;
+        pi = ci;
+    }
+};
 
 // The integrator weights of a segment start, wtab[k][s] for k < kinit:
 // I_s[t] = sum_k w_s[k] x[t - k] with sum_k w_s[k] z^-k = D(z) / (1 - z^-1)^s,
@@ -176,7 +215,7 @@ __device__ __forceinline__ void strm_v_body(const StrmVArgs& a, int gw, const do
     const int n0 = sg * a.seg, n1 = min(H, n0 + a.seg);
     const int t0 = n0 + a.R;            // first step that emits a row (row n0)
     const int te = n1 + a.R;
-    const float mh = a.mh[pg], ml = a.ml[pg];
+    const double ma = a.ma[pg];
     const int q0 = pg * G;
     const int nq = min(G, a.npairs - q0);
     const size_t HW = (size_t)H * a.W;
@@ -204,23 +243,22 @@ __device__ __forceinline__ void strm_v_body(const StrmVArgs& a, int gw, const do
                 apre = AB[o].a;
                 bpre = AB[o].b;
             }
-            float ur, ui, zr, zi;
-            cis_small(a.two_alpha * g, ur, ui);
-            cis_wide(mh, ml, g, zr, zi);
+            double Zr, Zi, Ur, Ui;
+            const double sg = group_phase(ma, a.two_alpha, (double)g, Zr, Zi, Ur, Ui) ? -1.0 : 1.0;
             double w[NB];
 #pragma unroll
             for (int s = 0; s < NB; ++s) w[s] = wtab[k * NB + s];
-            const double v0 = BWD ? (double)av : 1.0, v1 = BWD ? (double)bv : (double)g;
-            const double Ur = ur, Ui = ui;
-            double Zr = zr, Zi = zi;
+            const double v0 = BWD ? sg * (double)av : sg;
+            const double v1 = BWD ? sg * (double)bv : sg * (double)g;
+            PairSteps<G> ps(Zr, Zi, Ur, Ui);
 #pragma unroll
             for (int q = 0; q < G; ++q) {
-                const double c[4] = {v0 * Zr, v1 * Zr, v0 * Zi, v1 * Zi};
+                const double c[4] = {v0 * ps.zr, v1 * ps.zr, v0 * ps.zi, v1 * ps.zi};
 #pragma unroll
                 for (int ch = 0; ch < 4; ++ch)
 #pragma unroll
                     for (int s = 0; s < NB; ++s) I[q][ch][s] = fma(w[s], c[ch], I[q][ch][s]);
-                if (q + 1 < G) rotate(Zr, Zi, Ur, Ui);
+                ps.next(q);
             }
         }
     }
@@ -284,22 +322,21 @@ __device__ __forceinline__ void strm_v_body(const StrmVArgs& a, int gw, const do
             if (j < a.ntaps) {   // uniform
                 const int y = t - a.toff[j];
                 const bool in = y >= 0 && y < H;
-                const float g = in ? gcur[j] - a.center : 0.0f;
-                float ur, ui, zr, zi;
-                cis_small(a.two_alpha * g, ur, ui);
-                cis_wide(mh, ml, g, zr, zi);
-                const double cj = in ? (double)a.tcoef[j] : 0.0;
+                const double g = in ? (double)(gcur[j] - a.center) : 0.0;
+                double Zr, Zi, Ur, Ui;
+                const bool neg = group_phase(ma, a.two_alpha, g, Zr, Zi, Ur, Ui);
+                const double c0 = in ? (double)a.tcoef[j] : 0.0;
+                const double cj = neg ? -c0 : c0;   // (-1)^k of the phase folded in
                 const double w0 = BWD ? cj * (double)acur[j] : cj;
-                const double w1 = BWD ? cj * (double)bcur[j] : cj * (double)g;
-                const double Ur = ur, Ui = ui;
-                double Zr = zr, Zi = zi;
+                const double w1 = BWD ? cj * (double)bcur[j] : cj * g;
+                PairSteps<G> ps(Zr, Zi, Ur, Ui);
 #pragma unroll
                 for (int q = 0; q < G; ++q) {
-                    d[q][0] = fma(w0, Zr, d[q][0]);
-                    d[q][1] = fma(w1, Zr, d[q][1]);
-                    d[q][2] = fma(w0, Zi, d[q][2]);
-                    d[q][3] = fma(w1, Zi, d[q][3]);
-                    if (q + 1 < G) rotate(Zr, Zi, Ur, Ui);
+                    d[q][0] = fma(w0, ps.zr, d[q][0]);
+                    d[q][1] = fma(w1, ps.zr, d[q][1]);
+                    d[q][2] = fma(w0, ps.zi, d[q][2]);
+                    d[q][3] = fma(w1, ps.zi, d[q][3]);
+                    ps.next(q);
                 }
             }
         }
@@ -318,7 +355,8 @@ __device__ __forceinline__ void strm_v_body(const StrmVArgs& a, int gw, const do
             if (q < nq) {   // uniform
 #pragma unroll
                 for (int k = 0; k < 4; ++k)
-                    dst[((size_t)(q0 + q) * 4 + k) * plane] = (float)I[q][k][NB - 1];
+                    __builtin_nontemporal_store((float)I[q][k][NB - 1],
+                                                &dst[((size_t)(q0 + q) * 4 + k) * plane]);
             }
         }
     }
@@ -889,7 +927,7 @@ bf_status stream_setup(int mode, const StreamIO& io, int64_t H, int64_t W,
     va.ntaps = make_taps(sp, va.toff, va.tcoef);
     va.R = sp.R;
     va.center = rp.center;
-    va.two_alpha = (float)(2.0 * rp.alpha);
+    va.two_alpha = 2.0 * rp.alpha;
     va.kinit = 2 * sp.R + sp.nb;
     o->lds_v = (size_t)va.kinit * sp.nb * sizeof(double);
 
@@ -957,8 +995,7 @@ void stream_chunk(StreamSetup& s, const RangeParams& rp, const SpatialParams& sp
     va.ncolg = (va.W + 63) / 64;
     for (int g = 0; g < ngroups; ++g) {
         const double ma = (double)(rp.odd + 2 * (qb + g * G)) * rp.alpha;
-        va.mh[g] = (float)ma;
-        va.ml[g] = (float)(ma - (double)va.mh[g]);
+        va.ma[g] = ma;
     }
     va.nseg = nseg;
     va.seg = (va.H + nseg - 1) / nseg;

@@ -96,19 +96,26 @@ __host__ __device__ inline size_t tile_lds_floats(int mode, int TH, int TW, int 
 // with P of degree 4 and Q of degree 3, near-minimax on that interval
 // (coefficients from gen_cis_coeffs.py); truncation error below 5e-9, so the
 // float32 rounding of the evaluation dominates.
+template <typename T>
+__device__ __forceinline__ void cis_small_t(T x, T& c, T& s) {
+    const T x2 = x * x;
+    T pc = (T)-2.607594922e-07f;
+    pc = fma(pc, x2, (T)2.476181544e-05f);
+    pc = fma(pc, x2, (T)-1.388840145e-03f);
+    pc = fma(pc, x2, (T)4.166664183e-02f);
+    pc = fma(pc, x2, (T)-5.000000000e-01f);
+    c = fma(pc, x2, (T)1.0f);
+    T ps = (T)2.599969775e-06f;
+    ps = fma(ps, x2, (T)-1.980657107e-04f);
+    ps = fma(ps, x2, (T)8.333016187e-03f);
+    ps = fma(ps, x2, (T)-1.666665673e-01f);
+    s = fma(ps * x2, x, x);
+}
+
+// The float32 evaluation (the FP64 one, cis_small_t<double>, uses the same
+// float coefficients: its error is their truncation error alone).
 __device__ __forceinline__ void cis_small(float x, float& c, float& s) {
-    const float x2 = x * x;
-    float pc = -2.607594922e-07f;
-    pc = fmaf(pc, x2, 2.476181544e-05f);
-    pc = fmaf(pc, x2, -1.388840145e-03f);
-    pc = fmaf(pc, x2, 4.166664183e-02f);
-    pc = fmaf(pc, x2, -5.000000000e-01f);
-    c = fmaf(pc, x2, 1.0f);
-    float ps = 2.599969775e-06f;
-    ps = fmaf(ps, x2, -1.980657107e-04f);
-    ps = fmaf(ps, x2, 8.333016187e-03f);
-    ps = fmaf(ps, x2, -1.666665673e-01f);
-    s = fmaf(ps * x2, x, x);
+    cis_small_t<float>(x, c, s);
 }
 
 // exp(j m a g) for any phase: quadrant from the FP64 phase, remainder

@@ -90,7 +90,9 @@ def test_sv_constant_radius_matches_fixed_box_kernel():
     torch.cuda.synchronize()
     ref = oracle.forward(f, sr, oracle.range_degree(255.0, sr), [r])
     _check(sv.cpu().numpy(), ref, "sv const")
-    _check(sv.cpu().numpy(), fx.cpu().numpy().astype(np.float64), "sv vs fixed", atol=2e-2)
+    # each is within 1e-2 + 1e-4 |ref| of the oracle, so within twice that of each other
+    _check(sv.cpu().numpy(), fx.cpu().numpy().astype(np.float64), "sv vs fixed", atol=2e-2,
+           rtol=2e-4)
 
 
 def test_sv_rejects_bad_bounds():
