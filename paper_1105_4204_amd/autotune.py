@@ -98,7 +98,10 @@ class Tuner:
             f = (torch.rand(H * W + 1, device="cuda", generator=gen) * T)[1:].view(H, W)
             try:
                 if mode == "fwd":
-                    t = self._time(lambda: ops.trig_forward(f, T, sr, radii, N=N, tile=tile))
+                    # the batch's forward tiles also accumulate the adjoint's
+                    # sums: time that variant
+                    t = self._time(lambda: ops.trig_forward(f, T, sr, radii, N=N, tile=tile,
+                                                            return_aux=True))
                 else:
                     out, eta, aux = ops.trig_forward(f, T, sr, radii, N=N, return_aux=True)
                     G = torch.randn(H, W, device="cuda", generator=gen)
