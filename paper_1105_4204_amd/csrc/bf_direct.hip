@@ -129,8 +129,8 @@ bf_status launch_direct(const float* f, float* out, float* eta, int64_t H, int64
     const int S = kDirTile + 2 * sp.R;
     a.staged = (S * S <= kDirLdsTileMax) ? 1 : 0;
     const size_t lds = a.staged ? (size_t)S * S * sizeof(float) : 0;
-    hipFuncSetAttribute((const void*)bf_direct_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
-                        (int)lds);
+    (void)hipFuncSetAttribute((const void*)bf_direct_kernel,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     hipLaunchKernelGGL(bf_direct_kernel, dim3((unsigned)(a.tiles_x * tiles_y)),
                        dim3(kDirTile * kDirTile), lds, stream, a);
     const hipError_t e = hipGetLastError();

@@ -218,7 +218,6 @@ __device__ __forceinline__ void strm_v_body(const StrmVArgs& a, int gw, const do
     const double ma = a.ma[pg];
     const int q0 = pg * G;
     const int nq = min(G, a.npairs - q0);
-    const size_t HW = (size_t)H * a.W;
     const auto* F = gload_ptr(a.f);
     const auto* AB = gload_ptr(reinterpret_cast<const AbPair*>(a.ab));
     auto* VP = gstore_ptr(a.vp);
@@ -724,7 +723,6 @@ __global__ void __launch_bounds__(kSmThreads) bf_sb_lossab(const SbLossImg* imgs
     __shared__ float red[kSmThreads];
     const SbTask tk = tasks[blockIdx.x];
     const SbLossImg& m = imgs[tk.img];
-    const size_t HW = (size_t)m.H * m.W;
     float acc = 0.0f;
     for (int x = threadIdx.x; x < m.W; x += kSmThreads) {
         const size_t o = (size_t)tk.unit * m.W + x;
