@@ -63,9 +63,9 @@ WORKLOADS = {
 _SB_PROFILE = "profiles/bf_sb_kernels_ragged256_hbm_traffic.md"
 MEASURED_TRAFFIC = {
     ("bf_sb_v<3,4,1> (adjoint column pass)", "ragged256"):
-        {"bytes": 46638893662, "src": "48d2c590da1a", "profile": _SB_PROFILE},
+        {"bytes": 38584603448, "src": "4668532ab45f", "profile": _SB_PROFILE},
     ("bf_sb_v<3,4,0> (forward column pass)", "ragged256"):
-        {"bytes": 32933543302, "src": "48d2c590da1a", "profile": _SB_PROFILE},
+        {"bytes": 29683043121, "src": "4668532ab45f", "profile": _SB_PROFILE},
 }
 STREAM_SOURCES = ("bf_stream.hip", "bf_tile.h")
 
