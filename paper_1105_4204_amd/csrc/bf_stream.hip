@@ -118,6 +118,7 @@ struct StrmVArgs {
     int R;
     int npairs;             // pairs of this chunk
     int ngroups, ncolg, seg, nseg;
+    int gsize;              // pairs per group (the batch kernel for three boxes runs 4 or 5)
     float center;
     double two_alpha;       // 2 a
     double ma[kSmMaxGroups];   // m a of each group's first pair
@@ -693,7 +694,12 @@ __global__ void __launch_bounds__(kSmThreads) bf_sb_v(const StrmVArgs* __restric
     double* wtab = wt + (size_t)wave * wslice;
     strm_weights<NB>(a, wtab, threadIdx.x & 63, 64);
     wave_sync_lds();
-    strm_v_body<NB, G, MODE>(a, unit, wtab);
+    // three boxes: each image's own group size, so that one launch serves
+    // every image of the batch
+    if (NB == 3 && a.gsize == 4)
+        strm_v_body<NB, 4, MODE>(a, unit, wtab);
+    else
+        strm_v_body<NB, G, MODE>(a, unit, wtab);
 }
 
 // Row pass over a batch: workgroup b filters row tasks[b].unit of image
@@ -763,9 +769,20 @@ __global__ void __launch_bounds__(kSmThreads) bf_sb_lossred(const float* row_par
 
 namespace {
 
-// pairs per lane in the column pass: the integrator state (4 channels x nb
-// doubles per pair) must leave room for two waves per SIMD
-constexpr int sm_group(int nb) { return nb <= 2 ? 6 : (nb == 3 ? 4 : 3); }
+// Pairs per lane in the column pass: the integrator state (4 channels x nb
+// doubles per pair) must leave room for two waves per SIMD.  Three boxes run
+// groups of 4 or 5: per tap a group pays one phase evaluation (about 38
+// instructions) and about 8 per pair, so 5 wins where it does not add empty
+// slots to the last group (34 pairs: 7 groups of 5 against 9 of 4; 16 pairs
+// in a chunk: 4 groups either way).
+int group_pairs(int nb, int np) {
+    if (nb <= 2) return 6;
+    if (nb >= 4) return 3;
+    const int c4 = (np + 3) / 4 * (38 + 8 * 4), c5 = (np + 4) / 5 * (38 + 8 * 5);
+    return c5 < c4 ? 5 : 4;
+}
+// the column-pass variant: box count and group size
+constexpr int vkey(int nb, int G) { return nb * 8 + G; }
 
 // Row-pass instantiations: samples per lane (odd).
 constexpr int kSmLines[] = {3,  5,  7,  9,  11, 13, 15, 17, 19, 21, 23, 25, 27, 29,
@@ -822,9 +839,9 @@ size_t plane_pitch(int64_t W) {
     return W < 64 ? (size_t)((W + 3) / 4 * 4) : (size_t)((W + 63) / 64 * 64);
 }
 
-template <int NB, int MODE>
+template <int NB, int G, int MODE>
 void launch_v(const StrmVArgs& a, hipStream_t s, unsigned blocks, size_t lds) {
-    auto k = bf_strm_v<NB, sm_group(NB), MODE>;
+    auto k = bf_strm_v<NB, G, MODE>;
     (void)hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize,
                               (int)lds);
     hipLaunchKernelGGL(k, dim3(blocks), dim3(kSmThreads), lds, s, a);
@@ -985,9 +1002,10 @@ bf_status stream_setup(int mode, const StreamIO& io, int64_t H, int64_t W,
 // segments.
 void stream_chunk(StreamSetup& s, const RangeParams& rp, const SpatialParams& sp, int qb, int np,
                   int ci, int nchunks, int nseg) {
-    const int G = sm_group(sp.nb);
+    const int G = group_pairs(sp.nb, np);
     const int ngroups = (np + G - 1) / G;
     StrmVArgs& va = s.va;
+    va.gsize = G;
     va.npairs = np;
     va.ngroups = ngroups;
     va.ncolg = (va.W + 63) / 64;
@@ -1045,23 +1063,24 @@ double device_slots() {
     return 8.0 * std::max(cus, 1);   // two waves per SIMD
 }
 
-void launch_v_mode(int mode, int nb, const StrmVArgs& va, hipStream_t stream, unsigned blocks,
-                   size_t lds) {
-    if (mode == kSmBwd) {
-        switch (nb) {
-            case 1: launch_v<1, kSmBwd>(va, stream, blocks, lds); break;
-            case 2: launch_v<2, kSmBwd>(va, stream, blocks, lds); break;
-            case 3: launch_v<3, kSmBwd>(va, stream, blocks, lds); break;
-            default: launch_v<4, kSmBwd>(va, stream, blocks, lds); break;
-        }
-    } else {
-        switch (nb) {
-            case 1: launch_v<1, kSmFwd>(va, stream, blocks, lds); break;
-            case 2: launch_v<2, kSmFwd>(va, stream, blocks, lds); break;
-            case 3: launch_v<3, kSmFwd>(va, stream, blocks, lds); break;
-            default: launch_v<4, kSmFwd>(va, stream, blocks, lds); break;
-        }
+template <int MODE>
+void launch_v_key(int key, const StrmVArgs& va, hipStream_t stream, unsigned blocks,
+                  size_t lds) {
+    switch (key) {
+        case vkey(1, 6): launch_v<1, 6, MODE>(va, stream, blocks, lds); break;
+        case vkey(2, 6): launch_v<2, 6, MODE>(va, stream, blocks, lds); break;
+        case vkey(3, 4): launch_v<3, 4, MODE>(va, stream, blocks, lds); break;
+        case vkey(3, 5): launch_v<3, 5, MODE>(va, stream, blocks, lds); break;
+        default: launch_v<4, 3, MODE>(va, stream, blocks, lds); break;
     }
+}
+
+void launch_v_mode(int mode, int key, const StrmVArgs& va, hipStream_t stream, unsigned blocks,
+                   size_t lds) {
+    if (mode == kSmBwd)
+        launch_v_key<kSmBwd>(key, va, stream, blocks, lds);
+    else
+        launch_v_key<kSmFwd>(key, va, stream, blocks, lds);
 }
 
 void launch_h_mode(int mode, bool aux, const StrmHArgs& ha, int E, hipStream_t stream,
@@ -1110,11 +1129,12 @@ bf_status launch_stream(int mode, const StreamIO& io, int64_t H, int64_t W,
     for (int ci = 0; ci < nchunks; ++ci) {
         const int qb = ci * chunk;
         const int np = std::min(chunk, rp.npairs - qb);
-        const int G = sm_group(sp.nb);
+        const int G = group_pairs(sp.nb, np);
         const int nseg = image_segments(H, W, sp, (np + G - 1) / G, slots);
         stream_chunk(su, rp, sp, qb, np, ci, nchunks, nseg);
         const long long waves = (long long)su.va.ncolg * su.va.ngroups * nseg;
-        launch_v_mode(mode, sp.nb, su.va, stream, (unsigned)((waves + 3) / 4), su.lds_v);
+        launch_v_mode(mode, vkey(sp.nb, G), su.va, stream, (unsigned)((waves + 3) / 4),
+                      su.lds_v);
         launch_h_mode(mode, aux, su.ha, su.E, stream, (unsigned)H, su.lds_h);
     }
     const hipError_t e = hipGetLastError();
@@ -1135,6 +1155,7 @@ struct StreamBatch {
     std::vector<StreamSetup> fw, bw;   // per image: forward and adjoint arguments
     std::vector<int64_t> H, W;
     std::vector<size_t> vp_off, hw_off;   // per image: plane and pixel-plane offsets
+    std::vector<int> nseg;                 // per image: column segments
     std::vector<SbLossImg> li;
     struct Group {
         int key;        // column pass: nb; row pass: E
@@ -1189,7 +1210,7 @@ bf_status sb_upload(T* d, const std::vector<T>& h) {
 
 bool stream_batch_supported(int64_t H, int64_t W, const SpatialParams& sp, int npairs) {
     (void)H;
-    return stream_supported(W, sp) && npairs <= kSmMaxGroups * sm_group(sp.nb) &&
+    return stream_supported(W, sp) && npairs <= kSmMaxGroups * group_pairs(sp.nb, npairs) &&
            npairs <= kSmMaxChunk;
 }
 
@@ -1248,35 +1269,61 @@ bf_status stream_batch_create(int n, const int64_t* H, const int64_t* W, const R
         stream_batch_destroy(b);
         return st;
     }
-    // task lists: column waves grouped by box count, longest first; rows
-    // grouped by line length, image by image
+    // column segments: the fewest (at most kSmSegMax rows each), then more
+    // for every image while the batch has fewer than two waves per device
+    // slot (a small batch would leave most of the device idle), as long as
+    // a segment keeps at least 64 rows and twice its warm-up
+    b->nseg.resize(n);
+    {
+        const double slots = device_slots();
+        auto waves = [&](int f) {
+            double w = 0.0;
+            for (int i = 0; i < n; ++i) {
+                const int G = group_pairs(sp[i].nb, rp[i].npairs);
+                const int ns0 = min_segments(H[i]);
+                const int64_t lim = std::max<int64_t>(64, 2 * (2 * sp[i].R + sp[i].nb));
+                int ns = ns0 * f;
+                while (ns > ns0 && (H[i] + ns - 1) / ns < lim) --ns;
+                b->nseg[i] = ns;
+                w += (double)((W[i] + 63) / 64) * ((rp[i].npairs + G - 1) / G) * ns;
+            }
+            return w;
+        };
+        for (int f = 1; f <= 8; ++f)
+            if (waves(f) >= 2.0 * slots) break;
+    }
+    // task lists: column waves grouped by box count, longest first (cost:
+    // rows times taps times the group's size-dependent work); rows grouped
+    // by line length, image by image
     struct VT {
         double cost;
-        int nb;
+        int key;
         SbTask t;
     };
     std::vector<VT> vt;
     std::vector<SbTask> rows;
     std::vector<int> row_first(n), row_count(n);
     for (int i = 0; i < n; ++i) {
-        const int G = sm_group(sp[i].nb);
+        const int G = group_pairs(sp[i].nb, rp[i].npairs);
         const int ngroups = (rp[i].npairs + G - 1) / G;
-        const int nseg = min_segments(H[i]);
+        const int nseg = b->nseg[i];
         const int ncolg = (int)((W[i] + 63) / 64);
         const int seg = (int)((H[i] + nseg - 1) / nseg);
-        const double cost = (seg + 0.25 * (2.0 * sp[i].R + sp[i].nb)) * (1 << sp[i].nb);
-        for (int u = 0; u < ncolg * ngroups * nseg; ++u) vt.push_back({cost, sp[i].nb, {i, u}});
+        const double cost = (seg + 0.25 * (2.0 * sp[i].R + sp[i].nb)) * (1 << sp[i].nb) *
+                            (38.0 + 8.0 * G);
+        const int key = sp[i].nb;   // one launch per box count
+        for (int u = 0; u < ncolg * ngroups * nseg; ++u) vt.push_back({cost, key, {i, u}});
         row_first[i] = (int)rows.size();
         row_count[i] = (int)H[i];
         for (int y = 0; y < (int)H[i]; ++y) rows.push_back({i, y});
     }
     std::stable_sort(vt.begin(), vt.end(), [](const VT& a, const VT& c) {
-        return a.nb < c.nb || (a.nb == c.nb && a.cost > c.cost);
+        return a.key < c.key || (a.key == c.key && a.cost > c.cost);
     });
     std::vector<SbTask> vtasks;
     for (size_t k = 0; k < vt.size(); ++k) {
-        if (b->vgroups.empty() || b->vgroups.back().key != vt[k].nb)
-            b->vgroups.push_back({vt[k].nb, (int)k, 0, 0});
+        if (b->vgroups.empty() || b->vgroups.back().key != vt[k].key)
+            b->vgroups.push_back({vt[k].key, (int)k, 0, 0});
         b->vgroups.back().count++;
         vtasks.push_back(vt[k].t);
     }
@@ -1329,7 +1376,7 @@ bf_status stream_batch_bind(StreamBatch* b, const float* const* f, const float* 
         bf_status st = stream_setup(kSmFwd, io, H, W, b->rp[i], b->sp[i], vp, nullptr, ab,
                                     &b->fw[i]);
         if (st != BF_OK) return st;
-        const int nseg = min_segments(H);
+        const int nseg = b->nseg[i];
         stream_chunk(b->fw[i], b->rp[i], b->sp[i], 0, b->rp[i].npairs, 0, 1, nseg);
         vaf[i] = b->fw[i].va;
         haf[i] = b->fw[i].ha;
@@ -1370,15 +1417,26 @@ bf_status stream_batch_bind(StreamBatch* b, const float* const* f, const float* 
 
 namespace {
 
-template <int NB, int MODE>
+template <int NB, int G, int MODE>
 void launch_sb_v(const StrmVArgs* args, const SbTask* tasks, int count, size_t lds,
                  hipStream_t s) {
-    auto k = bf_sb_v<NB, sm_group(NB), MODE>;
+    auto k = bf_sb_v<NB, G, MODE>;
     (void)hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize,
                               (int)lds);
     const int wslice = (int)(lds / sizeof(double) / (kSmThreads / 64));
     hipLaunchKernelGGL(k, dim3((unsigned)((count + 3) / 4)), dim3(kSmThreads), lds, s, args,
                        tasks, count, wslice);
+}
+
+template <int MODE>
+void launch_sb_v_key(int key, const StrmVArgs* args, const SbTask* tasks, int count, size_t lds,
+                     hipStream_t s) {
+    switch (key) {   // the box count; three boxes take group sizes 4 and 5 in one kernel
+        case 1: launch_sb_v<1, 6, MODE>(args, tasks, count, lds, s); break;
+        case 2: launch_sb_v<2, 6, MODE>(args, tasks, count, lds, s); break;
+        case 3: launch_sb_v<3, 5, MODE>(args, tasks, count, lds, s); break;
+        default: launch_sb_v<4, 3, MODE>(args, tasks, count, lds, s); break;
+    }
 }
 
 template <int MODE, bool AUX, int I = 0>
@@ -1402,21 +1460,10 @@ void sb_passes(const StreamBatch* b, int mode, bool aux, hipStream_t s, bool col
     for (const auto& g : b->vgroups) {
         if (!col) break;
         const SbTask* t = b->vtasks + g.off;
-        if (mode == kSmBwd) {
-            switch (g.key) {
-                case 1: launch_sb_v<1, kSmBwd>(va, t, g.count, g.lds, s); break;
-                case 2: launch_sb_v<2, kSmBwd>(va, t, g.count, g.lds, s); break;
-                case 3: launch_sb_v<3, kSmBwd>(va, t, g.count, g.lds, s); break;
-                default: launch_sb_v<4, kSmBwd>(va, t, g.count, g.lds, s); break;
-            }
-        } else {
-            switch (g.key) {
-                case 1: launch_sb_v<1, kSmFwd>(va, t, g.count, g.lds, s); break;
-                case 2: launch_sb_v<2, kSmFwd>(va, t, g.count, g.lds, s); break;
-                case 3: launch_sb_v<3, kSmFwd>(va, t, g.count, g.lds, s); break;
-                default: launch_sb_v<4, kSmFwd>(va, t, g.count, g.lds, s); break;
-            }
-        }
+        if (mode == kSmBwd)
+            launch_sb_v_key<kSmBwd>(g.key, va, t, g.count, g.lds, s);
+        else
+            launch_sb_v_key<kSmFwd>(g.key, va, t, g.count, g.lds, s);
     }
     for (const auto& g : b->hgroups) {
         if (!row) break;
