@@ -303,7 +303,9 @@ typedef struct bf_batch_plan bf_batch_plan;
 bf_status bf_batch_plan_create(const bf_image_desc* descs, int32_t n, bf_batch_plan** plan);
 /* path: BF_PATH_AUTO (bf_batch_plan_create) runs the batch through the
  * streamed passes when every image is within their limits (W + 2R <= 5184,
- * at most 256 cosine pairs), else through the persistent fused-tile kernel;
+ * at most 256 cosine pairs, 32 (2R + nb) nb bytes <= 160 KiB for the column
+ * pass's weight tables: R <= 638 with four boxes), else through the
+ * persistent fused-tile kernel;
  * BF_PATH_FUSED and BF_PATH_STREAMED force one (BF_EUNSUPPORTED if an image
  * is outside the streamed passes' limits).  The streamed batch enqueues a
  * short sequence of kernels instead of one persistent kernel: the column

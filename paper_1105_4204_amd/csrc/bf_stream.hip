@@ -56,8 +56,8 @@ namespace bf {
 
 constexpr int kSmThreads = 256;
 constexpr int kSmMaxTaps = 16;        // 2^BF_MAX_BOXES
-constexpr int kSmMaxGroups = 64;      // pair groups per chunk
 constexpr int kSmMaxChunk = 256;      // pairs per chunk
+constexpr int kSmMaxGroups = (kSmMaxChunk + 2) / 3;   // pair groups per chunk (groups of 3 or more)
 constexpr int kSmLineMax = 81;        // row pass: samples per lane at most (odd)
 constexpr int kSmSegMax = 2048;       // column pass: rows per segment at most
 constexpr int kSmPhaseSync = 8;       // row pass: pairs between direct phase evaluations
@@ -1210,8 +1210,11 @@ bf_status sb_upload(T* d, const std::vector<T>& h) {
 
 bool stream_batch_supported(int64_t H, int64_t W, const SpatialParams& sp, int npairs) {
     (void)H;
+    // the batch's column pass keeps a segment-start weight table per wave
+    // (2R + nb rows of nb doubles), four waves to a workgroup, in LDS
+    const size_t lds = (size_t)(kSmThreads / 64) * (2 * sp.R + sp.nb) * sp.nb * sizeof(double);
     return stream_supported(W, sp) && npairs <= kSmMaxGroups * group_pairs(sp.nb, npairs) &&
-           npairs <= kSmMaxChunk;
+           npairs <= kSmMaxChunk && lds <= (size_t)160 * 1024;
 }
 
 void stream_batch_destroy(StreamBatch* b) {

@@ -258,3 +258,18 @@ def test_sigma_s_100_sampled():
     out, eta = _ops().trig_forward(_cuda(f_np), 255.0, 20.0, radii, return_eta=True)
     torch.cuda.synchronize()
     _sampled(f_np, 20.0, N, radii, out, eta, "2048^2 sigma_s=100 N=66 sampled", 34, 8192)
+
+
+def test_four_boxes_many_pairs_in_one_chunk():
+    """Four boxes (three pairs per column-pass group) with more than 192 pairs
+    in one chunk: 68 groups, beyond the 64 the argument table once held."""
+    from paper_1105_4204_amd import ops
+    H, W, sr, N, radii = 24, 40, 8.0, 420, [1, 1, 2, 2]
+    f = synth.piecewise_smooth(H, W, seed=424, n_shapes=3)
+    print(f"case {H}x{W} N={N} radii={radii}", flush=True)
+    ref = oracle.forward(f, sr, N, radii)
+    out = ops.trig_forward(torch.from_numpy(f).cuda(), 255.0, sr, radii, N=N, path=2)
+    torch.cuda.synchronize()
+    err = np.abs(out.cpu().numpy().astype(np.float64) - ref)
+    print(f"max_abs {err.max():.3e}", flush=True)
+    assert np.all(err <= 1e-2 + 1e-4 * np.abs(ref))
