@@ -62,10 +62,10 @@ WORKLOADS = {
 # (hash of STREAM_SOURCES).  Record: profiles/bf_sb_kernels_ragged256_hbm_traffic.md.
 _SB_PROFILE = "profiles/bf_sb_kernels_ragged256_hbm_traffic.md"
 MEASURED_TRAFFIC = {
-    ("bf_sb_v<3,4,1> (adjoint column pass)", "ragged256"):
-        {"bytes": 38584603448, "src": "4668532ab45f", "profile": _SB_PROFILE},
-    ("bf_sb_v<3,4,0> (forward column pass)", "ragged256"):
-        {"bytes": 29683043121, "src": "4668532ab45f", "profile": _SB_PROFILE},
+    ("bf_sb_v<3,5,1> (adjoint column pass, groups of 4 or 5 pairs)", "ragged256"):
+        {"bytes": 37265734375, "src": "65e3a0f944f6", "profile": _SB_PROFILE},
+    ("bf_sb_v<3,5,0> (forward column pass, groups of 4 or 5 pairs)", "ragged256"):
+        {"bytes": 29574927421, "src": "65e3a0f944f6", "profile": _SB_PROFILE},
 }
 STREAM_SOURCES = ("bf_stream.hip", "bf_tile.h")
 
@@ -172,9 +172,10 @@ def line_lanes(W: int, R: int) -> int:
 
 STAGES = ("forward column pass", "forward row pass", "loss and adjoint weights",
           "adjoint column pass", "adjoint row pass")
-STAGE_KERNELS = ("bf_sb_v<3,4,0> (forward column pass)",
+STAGE_KERNELS = ("bf_sb_v<3,5,0> (forward column pass, groups of 4 or 5 pairs)",
                  "bf_sb_h<E,0,true> (forward row pass, one launch per line length E)",
-                 "bf_sb_lossab + bf_sb_lossred", "bf_sb_v<3,4,1> (adjoint column pass)",
+                 "bf_sb_lossab + bf_sb_lossred",
+                 "bf_sb_v<3,5,1> (adjoint column pass, groups of 4 or 5 pairs)",
                  "bf_sb_h<E,1,false> (adjoint row pass, one launch per line length E)")
 
 
@@ -472,6 +473,31 @@ def config4_bench(steps):
             "stages_ms": [round(x, 3) for x in res.get("stage_ms", [])]}
 
 
+def colour_bench(reps=5):
+    """A 3 x 2048 x 2048 colour image (the colour generator, seed 9), each
+    channel filtered on its own as one item of a forward-only batch plan
+    (sigma_s = 10 as boxes 9, 9, 10, sigma_r = 20, N = 66); launches timed
+    with HIP events on the stream."""
+    import torch
+
+    from paper_1105_4204_amd import batch, synth
+    img = torch.from_numpy(synth.colour(2048, 2048, seed=9)).cuda()
+    C, H, W = img.shape
+    spec = dict(H=H, W=W, T=255.0, sigma_r=20.0, radii=[9, 9, 10])
+    plan = batch.BatchPlan([spec] * C)
+    out = torch.empty_like(img)
+    plan.bind([img[c] for c in range(C)], out=[out[c] for c in range(C)])
+    stream = torch.cuda.current_stream()
+    plan.launch()
+    ms = _timed(lambda: plan.launch(), reps, stream)
+    plan.check()
+    plan.close()
+    return {"workload": "3 x 2048x2048 f32 colour (per-channel gain, offset, noise), boxes 9, 9, 10, "
+                        "sigma_r=20, N=66, channel-wise forward as one batch",
+            "ms": round(ms, 3), "mpix_s": round(H * W / 1e3 / ms, 1),
+            "channel_mpix_s": round(C * H * W / 1e3 / ms, 1)}
+
+
 def batch_cpu_baseline(specs, fs, ts, budget_s=30.0, n_images=8, fwd_px=32768, grad_px=128):
     """The FP64 oracle on the host cores over a bounded sample of the headline
     workload: for each of the first n_images images of the ragged batch, the
@@ -654,6 +680,7 @@ def main():
                                                     "fwd_mpix_s", "roofline_fwd")}
         if args.workload != "config4":
             extras["config4"] = config4_bench(max(3, args.steps // 4))
+        extras["colour"] = colour_bench()
         progress("extras: sigma_s sweep, other kernels, 4096^2")
         if not args.no_sweep:
             extras["sigma_s_sweep"] = sigma_s_sweep(f2, T, wl["sigma_r"])
