@@ -273,3 +273,39 @@ def test_four_boxes_many_pairs_in_one_chunk():
     err = np.abs(out.cpu().numpy().astype(np.float64) - ref)
     print(f"max_abs {err.max():.3e}", flush=True)
     assert np.all(err <= 1e-2 + 1e-4 * np.abs(ref))
+
+
+def test_stream_forward_and_adjoint_captured_in_a_graph():
+    """The streamed forward (with eta and the adjoint's sums) and adjoint,
+    given a caller workspace, allocate and synchronise nothing: captured into
+    a HIP graph and replayed three times, with eager work on the outputs
+    between replays, they reproduce the eager results bit for bit."""
+    from paper_1105_4204_amd import _native as nat
+    from paper_1105_4204_amd import ops
+    H, W, sr, radii = 150, 230, 20.0, [4, 4, 5]
+    f = torch.from_numpy(synth.piecewise_smooth(H, W, seed=808, n_shapes=4)).cuda()
+    G = torch.randn(H, W, device="cuda", generator=torch.Generator("cuda").manual_seed(9))
+    nws = nat.stream_workspace_bytes(H, W, 8)          # several chunks
+    ws = torch.empty(nws, dtype=torch.uint8, device="cuda")
+    kw = dict(path=2, workspace=ws)
+    o1, e1, x1 = ops.trig_forward(f, 255.0, sr, radii, return_aux=True, **kw)
+    g1 = ops.trig_backward(f, o1, e1, x1, G, 255.0, sr, radii, **kw)
+    torch.cuda.synchronize()
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):       # warm-up off the capture stream
+        ops.trig_forward(f, 255.0, sr, radii, return_aux=True, **kw)
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        o, e, x = ops.trig_forward(f, 255.0, sr, radii, return_aux=True, **kw)
+        g = ops.trig_backward(f, o, e, x, G, 255.0, sr, radii, **kw)
+    for rep in range(3):
+        for t in (o, e, x, g):
+            t.fill_(-1.0)
+        graph.replay()
+        torch.cuda.synchronize()
+        print(f"replay {rep}", flush=True)
+        assert torch.equal(o, o1) and torch.equal(e, e1), rep
+        assert torch.equal(x, x1) and torch.equal(g, g1), rep
