@@ -362,13 +362,27 @@ __device__ __forceinline__ void strm_v_body(const StrmVArgs& a, int gw, const do
     }
 }
 
+// Workgroups are dealt to the eight XCDs in turn (workgroup b on XCD b mod
+// 8).  Consecutive column-pass tasks are the pair groups of one column group
+// and segment, which read the same tap rows: this mapping puts four
+// consecutive logical workgroups (sixteen waves) on one XCD, so that they
+// share its L2, and keeps the order of the task list window by window (the
+// last, incomplete window maps to itself).
+__device__ __forceinline__ unsigned xcd_local_block(unsigned b, unsigned nblk) {
+    const unsigned full = nblk & ~31u;
+    if (b >= full) return b;
+    const unsigned w = b & ~31u;
+    return w + 4u * (b & 7u) + ((b - w) >> 3);
+}
+
 template <int NB, int G, int MODE>
 __global__ void __launch_bounds__(kSmThreads) bf_strm_v(const StrmVArgs a) {
     extern __shared__ double wtab[];   // [k][s]: integrator weights of the segment start
     strm_weights<NB>(a, wtab, threadIdx.x, kSmThreads);
     __syncthreads();
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    strm_v_body<NB, G, MODE>(a, blockIdx.x * (kSmThreads / 64) + wave, wtab);
+    const int blk = (int)xcd_local_block(blockIdx.x, gridDim.x);
+    strm_v_body<NB, G, MODE>(a, blk * (kSmThreads / 64) + wave, wtab);
 }
 
 // A = G / eta and B = A (out - T/2), the adjoint's per-pixel weights.
@@ -686,7 +700,7 @@ __global__ void __launch_bounds__(kSmThreads) bf_sb_v(const StrmVArgs* __restric
                                                       int ntasks, int wslice) {
     extern __shared__ double wt[];
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int gw = blockIdx.x * (kSmThreads / 64) + wave;
+    const int gw = (int)xcd_local_block(blockIdx.x, gridDim.x) * (kSmThreads / 64) + wave;
     if (gw >= ntasks) return;   // no block barriers in this kernel
     const int img = __builtin_amdgcn_readfirstlane(tasks[gw].img);
     const int unit = __builtin_amdgcn_readfirstlane(tasks[gw].unit);
