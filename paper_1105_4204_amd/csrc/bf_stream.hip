@@ -738,18 +738,26 @@ struct SbLossImg {
 // Per row of every image: the SSD loss gradient G = 2 (out - target), the
 // adjoint's weights A = G / eta and B = A (out - T/2), and the row's partial
 // sum of squared differences (a fixed-order block reduction).
-__global__ void __launch_bounds__(kSmThreads) bf_sb_lossab(const SbLossImg* imgs,
-                                                           const SbTask* tasks, float* row_part) {
+__global__ void __launch_bounds__(kSmThreads) bf_sb_lossab(const SbLossImg* __restrict__ imgs,
+                                                           const SbTask* __restrict__ tasks,
+                                                           float* row_part) {
     __shared__ float red[kSmThreads];
     const SbTask tk = tasks[blockIdx.x];
     const SbLossImg& m = imgs[tk.img];
+    const auto* out = gload_ptr(m.out);
+    const auto* target = gload_ptr(m.target);
+    const auto* eta = gload_ptr(m.eta);
+    auto* ab = gstore_ptr(reinterpret_cast<AbPair*>(m.ab));
+    const int W = m.W;
+    const float center = m.center;
     float acc = 0.0f;
-    for (int x = threadIdx.x; x < m.W; x += kSmThreads) {
-        const size_t o = (size_t)tk.unit * m.W + x;
-        const float d = m.out[o] - m.target[o];
-        const float A = 2.0f * d / m.eta[o];
-        m.ab[2 * o] = A;
-        m.ab[2 * o + 1] = A * (m.out[o] - m.center);
+    for (int x = threadIdx.x; x < W; x += kSmThreads) {
+        const size_t o = (size_t)tk.unit * W + x;
+        const float ov = out[o];
+        const float d = ov - target[o];
+        const float A = 2.0f * d / eta[o];
+        ab[o].a = A;
+        ab[o].b = A * (ov - center);
         acc = fmaf(d, d, acc);
     }
     red[threadIdx.x] = acc;
@@ -1350,9 +1358,16 @@ bf_status stream_batch_create(int n, const int64_t* H, const int64_t* W, const R
     std::vector<int> keys(E.begin(), E.end());
     std::sort(keys.begin(), keys.end());
     keys.erase(std::unique(keys.begin(), keys.end()), keys.end());
+    // within a line length, the images with the most pairs first: a row's
+    // work grows with its pair count, and the longest rows should not be the
+    // last to start
+    std::vector<int> order(n);
+    for (int i = 0; i < n; ++i) order[i] = i;
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int u, int v) { return rp[u].npairs > rp[v].npairs; });
     for (int e : keys) {
         b->hgroups.push_back({e, (int)htasks.size(), 0, 0});
-        for (int i = 0; i < n; ++i)
+        for (int i : order)
             if (E[i] == e)
                 for (int y = 0; y < (int)H[i]; ++y) htasks.push_back({i, y});
         b->hgroups.back().count = (int)htasks.size() - b->hgroups.back().off;
