@@ -63,9 +63,9 @@ WORKLOADS = {
 _SB_PROFILE = "profiles/bf_sb_kernels_ragged256_hbm_traffic.md"
 MEASURED_TRAFFIC = {
     ("bf_sb_v<3,5,1> (adjoint column pass, groups of 4 or 5 pairs)", "ragged256"):
-        {"bytes": 37265734375, "src": "65e3a0f944f6", "profile": _SB_PROFILE},
+        {"bytes": 32742617439, "src": "001321716503", "profile": _SB_PROFILE},
     ("bf_sb_v<3,5,0> (forward column pass, groups of 4 or 5 pairs)", "ragged256"):
-        {"bytes": 29574927421, "src": "65e3a0f944f6", "profile": _SB_PROFILE},
+        {"bytes": 29165212595, "src": "001321716503", "profile": _SB_PROFILE},
 }
 STREAM_SOURCES = ("bf_stream.hip", "bf_tile.h")
 
