@@ -550,25 +550,33 @@ __device__ __forceinline__ void strm_h_body(const StrmHArgs& a, int y) {
             for (int p = lane; p < R; p += 64) line[p] = 0u;
             for (int p = R + W + lane; p < 64 * E; p += 64) line[p] = 0u;
             wave_sync_lds();
-            // the grid: |q| L1 < 2^30 for the row's largest sample
+            // the grid: |q| L1 < 2^30 for the row's largest sample; each
+            // sample rounded to the nearest grid point in one FP64 fused
+            // multiply-add: x 2^e1 + 1.5 2^52 has unit spacing, so the
+            // addition rounds x 2^e1 to an integer, which the low word holds
+            // in two's complement (|x 2^e1| < 2^30)
             vmax = wave_max(vmax);
             const int e1 = vmax > 0.0f ? 30 - __builtin_amdgcn_frexp_expf(a.L1 * vmax) : 0;
+            const double s1 = ldexp(1.0, e1);
             uint32_t v[E];
 #pragma unroll
             for (int e = 0; e < E; ++e)
-                v[e] = (uint32_t)__float2int_rn(ldexpf(linef[p0 + e], e1));
+                v[e] = (uint32_t)__double_as_longlong(
+                    fma((double)linef[p0 + e], s1, 6755399441055744.0));
             for (int k = 0; k < a.nb; ++k) {
                 const int r = a.r[k];
-                // inclusive prefix along the line: lane-local, then across lanes
-                uint32_t tot = 0u;
+                // inclusive prefix along the line: the lane's total (three-input
+                // adds), its offset from the lanes below, then the running sum
+                // from that offset
+                uint32_t tot = v[0];
+#pragma unroll
+                for (int e = 1; e < E; ++e) tot += v[e];
+                uint32_t run = wave_excl_scan(tot, lane);
 #pragma unroll
                 for (int e = 0; e < E; ++e) {
-                    tot += v[e];
-                    v[e] = tot;
+                    run += v[e];
+                    line[p0 + e] = run;
                 }
-                const uint32_t off = wave_excl_scan(tot, lane);
-#pragma unroll
-                for (int e = 0; e < E; ++e) line[p0 + e] = v[e] + off;
                 wave_sync_lds();
                 // window sums: prefix at p + r minus prefix at p - r - 1, in
                 // blocks of 8 (a scheduling fence keeps the compiler from
@@ -582,6 +590,8 @@ __device__ __forceinline__ void strm_h_body(const StrmHArgs& a, int y) {
                     __builtin_amdgcn_sched_barrier(0);
                 }
                 wave_sync_lds();
+                // onto the next stage's grid, rounded to nearest (truncation's
+                // bias would add up coherently over the later windows)
                 const int sh = a.sh[k];
                 if (k + 1 < a.nb && sh > 0) {   // uniform
                     const int rnd = 1 << (sh - 1);
@@ -589,28 +599,29 @@ __device__ __forceinline__ void strm_h_body(const StrmHArgs& a, int y) {
                     for (int e = 0; e < E; ++e) v[e] = (uint32_t)(((int32_t)v[e] + rnd) >> sh);
                 }
             }
-            // the filtered channel, as float, in place of the line
-            const int eo = a.shtot - e1;
+            // the filtered channel times the pair's coefficient, as float, in
+            // place of the line
+            const float cs = ldexpf(a.chat[qq], a.shtot - e1);
 #pragma unroll
-            for (int e = 0; e < E; ++e) linef[p0 + e] = ldexpf((float)(int32_t)v[e], eo);
+            for (int e = 0; e < E; ++e) linef[p0 + e] = (float)(int32_t)v[e] * cs;
         }
         __syncthreads();
-        const float c = a.chat[qq];
         const float mh = a.mh[qq], ml = a.ml[qq];
-        const float cm = c * (float)m;
+        const float fm = (float)m;
         const float* l0 = reinterpret_cast<const float*>(slds) + a.padl + R;
         const float* l1 = l0 + a.bufsz;
         const float* l2 = l1 + a.bufsz;
         const float* l3 = l2 + a.bufsz;
         const bool direct = !CARRY || qq % kSmPhaseSync == 0;   // uniform
-        // every pixel slot (slots past W read inside the lines and are never stored)
+        // every pixel slot (slots past W read inside the lines and are never
+        // stored); the lines already carry the pair's coefficient
 #pragma unroll
         for (int i = 0; i < NX; ++i) {
             const int x = t + i * kSmThreads;
             const float D0 = l0[x];
             if (centre) {   // m = 0: C = 1, S = 0
-                acc[0][i] = fmaf(c, D0, acc[0][i]);
-                if (!BWD) acc[1][i] = fmaf(c, l1[x], acc[1][i]);
+                acc[0][i] += D0;
+                if (!BWD) acc[1][i] += l1[x];
                 if (CARRY) {
                     pc[i % NP] = 1.0f;
                     ps[i % NP] = 0.0f;
@@ -630,20 +641,20 @@ __device__ __forceinline__ void strm_h_body(const StrmHArgs& a, int y) {
                     ps[i % NP] = S;
                 }
                 if (!BWD) {
-                    acc[0][i] = fmaf(c * C, D0, fmaf(c * S, D2, acc[0][i]));
-                    acc[1][i] = fmaf(c * C, D1, fmaf(c * S, D3, acc[1][i]));
+                    acc[0][i] = fmaf(C, D0, fmaf(S, D2, acc[0][i]));
+                    acc[1][i] = fmaf(C, D1, fmaf(S, D3, acc[1][i]));
                     if (AUX) {
-                        acc[2][i] = fmaf(cm * C, D3, fmaf(-cm * S, D1, acc[2][i]));
-                        acc[3][i] = fmaf(cm * C, D2, fmaf(-cm * S, D0, acc[3][i]));
+                        const float mC = fm * C, mS = fm * S;
+                        acc[2][i] = fmaf(mC, D3, fmaf(-mS, D1, acc[2][i]));
+                        acc[3][i] = fmaf(mC, D2, fmaf(-mS, D0, acc[3][i]));
                     }
                 } else {
                     // c {(C - ma g S) F[AC] + (S + ma g C) F[AS] + ma (S F[BC] - C F[BS])}
                     const float u = mh * gx[i];
-                    float t2 = fmaf(C - u * S, D0, 0.0f);
-                    t2 = fmaf(S + u * C, D2, t2);
+                    float t2 = fmaf(fmaf(-u, S, C), D0, acc[0][i]);
+                    t2 = fmaf(fmaf(u, C, S), D2, t2);
                     t2 = fmaf(mh * S, D1, t2);
-                    t2 = fmaf(-mh * C, D3, t2);
-                    acc[0][i] = fmaf(c, t2, acc[0][i]);
+                    acc[0][i] = fmaf(-mh * C, D3, t2);
                 }
             }
         }
