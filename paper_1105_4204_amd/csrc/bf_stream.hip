@@ -522,7 +522,6 @@ __device__ __forceinline__ void strm_h_body(const StrmHArgs& a, int y) {
             const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
                 const_cast<float*>(src), 0, W4 * (int)sizeof(float), kBufferWord3);
             float* dst4 = linef + R + 4 * lane;
-            float vmax = 0.0f;
             constexpr int NH = (NX + 1) / 2;   // two batches: half the staging registers
 #pragma unroll
             for (int b = 0; b < NX; b += NH) {
@@ -535,34 +534,37 @@ __device__ __forceinline__ void strm_h_body(const StrmHArgs& a, int y) {
                                         __uint_as_float(q[2]), __uint_as_float(q[3]));
                 }
 #pragma unroll
-                for (int i = 0; i < NH; ++i) {
-                    if (b + i < NX) {
-                        const int x = 4 * lane + 256 * (b + i);
-                        // the max skips samples past W (row padding)
-                        vmax = fmaxf(vmax, fabsf(ld[i].x));
-                        vmax = fmaxf(vmax, x + 1 < W ? fabsf(ld[i].y) : 0.0f);
-                        vmax = fmaxf(vmax, x + 2 < W ? fabsf(ld[i].z) : 0.0f);
-                        vmax = fmaxf(vmax, x + 3 < W ? fabsf(ld[i].w) : 0.0f);
-                        *reinterpret_cast<float4*>(dst4 + 256 * (b + i)) = ld[i];
-                    }
-                }
+                for (int i = 0; i < NH; ++i)
+                    if (b + i < NX) *reinterpret_cast<float4*>(dst4 + 256 * (b + i)) = ld[i];
             }
-            for (int p = lane; p < R; p += 64) line[p] = 0u;
-            for (int p = R + W + lane; p < 64 * E; p += 64) line[p] = 0u;
+            // zero margins (over the row padding past W as well): one store
+            // per lane, and a loop only where a margin is wider than the wave
+            const int rm = R + W;
+            if (lane < R) line[lane] = 0u;
+            if (R > 64)   // uniform
+                for (int p = lane + 64; p < R; p += 64) line[p] = 0u;
+            if (rm + lane < 64 * E) line[rm + lane] = 0u;
+            if (64 * E - rm > 64)   // uniform
+                for (int p = rm + lane + 64; p < 64 * E; p += 64) line[p] = 0u;
             wave_sync_lds();
+            // the lane's samples and the row's largest magnitude
+            float xs[E];
+            float vmax = 0.0f;
+#pragma unroll
+            for (int e = 0; e < E; ++e) {
+                xs[e] = linef[p0 + e];
+                vmax = fmaxf(vmax, fabsf(xs[e]));
+            }
             // the grid: |q| L1 < 2^30 for the row's largest sample; each
-            // sample rounded to the nearest grid point in one FP64 fused
-            // multiply-add: x 2^e1 + 1.5 2^52 has unit spacing, so the
-            // addition rounds x 2^e1 to an integer, which the low word holds
-            // in two's complement (|x 2^e1| < 2^30)
+            // sample rounded to the nearest grid point (in float: an FP64
+            // rounding here held the lane's samples as doubles, and the
+            // registers cost more occupancy than the instruction saved)
             vmax = wave_max(vmax);
             const int e1 = vmax > 0.0f ? 30 - __builtin_amdgcn_frexp_expf(a.L1 * vmax) : 0;
-            const double s1 = ldexp(1.0, e1);
             uint32_t v[E];
 #pragma unroll
             for (int e = 0; e < E; ++e)
-                v[e] = (uint32_t)__double_as_longlong(
-                    fma((double)linef[p0 + e], s1, 6755399441055744.0));
+                v[e] = (uint32_t)__float2int_rn(ldexpf(xs[e], e1));
             for (int k = 0; k < a.nb; ++k) {
                 const int r = a.r[k];
                 // inclusive prefix along the line: the lane's total (three-input
