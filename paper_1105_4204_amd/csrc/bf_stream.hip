@@ -118,7 +118,7 @@ struct StrmVArgs {
     int R;
     int npairs;             // pairs of this chunk
     int ngroups, ncolg, seg, nseg;
-    int gsize;              // pairs per group (the batch kernel for three boxes runs 4 or 5)
+    int gsize;              // pairs per group (the batch kernel for three boxes runs 4, 5 or 6)
     float center;
     double two_alpha;       // 2 a
     double ma[kSmMaxGroups];   // m a of each group's first pair
@@ -308,15 +308,11 @@ __device__ __forceinline__ void strm_v_body(const StrmVArgs& a, int gw, const do
                 bq[PF - 1][j] = (AB + o)[x].b;
             }
         }
-        // d = sum_j c_j x[t - o_j] in FP64: the channels of a sample are
-        // v0 Z and v1 Z (forward v = (1, g), adjoint v = (A, B)) with Z the
-        // pair's phase carried in FP64 from the group's first pair; c_j v
-        // is exact, so each tap adds the sample's exact products
-        double d[G][4];
-#pragma unroll
-        for (int q = 0; q < G; ++q)
-#pragma unroll
-            for (int k = 0; k < 4; ++k) d[q][k] = 0.0;
+        // d = sum_j c_j x[t - o_j] in FP64, added tap by tap into the first
+        // integrator (no separate sum: its 4 G doubles would cost the
+        // registers of a wave): the channels of a sample are v0 Z and v1 Z
+        // (forward v = (1, g), adjoint v = (A, B)) with Z the pair's phase
+        // carried in FP64 from the group's first pair; c_j v is exact
 #pragma unroll
         for (int j = 0; j < NT; ++j) {
             if (j < a.ntaps) {   // uniform
@@ -332,10 +328,10 @@ __device__ __forceinline__ void strm_v_body(const StrmVArgs& a, int gw, const do
                 PairSteps<G> ps(Zr, Zi, Ur, Ui);
 #pragma unroll
                 for (int q = 0; q < G; ++q) {
-                    d[q][0] = fma(w0, ps.zr, d[q][0]);
-                    d[q][1] = fma(w1, ps.zr, d[q][1]);
-                    d[q][2] = fma(w0, ps.zi, d[q][2]);
-                    d[q][3] = fma(w1, ps.zi, d[q][3]);
+                    I[q][0][0] = fma(w0, ps.zr, I[q][0][0]);
+                    I[q][1][0] = fma(w1, ps.zr, I[q][1][0]);
+                    I[q][2][0] = fma(w0, ps.zi, I[q][2][0]);
+                    I[q][3][0] = fma(w1, ps.zi, I[q][3][0]);
                     ps.next(q);
                 }
             }
@@ -343,11 +339,9 @@ __device__ __forceinline__ void strm_v_body(const StrmVArgs& a, int gw, const do
 #pragma unroll
         for (int q = 0; q < G; ++q)
 #pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                I[q][k][0] += d[q][k];
+            for (int k = 0; k < 4; ++k)
 #pragma unroll
                 for (int s = 1; s < NB; ++s) I[q][k][s] += I[q][k][s - 1];
-            }
         auto* dst = VP + (size_t)(t - a.R) * a.Wp + x;
         const size_t plane = (size_t)H * a.Wp;
 #pragma unroll
@@ -725,6 +719,8 @@ __global__ void __launch_bounds__(kSmThreads) bf_sb_v(const StrmVArgs* __restric
     // every image of the batch
     if (NB == 3 && a.gsize == 4)
         strm_v_body<NB, 4, MODE>(a, unit, wtab);
+    else if (NB == 3 && a.gsize == 5)
+        strm_v_body<NB, 5, MODE>(a, unit, wtab);
     else
         strm_v_body<NB, G, MODE>(a, unit, wtab);
 }
@@ -806,15 +802,17 @@ namespace {
 
 // Pairs per lane in the column pass: the integrator state (4 channels x nb
 // doubles per pair) must leave room for two waves per SIMD.  Three boxes run
-// groups of 4 or 5: per tap a group pays one phase evaluation (about 38
-// instructions) and about 8 per pair, so 5 wins where it does not add empty
-// slots to the last group (34 pairs: 7 groups of 5 against 9 of 4; 16 pairs
-// in a chunk: 4 groups either way).
+// groups of 4, 5 or 6: per tap a group pays one phase evaluation (about 38
+// instructions) and about 8 per pair, so the largest group wins unless it
+// leaves empty slots in the last group (34 pairs: 6 groups of 6, against 7
+// of 5 or 9 of 4; 9 pairs: 2 groups of 5).
 int group_pairs(int nb, int np) {
     if (nb <= 2) return 6;
     if (nb >= 4) return 3;
-    const int c4 = (np + 3) / 4 * (38 + 8 * 4), c5 = (np + 4) / 5 * (38 + 8 * 5);
-    return c5 < c4 ? 5 : 4;
+    int best = 4;
+    for (int g = 5; g <= 6; ++g)
+        if ((np + g - 1) / g * (38 + 8 * g) < (np + best - 1) / best * (38 + 8 * best)) best = g;
+    return best;
 }
 // the column-pass variant: box count and group size
 constexpr int vkey(int nb, int G) { return nb * 8 + G; }
@@ -1106,6 +1104,7 @@ void launch_v_key(int key, const StrmVArgs& va, hipStream_t stream, unsigned blo
         case vkey(2, 6): launch_v<2, 6, MODE>(va, stream, blocks, lds); break;
         case vkey(3, 4): launch_v<3, 4, MODE>(va, stream, blocks, lds); break;
         case vkey(3, 5): launch_v<3, 5, MODE>(va, stream, blocks, lds); break;
+        case vkey(3, 6): launch_v<3, 6, MODE>(va, stream, blocks, lds); break;
         default: launch_v<4, 3, MODE>(va, stream, blocks, lds); break;
     }
 }
@@ -1476,10 +1475,10 @@ void launch_sb_v(const StrmVArgs* args, const SbTask* tasks, int count, size_t l
 template <int MODE>
 void launch_sb_v_key(int key, const StrmVArgs* args, const SbTask* tasks, int count, size_t lds,
                      hipStream_t s) {
-    switch (key) {   // the box count; three boxes take group sizes 4 and 5 in one kernel
+    switch (key) {   // the box count; three boxes take group sizes 4, 5 and 6 in one kernel
         case 1: launch_sb_v<1, 6, MODE>(args, tasks, count, lds, s); break;
         case 2: launch_sb_v<2, 6, MODE>(args, tasks, count, lds, s); break;
-        case 3: launch_sb_v<3, 5, MODE>(args, tasks, count, lds, s); break;
+        case 3: launch_sb_v<3, 6, MODE>(args, tasks, count, lds, s); break;
         default: launch_sb_v<4, 3, MODE>(args, tasks, count, lds, s); break;
     }
 }
