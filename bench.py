@@ -62,9 +62,9 @@ WORKLOADS = {
 # (hash of STREAM_SOURCES).  Record: profiles/bf_sb_kernels_ragged256_hbm_traffic.md.
 _SB_PROFILE = "profiles/bf_sb_kernels_ragged256_hbm_traffic.md"
 MEASURED_TRAFFIC = {
-    ("bf_sb_v<3,6,1> (adjoint column pass, groups of 4, 5 or 6 pairs)", "ragged256"):
+    ("bf_sb_v<3,7,1> (adjoint column pass, groups of 4 to 7 pairs)", "ragged256"):
         {"bytes": 32742617439, "src": "001321716503", "profile": _SB_PROFILE},
-    ("bf_sb_v<3,6,0> (forward column pass, groups of 4, 5 or 6 pairs)", "ragged256"):
+    ("bf_sb_v<3,8,0> (forward column pass, groups of 4 to 8 pairs)", "ragged256"):
         {"bytes": 29165212595, "src": "001321716503", "profile": _SB_PROFILE},
 }
 STREAM_SOURCES = ("bf_stream.hip", "bf_tile.h")
@@ -172,10 +172,10 @@ def line_lanes(W: int, R: int) -> int:
 
 STAGES = ("forward column pass", "forward row pass", "loss and adjoint weights",
           "adjoint column pass", "adjoint row pass")
-STAGE_KERNELS = ("bf_sb_v<3,6,0> (forward column pass, groups of 4, 5 or 6 pairs)",
+STAGE_KERNELS = ("bf_sb_v<3,8,0> (forward column pass, groups of 4 to 8 pairs)",
                  "bf_sb_h<E,0,true> (forward row pass, one launch per line length E)",
                  "bf_sb_lossab + bf_sb_lossred",
-                 "bf_sb_v<3,6,1> (adjoint column pass, groups of 4, 5 or 6 pairs)",
+                 "bf_sb_v<3,7,1> (adjoint column pass, groups of 4 to 7 pairs)",
                  "bf_sb_h<E,1,false> (adjoint row pass, one launch per line length E)")
 
 

@@ -701,6 +701,19 @@ struct SbTask {
 // Column pass over a batch: wave gw takes task gw (its image's arguments are
 // read from device memory; the segment-start weights go to a wave-private
 // slice of LDS of kinit_max * NB doubles).
+// Three boxes: each image's own group size (4 .. G), so that one launch
+// serves every image of the batch.
+template <int NB, int G, int MODE>
+__device__ __forceinline__ void sb_v_dispatch(const StrmVArgs& a, int unit, const double* wtab) {
+    if constexpr (NB == 3 && G > 4) {
+        if (a.gsize < G) {
+            sb_v_dispatch<NB, G - 1, MODE>(a, unit, wtab);
+            return;
+        }
+    }
+    strm_v_body<NB, G, MODE>(a, unit, wtab);
+}
+
 template <int NB, int G, int MODE>
 __global__ void __launch_bounds__(kSmThreads) bf_sb_v(const StrmVArgs* __restrict__ args,
                                                       const SbTask* __restrict__ tasks,
@@ -715,14 +728,7 @@ __global__ void __launch_bounds__(kSmThreads) bf_sb_v(const StrmVArgs* __restric
     double* wtab = wt + (size_t)wave * wslice;
     strm_weights<NB>(a, wtab, threadIdx.x & 63, 64);
     wave_sync_lds();
-    // three boxes: each image's own group size, so that one launch serves
-    // every image of the batch
-    if (NB == 3 && a.gsize == 4)
-        strm_v_body<NB, 4, MODE>(a, unit, wtab);
-    else if (NB == 3 && a.gsize == 5)
-        strm_v_body<NB, 5, MODE>(a, unit, wtab);
-    else
-        strm_v_body<NB, G, MODE>(a, unit, wtab);
+    sb_v_dispatch<NB, G, MODE>(a, unit, wtab);
 }
 
 // Row pass over a batch: workgroup b filters row tasks[b].unit of image
@@ -802,15 +808,17 @@ namespace {
 
 // Pairs per lane in the column pass: the integrator state (4 channels x nb
 // doubles per pair) must leave room for two waves per SIMD.  Three boxes run
-// groups of 4, 5 or 6: per tap a group pays one phase evaluation (about 38
-// instructions) and about 8 per pair, so the largest group wins unless it
-// leaves empty slots in the last group (34 pairs: 6 groups of 6, against 7
-// of 5 or 9 of 4; 9 pairs: 2 groups of 5).
-int group_pairs(int nb, int np) {
+// groups of 4 to 8 (forward) or 4 to 7 (adjoint, whose taps also carry A and
+// B): per tap a group pays one phase evaluation (about 38 instructions) and
+// about 8 per pair, so the largest group wins unless it leaves empty slots
+// in the last group (34 pairs: 5 groups of 7, against 6 of 6 or 5 of 8; 16
+// pairs: 2 groups of 8 forward, 3 of 6 adjoint).
+int group_pairs(int nb, int np, int mode) {
     if (nb <= 2) return 6;
     if (nb >= 4) return 3;
+    const int gmax = mode == kSmBwd ? 7 : 8;
     int best = 4;
-    for (int g = 5; g <= 6; ++g)
+    for (int g = 5; g <= gmax; ++g)
         if ((np + g - 1) / g * (38 + 8 * g) < (np + best - 1) / best * (38 + 8 * best)) best = g;
     return best;
 }
@@ -949,6 +957,7 @@ namespace {
 
 // Everything of one image's two passes but the pair chunk.
 struct StreamSetup {
+    int mode;         // forward or adjoint
     StrmVArgs va;
     StrmHArgs ha;
     int E;            // row-pass samples per lane
@@ -964,6 +973,7 @@ bf_status stream_setup(int mode, const StreamIO& io, int64_t H, int64_t W,
                        float* ab, StreamSetup* o) {
     const bool bwd = mode == kSmBwd;
     const int Wp = (int)plane_pitch(W);
+    o->mode = mode;
     StrmVArgs& va = o->va;
     va = StrmVArgs{};
     va.f = io.f;
@@ -1035,7 +1045,7 @@ bf_status stream_setup(int mode, const StreamIO& io, int64_t H, int64_t W,
 // segments.
 void stream_chunk(StreamSetup& s, const RangeParams& rp, const SpatialParams& sp, int qb, int np,
                   int ci, int nchunks, int nseg) {
-    const int G = group_pairs(sp.nb, np);
+    const int G = group_pairs(sp.nb, np, s.mode);
     const int ngroups = (np + G - 1) / G;
     StrmVArgs& va = s.va;
     va.gsize = G;
@@ -1105,6 +1115,10 @@ void launch_v_key(int key, const StrmVArgs& va, hipStream_t stream, unsigned blo
         case vkey(3, 4): launch_v<3, 4, MODE>(va, stream, blocks, lds); break;
         case vkey(3, 5): launch_v<3, 5, MODE>(va, stream, blocks, lds); break;
         case vkey(3, 6): launch_v<3, 6, MODE>(va, stream, blocks, lds); break;
+        case vkey(3, 7): launch_v<3, 7, MODE>(va, stream, blocks, lds); break;
+        case vkey(3, 8):   // forward only
+            if constexpr (MODE == kSmFwd) launch_v<3, 8, MODE>(va, stream, blocks, lds);
+            break;
         default: launch_v<4, 3, MODE>(va, stream, blocks, lds); break;
     }
 }
@@ -1163,7 +1177,7 @@ bf_status launch_stream(int mode, const StreamIO& io, int64_t H, int64_t W,
     for (int ci = 0; ci < nchunks; ++ci) {
         const int qb = ci * chunk;
         const int np = std::min(chunk, rp.npairs - qb);
-        const int G = group_pairs(sp.nb, np);
+        const int G = group_pairs(sp.nb, np, mode);
         const int nseg = image_segments(H, W, sp, (np + G - 1) / G, slots);
         stream_chunk(su, rp, sp, qb, np, ci, nchunks, nseg);
         const long long waves = (long long)su.va.ncolg * su.va.ngroups * nseg;
@@ -1196,7 +1210,7 @@ struct StreamBatch {
         int off, count; // slice of the task list
         size_t lds;
     };
-    std::vector<Group> vgroups, hgroups;
+    std::vector<Group> vgroups[2], hgroups;   // column launches per direction; row launches
     int nrows = 0;
     float* loss = nullptr;
     // device memory (owned)
@@ -1208,13 +1222,13 @@ struct StreamBatch {
     StrmHArgs* ha_f = nullptr;
     StrmHArgs* ha_b = nullptr;
     SbLossImg* li_d = nullptr;
-    SbTask* vtasks = nullptr;
+    SbTask* vtasks[2] = {nullptr, nullptr};   // column tasks: forward, adjoint (group sizes differ)
     SbTask* htasks = nullptr;
     SbTask* rows = nullptr;         // every row of every image, image by image
     float* row_part = nullptr;
     int* row_first = nullptr;
     int* row_count = nullptr;
-    int nvtasks = 0, nhtasks = 0;
+    int nhtasks = 0;
 };
 
 namespace {
@@ -1247,7 +1261,7 @@ bool stream_batch_supported(int64_t H, int64_t W, const SpatialParams& sp, int n
     // the batch's column pass keeps a segment-start weight table per wave
     // (2R + nb rows of nb doubles), four waves to a workgroup, in LDS
     const size_t lds = (size_t)(kSmThreads / 64) * (2 * sp.R + sp.nb) * sp.nb * sizeof(double);
-    return stream_supported(W, sp) && npairs <= kSmMaxGroups * group_pairs(sp.nb, npairs) &&
+    return stream_supported(W, sp) && npairs <= kSmMaxGroups * group_pairs(sp.nb, npairs, kSmBwd) &&
            npairs <= kSmMaxChunk && lds <= (size_t)160 * 1024;
 }
 
@@ -1261,7 +1275,8 @@ void stream_batch_destroy(StreamBatch* b) {
     (void)hipFree(b->ha_f);
     (void)hipFree(b->ha_b);
     (void)hipFree(b->li_d);
-    (void)hipFree(b->vtasks);
+    (void)hipFree(b->vtasks[0]);
+    (void)hipFree(b->vtasks[1]);
     (void)hipFree(b->htasks);
     (void)hipFree(b->rows);
     (void)hipFree(b->row_part);
@@ -1316,7 +1331,7 @@ bf_status stream_batch_create(int n, const int64_t* H, const int64_t* W, const R
         auto waves = [&](int f) {
             double w = 0.0;
             for (int i = 0; i < n; ++i) {
-                const int G = group_pairs(sp[i].nb, rp[i].npairs);
+                const int G = group_pairs(sp[i].nb, rp[i].npairs, kSmFwd);
                 const int ns0 = min_segments(H[i]);
                 const int64_t lim = std::max<int64_t>(64, 2 * (2 * sp[i].R + sp[i].nb));
                 int ns = ns0 * f;
@@ -1337,32 +1352,36 @@ bf_status stream_batch_create(int n, const int64_t* H, const int64_t* W, const R
         int key;
         SbTask t;
     };
-    std::vector<VT> vt;
+    std::vector<SbTask> vtasks[2];
+    for (int mode = 0; mode < 2; ++mode) {
+        std::vector<VT> vt;
+        for (int i = 0; i < n; ++i) {
+            const int G = group_pairs(sp[i].nb, rp[i].npairs, mode);
+            const int ngroups = (rp[i].npairs + G - 1) / G;
+            const int nseg = b->nseg[i];
+            const int ncolg = (int)((W[i] + 63) / 64);
+            const int seg = (int)((H[i] + nseg - 1) / nseg);
+            const double cost = (seg + 0.25 * (2.0 * sp[i].R + sp[i].nb)) * (1 << sp[i].nb) *
+                                (38.0 + 8.0 * G);
+            const int key = sp[i].nb;   // one launch per box count
+            for (int u = 0; u < ncolg * ngroups * nseg; ++u) vt.push_back({cost, key, {i, u}});
+        }
+        std::stable_sort(vt.begin(), vt.end(), [](const VT& a, const VT& c) {
+            return a.key < c.key || (a.key == c.key && a.cost > c.cost);
+        });
+        auto& vg = b->vgroups[mode];
+        for (size_t k = 0; k < vt.size(); ++k) {
+            if (vg.empty() || vg.back().key != vt[k].key) vg.push_back({vt[k].key, (int)k, 0, 0});
+            vg.back().count++;
+            vtasks[mode].push_back(vt[k].t);
+        }
+    }
     std::vector<SbTask> rows;
     std::vector<int> row_first(n), row_count(n);
     for (int i = 0; i < n; ++i) {
-        const int G = group_pairs(sp[i].nb, rp[i].npairs);
-        const int ngroups = (rp[i].npairs + G - 1) / G;
-        const int nseg = b->nseg[i];
-        const int ncolg = (int)((W[i] + 63) / 64);
-        const int seg = (int)((H[i] + nseg - 1) / nseg);
-        const double cost = (seg + 0.25 * (2.0 * sp[i].R + sp[i].nb)) * (1 << sp[i].nb) *
-                            (38.0 + 8.0 * G);
-        const int key = sp[i].nb;   // one launch per box count
-        for (int u = 0; u < ncolg * ngroups * nseg; ++u) vt.push_back({cost, key, {i, u}});
         row_first[i] = (int)rows.size();
         row_count[i] = (int)H[i];
         for (int y = 0; y < (int)H[i]; ++y) rows.push_back({i, y});
-    }
-    std::stable_sort(vt.begin(), vt.end(), [](const VT& a, const VT& c) {
-        return a.key < c.key || (a.key == c.key && a.cost > c.cost);
-    });
-    std::vector<SbTask> vtasks;
-    for (size_t k = 0; k < vt.size(); ++k) {
-        if (b->vgroups.empty() || b->vgroups.back().key != vt[k].key)
-            b->vgroups.push_back({vt[k].key, (int)k, 0, 0});
-        b->vgroups.back().count++;
-        vtasks.push_back(vt[k].t);
     }
     std::vector<int> E(n);
     for (int i = 0; i < n; ++i) E[i] = line_lanes(W[i], sp[i].R);
@@ -1384,11 +1403,13 @@ bf_status stream_batch_create(int n, const int64_t* H, const int64_t* W, const R
                 for (int y = 0; y < (int)H[i]; ++y) htasks.push_back({i, y});
         b->hgroups.back().count = (int)htasks.size() - b->hgroups.back().off;
     }
-    b->nvtasks = (int)vtasks.size();
     b->nhtasks = (int)htasks.size();
-    if ((st = sb_alloc(&b->vtasks, vtasks.size())) != BF_OK ||
+    if ((st = sb_alloc(&b->vtasks[0], vtasks[0].size())) != BF_OK ||
+        (st = sb_alloc(&b->vtasks[1], vtasks[1].size())) != BF_OK ||
         (st = sb_alloc(&b->htasks, htasks.size())) != BF_OK ||
-        (st = sb_upload(b->vtasks, vtasks)) != BF_OK || (st = sb_upload(b->htasks, htasks)) != BF_OK ||
+        (st = sb_upload(b->vtasks[0], vtasks[0])) != BF_OK ||
+        (st = sb_upload(b->vtasks[1], vtasks[1])) != BF_OK ||
+        (st = sb_upload(b->htasks, htasks)) != BF_OK ||
         (st = sb_upload(b->rows, rows)) != BF_OK || (st = sb_upload(b->row_first, row_first)) != BF_OK ||
         (st = sb_upload(b->row_count, row_count)) != BF_OK) {
         stream_batch_destroy(b);
@@ -1405,7 +1426,8 @@ bf_status stream_batch_bind(StreamBatch* b, const float* const* f, const float* 
     std::vector<StrmVArgs> vaf(n), vab(n);
     std::vector<StrmHArgs> haf(n), hab(n);
     b->li.assign(n, SbLossImg{});
-    for (auto& g : b->vgroups) g.lds = 0;
+    for (auto& vg : b->vgroups)
+        for (auto& g : vg) g.lds = 0;
     for (auto& g : b->hgroups) g.lds = 0;
     for (int i = 0; i < n; ++i) {
         const int64_t H = b->H[i], W = b->W[i];
@@ -1438,9 +1460,10 @@ bf_status stream_batch_bind(StreamBatch* b, const float* const* f, const float* 
             hab[i] = b->bw[i].ha;
             b->li[i] = SbLossImg{out[i], eta[i], target[i], ab, (int)H, (int)W, b->rp[i].center};
         }
-        for (auto& g : b->vgroups)
-            if (g.key == b->sp[i].nb)
-                g.lds = std::max(g.lds, (size_t)(kSmThreads / 64) * b->fw[i].lds_v);
+        for (auto& vg : b->vgroups)
+            for (auto& g : vg)
+                if (g.key == b->sp[i].nb)
+                    g.lds = std::max(g.lds, (size_t)(kSmThreads / 64) * b->fw[i].lds_v);
         for (auto& g : b->hgroups)
             if (g.key == b->fw[i].E) g.lds = std::max(g.lds, b->fw[i].lds_h);
     }
@@ -1450,11 +1473,13 @@ bf_status stream_batch_bind(StreamBatch* b, const float* const* f, const float* 
     if (b->bwd && ((st = sb_upload(b->va_b, vab)) != BF_OK ||
                    (st = sb_upload(b->ha_b, hab)) != BF_OK || (st = sb_upload(b->li_d, b->li)) != BF_OK))
         return st;
-    for (const auto& g : b->vgroups)
-        if (g.lds > 160 * 1024) {
-            set_error("streamed batch: the segment-start weights need %zu bytes of LDS", g.lds);
-            return BF_EUNSUPPORTED;
-        }
+    for (const auto& vg : b->vgroups)
+        for (const auto& g : vg)
+            if (g.lds > 160 * 1024) {
+                set_error("streamed batch: the segment-start weights need %zu bytes of LDS",
+                          g.lds);
+                return BF_EUNSUPPORTED;
+            }
     b->loss = loss;
     return BF_OK;
 }
@@ -1475,10 +1500,10 @@ void launch_sb_v(const StrmVArgs* args, const SbTask* tasks, int count, size_t l
 template <int MODE>
 void launch_sb_v_key(int key, const StrmVArgs* args, const SbTask* tasks, int count, size_t lds,
                      hipStream_t s) {
-    switch (key) {   // the box count; three boxes take group sizes 4, 5 and 6 in one kernel
+    switch (key) {   // the box count; three boxes take every group size in one kernel
         case 1: launch_sb_v<1, 6, MODE>(args, tasks, count, lds, s); break;
         case 2: launch_sb_v<2, 6, MODE>(args, tasks, count, lds, s); break;
-        case 3: launch_sb_v<3, 6, MODE>(args, tasks, count, lds, s); break;
+        case 3: launch_sb_v<3, MODE == kSmBwd ? 7 : 8, MODE>(args, tasks, count, lds, s); break;
         default: launch_sb_v<4, 3, MODE>(args, tasks, count, lds, s); break;
     }
 }
@@ -1501,9 +1526,9 @@ void launch_sb_h(const StrmHArgs* args, const SbTask* tasks, int count, int E, s
 void sb_passes(const StreamBatch* b, int mode, bool aux, hipStream_t s, bool col, bool row) {
     const StrmVArgs* va = mode == kSmBwd ? b->va_b : b->va_f;
     const StrmHArgs* ha = mode == kSmBwd ? b->ha_b : b->ha_f;
-    for (const auto& g : b->vgroups) {
+    for (const auto& g : b->vgroups[mode == kSmBwd ? 1 : 0]) {
         if (!col) break;
-        const SbTask* t = b->vtasks + g.off;
+        const SbTask* t = b->vtasks[mode == kSmBwd ? 1 : 0] + g.off;
         if (mode == kSmBwd)
             launch_sb_v_key<kSmBwd>(g.key, va, t, g.count, g.lds, s);
         else
