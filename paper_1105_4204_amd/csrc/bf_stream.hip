@@ -118,7 +118,7 @@ struct StrmVArgs {
     int R;
     int npairs;             // pairs of this chunk
     int ngroups, ncolg, seg, nseg;
-    int gsize;              // pairs per group (the batch kernel for three boxes runs 4, 5 or 6)
+    int gsize;              // pairs per group (three boxes: 4 to 8 forward, 4 to 7 adjoint)
     float center;
     double two_alpha;       // 2 a
     double ma[kSmMaxGroups];   // m a of each group's first pair
