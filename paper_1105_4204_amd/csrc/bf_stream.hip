@@ -264,9 +264,13 @@ __device__ __forceinline__ void strm_v_body(const StrmVArgs& a, int gw, const do
     }
 
     // tap rows are wave-uniform: row base in SGPRs, the lane's column as
-    // offset; the taps of the next kSmAhead rows are in flight (clamped,
-    // unconditional loads) while a row is computed
-    constexpr int PF = kSmAhead;
+    // offset; the taps of the next PF rows are in flight (clamped,
+    // unconditional loads) while a row is computed: kSmAhead where the
+    // integrators fill the registers (three and four boxes), four rows for
+    // one box and two for two, whose few waves on small images would
+    // otherwise wait on every row's loads (within the registers that keep
+    // their waves per SIMD)
+    constexpr int PF = NB == 1 ? 4 : NB == 2 ? 2 : kSmAhead;
     float gq[PF][NT], aq[PF][NT], bq[PF][NT];
 #pragma unroll
     for (int p = 0; p < PF; ++p)
@@ -501,35 +505,60 @@ __device__ __forceinline__ void strm_h_body(const StrmHArgs& a, int y) {
 
     const size_t plane = (size_t)a.H * a.Wp;
     const int p0 = lane * E;
+    // piece i (256 samples) of this wave's channel of pair q: 16-byte buffer
+    // loads (lane offset in a register, the piece in the instruction; the
+    // buffer ends at W rounded up to 4, so pieces past it read zero)
+    const int W4 = (W + 3) & ~3;
+    auto piece = [&](int q, int i) {
+        const float* src = a.vp + ((size_t)q * 4 + wave) * plane + (size_t)y * a.Wp;
+        const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+            const_cast<float*>(src), 0, W4 * (int)sizeof(float), kBufferWord3);
+        const auto v = __builtin_amdgcn_raw_buffer_load_b128(rs, 16 * lane, 1024 * i, 0);
+        return make_float4(__uint_as_float(v[0]), __uint_as_float(v[1]), __uint_as_float(v[2]),
+                           __uint_as_float(v[3]));
+    };
+    // short lines (two pieces at most): the next pair's row is loaded while
+    // this pair is filtered (the few registers it takes are there; a row with
+    // many pairs on one workgroup otherwise waits on every pair's loads)
+    constexpr bool PREF = NX <= 2;
+    float4 nxt[NX];
+    if (PREF && a.npairs > 0) {
+#pragma unroll
+        for (int i = 0; i < NX; ++i) nxt[i] = piece(0, i);
+    }
     for (int qq = 0; qq < a.npairs; ++qq) {
         const int m = a.m0 + 2 * qq;
         const bool centre = m == 0;
         const int nch = centre ? (BWD ? 1 : 2) : 4;
+        float4 cur[NX];
+        if (PREF) {
+#pragma unroll
+            for (int i = 0; i < NX; ++i) cur[i] = nxt[i];
+            if (qq + 1 < a.npairs) {   // uniform
+#pragma unroll
+                for (int i = 0; i < NX; ++i) nxt[i] = piece(qq + 1, i);
+            }
+        }
         if (wave < nch) {
-            const float* src = a.vp + ((size_t)qq * 4 + wave) * plane + (size_t)y * a.Wp;
-            // the row into the line at position R + x, raw, in 16-byte buffer
-            // loads (lane offset in a register, the chunk in the instruction;
-            // the buffer ends at W rounded up to 4, so chunks past it read zero)
-            // and aligned 16-byte LDS stores; then the zero margins [0, R) and
-            // [R + W, end of the line)
-            const int W4 = (W + 3) & ~3;
-            const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
-                const_cast<float*>(src), 0, W4 * (int)sizeof(float), kBufferWord3);
+            // the row into the line at position R + x, raw, with aligned
+            // 16-byte LDS stores; then the zero margins [0, R) and [R + W,
+            // end of the line)
             float* dst4 = linef + R + 4 * lane;
-            constexpr int NH = (NX + 1) / 2;   // two batches: half the staging registers
+            if (PREF) {
 #pragma unroll
-            for (int b = 0; b < NX; b += NH) {
-                float4 ld[NH];
+                for (int i = 0; i < NX; ++i) *reinterpret_cast<float4*>(dst4 + 256 * i) = cur[i];
+            } else {
+                constexpr int NH = (NX + 1) / 2;   // two batches: half the staging registers
 #pragma unroll
-                for (int i = 0; i < NH; ++i) {
-                    const auto q = __builtin_amdgcn_raw_buffer_load_b128(
-                        rs, 16 * lane, 1024 * (b + i), 0);
-                    ld[i] = make_float4(__uint_as_float(q[0]), __uint_as_float(q[1]),
-                                        __uint_as_float(q[2]), __uint_as_float(q[3]));
+                for (int b = 0; b < NX; b += NH) {
+                    float4 ld[NH];
+#pragma unroll
+                    for (int i = 0; i < NH; ++i)
+                        if (b + i < NX) ld[i] = piece(qq, b + i);
+#pragma unroll
+                    for (int i = 0; i < NH; ++i)
+                        if (b + i < NX) *reinterpret_cast<float4*>(dst4 + 256 * (b + i)) = ld[i];
                 }
-#pragma unroll
-                for (int i = 0; i < NH; ++i)
-                    if (b + i < NX) *reinterpret_cast<float4*>(dst4 + 256 * (b + i)) = ld[i];
             }
             // zero margins (over the row padding past W as well): one store
             // per lane, and a loop only where a margin is wider than the wave
