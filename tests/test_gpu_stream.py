@@ -194,6 +194,48 @@ def test_stream_adjoint_wide_full_parity(case):
     _grad_check(gf.cpu().numpy(), ref, f"streamed adjoint {case}")
 
 
+# Three boxes, at pair counts (N // 2 + 1 = 4 .. 34) that give every group size
+# of the column pass: forward 4 to 8, adjoint 4 to 7, one or several groups
+# per column (pairs: group size forward / adjoint):
+# 4: 4/4, 5: 5/5, 6: 6/6, 7: 7/7, 8: 8/4 (two groups), 9: 5/5 (two),
+# 13: 7/7 (two), 16: 8/6 (two / three), 24: 8/6, 34: 7/7 (five).
+GROUP_N = [6, 8, 10, 12, 14, 16, 24, 30, 46, 66]
+GROUP_N_ADJ = [6, 8, 10, 12, 24, 30]
+
+
+@pytest.mark.parametrize("N", GROUP_N)
+def test_three_box_group_sizes_forward(N):
+    """Every pixel against the oracle at each group size of the forward
+    column pass (sigma_r 120: these degrees are all valid)."""
+    H, W, sr, radii = 37, 70, 120.0, [4, 4, 5]
+    print(f"N {N}", flush=True)
+    f = synth.piecewise_smooth(H, W, seed=N + 11, n_shapes=3)
+    ref, eta_ref = oracle.forward(f, sr, N, radii, return_eta=True)
+    out, eta = _ops().trig_forward(_cuda(f), 255.0, sr, radii, N=N, return_eta=True,
+                                   path=STREAMED)
+    torch.cuda.synchronize()
+    _check(out.cpu().numpy(), ref, f"group sizes, N {N}")
+    e = eta.cpu().numpy().astype(np.float64)
+    assert np.allclose(e, eta_ref, rtol=2e-4, atol=1e-4 * eta_ref.max()), N
+
+
+@pytest.mark.parametrize("N", GROUP_N_ADJ)
+def test_three_box_group_sizes_adjoint(N):
+    """Every pixel of the adjoint against the oracle's exact gradient at each
+    group size of the adjoint column pass."""
+    H, W, sr, radii = 24, 40, 120.0, [4, 4, 5]
+    print(f"N {N}", flush=True)
+    f = synth.piecewise_smooth(H, W, seed=N + 13, n_shapes=3)
+    G = np.random.default_rng(N).normal(size=(H, W))
+    ref = oracle.grad(f, sr, N, radii, G)
+    fg = _cuda(f)
+    out, eta, aux = _ops().trig_forward(fg, 255.0, sr, radii, N=N, return_aux=True,
+                                        path=STREAMED)
+    gf = _ops().trig_backward(fg, out, eta, aux, _cuda(G), 255.0, sr, radii, N=N, path=STREAMED)
+    torch.cuda.synchronize()
+    _grad_check(gf.cpu().numpy(), ref, f"group sizes adjoint, N {N}")
+
+
 def test_stream_adjoint_chunks():
     """The streamed adjoint and the forward's sums with one-pair chunks (the
     partial sums carried between chunks) against the recommended workspace."""
