@@ -63,9 +63,9 @@ WORKLOADS = {
 _SB_PROFILE = "profiles/bf_sb_kernels_ragged256_hbm_traffic.md"
 MEASURED_TRAFFIC = {
     ("bf_sb_v<3,7,1> (adjoint column pass, groups of 4 to 7 pairs)", "ragged256"):
-        {"bytes": 33267732297, "src": "f9b78deca1a1", "profile": _SB_PROFILE},
+        {"bytes": 33267732297, "src": "86fe931f85cd", "profile": _SB_PROFILE},
     ("bf_sb_v<3,8,0> (forward column pass, groups of 4 to 8 pairs)", "ragged256"):
-        {"bytes": 29166826038, "src": "f9b78deca1a1", "profile": _SB_PROFILE},
+        {"bytes": 29166826038, "src": "86fe931f85cd", "profile": _SB_PROFILE},
 }
 STREAM_SOURCES = ("bf_stream.hip", "bf_tile.h")
 

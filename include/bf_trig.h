@@ -143,8 +143,9 @@ bf_status bf_trig_workspace_bytes(int64_t H, int64_t W, const bf_spatial_spec* s
 
 /* The same for a given degree (T, sigma_r and N as for the forward): the
  * recommended size holds every cosine pair of that degree in one chunk, up to
- * 4 GiB of planes (at least 16 pairs), which is the size of the library's
- * own workspace.  0 where the fused kernel is used. */
+ * 16 GiB of planes (at least 16 pairs; 64 pairs at 4096^2), which is the size
+ * of the library's own workspace.  A smaller workspace runs the pairs in
+ * chunks of equal size.  0 where the fused kernel is used. */
 bf_status bf_trig_workspace_bytes_ex(int64_t H, int64_t W, float T, float sigma_r, int32_t N,
                                      const bf_spatial_spec* spatial_spec, int64_t* bytes_out);
 
@@ -153,7 +154,7 @@ bf_status bf_trig_workspace_bytes_ex(int64_t H, int64_t W, float T, float sigma_
  * Equivalent to bf_trig_forward_ex with opts == NULL: every kernel width the
  * limits above allow runs; where the streamed passes run, the library uses a
  * workspace of its own (the size bf_trig_workspace_bytes_ex recommends: every
- * pair in one chunk up to 4 GiB of planes), allocated on first need per
+ * pair in one chunk up to 16 GiB of planes), allocated on first need per
  * device and kept until the process ends, so such a call may not be captured
  * (BF_ECAPTURE) and may return BF_ENOMEM.  Calls that share it are ordered on
  * the device, whatever their streams.

@@ -199,7 +199,7 @@ def stream_workspace_bytes(H: int, W: int, pairs: int) -> int:
 
 def workspace_bytes_ex(H: int, W: int, T: float, sigma_r: float, N: int, radii) -> int:
     """Recommended workspace of the streamed passes for this degree (every
-    pair in one chunk up to 4 GiB of planes; 0 where the fused kernel runs)."""
+    pair in one chunk up to 16 GiB of planes; 0 where the fused kernel runs)."""
     n = ctypes.c_int64()
     spec = SpatialSpec.of(radii)
     check(lib().bf_trig_workspace_bytes_ex(int(H), int(W), float(T), float(sigma_r), int(N),

@@ -113,9 +113,10 @@ bf_status stream_batch_stage(const StreamBatch* b, int stage, hipStream_t s);
 void stream_batch_destroy(StreamBatch* b);
 // Pairs per chunk of the workspace bf_trig_workspace_bytes recommends; the
 // library's own workspace and bf_trig_workspace_bytes_ex hold every pair up
-// to a budget of 4 GiB of planes (but at least this many pairs).
+// to a budget of 16 GiB of planes (but at least this many pairs): a few per
+// cent of the device's memory, 64 pairs at 4096^2.
 constexpr int kStreamChunkPairs = 16;
-constexpr size_t kStreamBudget = (size_t)4 << 30;
+constexpr size_t kStreamBudget = (size_t)16 << 30;
 size_t stream_default_workspace(int64_t H, int64_t W, int npairs);
 // The library's own streamed-path workspace for the current device (bf_api.cpp):
 // library_workspace takes a lock and orders `stream` after the previous user;

@@ -1180,11 +1180,15 @@ bf_status launch_stream(int mode, const StreamIO& io, int64_t H, int64_t W,
                   "too large", (long long)(W + 2 * sp.R), 64 * kSmLineMax);
         return BF_EUNSUPPORTED;
     }
-    const int chunk = stream_chunk_pairs(H, W, ws_bytes, rp.npairs);
+    int chunk = stream_chunk_pairs(H, W, ws_bytes, rp.npairs);
     if (chunk <= 0) {
         set_error("streamed path: workspace of %zu bytes is below the %zu bytes one pair needs",
                   ws_bytes, stream_workspace_bytes(H, W, 1));
         return BF_EINVAL;
+    }
+    if (rp.npairs > 0) {   // as many chunks as the workspace needs, of equal size
+        const int n = (rp.npairs + chunk - 1) / chunk;
+        chunk = (rp.npairs + n - 1) / n;
     }
     const bool bwd = mode == kSmBwd;
     const bool aux = !bwd && io.aux != nullptr;

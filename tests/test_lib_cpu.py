@@ -168,7 +168,7 @@ def test_workspace_query_and_streamed_validation():
     """The streamed passes run wherever their line holds W + 2R (<= 5184);
     their recommended workspace is 16 pairs' column-filtered planes (pitch W
     rounded up to 64) plus the partial sums and the adjoint's weights, and
-    for a given degree every pair up to 4 GiB.  Wider images run the fused
+    for a given degree every pair up to 16 GiB.  Wider images run the fused
     tiles, which need no workspace.  The
     documented limits, through the C ABI: radii up to BF_MAX_RADIUS = 256
     (BF_ERANGE above), W + 2R <= 5184 and a composite mass below 2^31
@@ -182,11 +182,12 @@ def test_workspace_query_and_streamed_validation():
     assert nat.workspace_bytes(2048, 2048, [29, 29, 30]) == nat.stream_workspace_bytes(2048, 2048, 16)
     assert nat.workspace_bytes(64, 8192, [9, 9, 10]) == 0
     assert nat.stream_workspace_bytes(64, 80, 16) == 16 * 16 * 64 * 128 + 24 * 64 * 80
-    # for a given degree: every pair in one chunk (34 at N = 66), up to 4 GiB of planes
+    # for a given degree: every pair in one chunk (34 at N = 66), up to 16 GiB of
+    # planes (64 pairs of 4096^2: 16 x 64 x 4096^2 bytes)
     assert nat.workspace_bytes_ex(2048, 2048, 255.0, 20.0, 0, [29, 29, 30]) == \
         nat.stream_workspace_bytes(2048, 2048, 34)
     assert nat.workspace_bytes_ex(4096, 4096, 255.0, 10.0, 0, [29, 29, 30]) == \
-        nat.stream_workspace_bytes(4096, 4096, 16)
+        nat.stream_workspace_bytes(4096, 4096, 64)
     assert nat.workspace_bytes_ex(64, 8192, 255.0, 20.0, 0, [9, 9, 10]) == 0
     assert nat.workspace_bytes(10, 10, [100, 100, 100]) == nat.stream_workspace_bytes(10, 10, 16)
     assert nat.workspace_bytes(64, 4584, [100, 100, 100]) > 0        # W + 2R = 5184
