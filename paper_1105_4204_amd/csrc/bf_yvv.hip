@@ -19,7 +19,7 @@
 //   vertical pass   (bf_yvv_v): lane = image column, walking down the rows:
 //     builds the channel, runs the causal pass (results stored), then the
 //     anticausal pass back up (in place);
-//   horizontal pass (bf_yvv_h): lane = image row; 64 x 32 blocks go through
+//   horizontal pass (bf_yvv_h): lane = image row; 64 x 16 blocks go through
 //     LDS so that global accesses stay coalesced; causal pass left to right
 //     (in place), then the anticausal pass right to left, demodulated on the
 //     fly: each thread sums c_m (C or S) F[channel] over its group's pairs,
@@ -43,8 +43,9 @@ namespace bf {
 constexpr int kYvThreads = 256;      // four waves, one per channel
 constexpr int kYvPairs = 2;          // pairs per thread (one direct phase, one recurrence step)
 constexpr int kYvChunkGroups = 20;   // groups per launch chunk, at most (40 pairs)
-constexpr int kYvBlk = 32;           // horizontal pass: columns per LDS block
+constexpr int kYvBlk = 16;           // horizontal pass: columns per LDS block
 constexpr int kYvBlkP = kYvBlk + 1;
+constexpr int kYvRowsPer = 64 / kYvBlk;   // rows one block transfer instruction covers
 constexpr int kYvRows = 16;          // vertical pass: rows whose loads are issued together
 
 struct YvArgs {
@@ -170,12 +171,13 @@ __global__ void __launch_bounds__(kYvThreads) bf_yvv_v(const YvArgs a) {
     }
 }
 
-// Horizontal pass: one wave per channel, one lane per image row; 64 x 32
-// blocks of each plane are moved through LDS with coalesced accesses.  Two
-// waves per SIMD (at most 256 registers a lane, a few spilled): two
-// workgroups share a CU, which hides part of the FP64 recursion's latency
-// (2048^2, N = 66: 6.0 -> 5.1 ms per forward).
-__global__ void __launch_bounds__(kYvThreads, 2) bf_yvv_h(const YvArgs a) {
+// Horizontal pass: one wave per channel, one lane per image row; 64 x 16
+// blocks of each plane are moved through LDS with coalesced accesses.  Three
+// workgroups share a CU (39 KB of LDS and at most 168 registers a lane each),
+// which hides part of the FP64 recursion's latency and lets the 544
+// workgroups of a 2048^2, N = 66 forward run in one round (two workgroups of
+// 64 x 32 blocks per CU: 6.0 -> 5.1 ms per forward; three of 64 x 16: 4.9).
+__global__ void __launch_bounds__(kYvThreads, 3) bf_yvv_h(const YvArgs a) {
     __shared__ float blk[4][kYvPairs][64][kYvBlkP];
     __shared__ float gblk[64][kYvBlkP];
     const int lane = threadIdx.x & 63;
@@ -190,21 +192,23 @@ __global__ void __launch_bounds__(kYvThreads, 2) bf_yvv_h(const YvArgs a) {
     float cq[kYvPairs];
 #pragma unroll
     for (int p = 0; p < kYvPairs; ++p) cq[p] = p < np ? a.chat[qg + p] : 0.0f;
-    // block transfers: lane l moves column l & 31 of rows 2 r + (l >> 5).
-    // Double buffering: while a block is filtered from LDS, the next block's
-    // values are already on their way into registers (t, tg), from clamped
-    // positions without branches; they are masked when written to LDS.
-    const int bc = lane & 31, br = lane >> 5;
-    float t[kYvPairs][32];
-    float tg[8];
+    // block transfers: lane l moves column l % kYvBlk of rows
+    // kYvRowsPer r + l / kYvBlk.  Double buffering: while a block is filtered
+    // from LDS, the next block's values are already on their way into
+    // registers (t, tg), from clamped positions without branches; they are
+    // masked when written to LDS.  Blocks of 16 columns keep the workgroup's
+    // LDS within a quarter of the CU's, so four workgroups fit on a CU.
+    const int bc = lane % kYvBlk, br = lane / kYvBlk;
+    float t[kYvPairs][kYvBlk];
+    float tg[kYvBlk / 4];
     auto fetch_blk = [&](int x0) {
         const int x = min(x0 + bc, a.W - 1);
 #pragma unroll
         for (int p = 0; p < kYvPairs; ++p) {
             const int pc = min(p, np - 1);
 #pragma unroll
-            for (int r = 0; r < 32; ++r) {
-                const int y = min(y0 + 2 * r + br, a.H - 1);
+            for (int r = 0; r < kYvBlk; ++r) {
+                const int y = min(y0 + kYvRowsPer * r + br, a.H - 1);
                 t[p][r] = planes[(size_t)pc * 4 * HW + (size_t)y * a.W + x];
             }
         }
@@ -213,33 +217,35 @@ __global__ void __launch_bounds__(kYvThreads, 2) bf_yvv_h(const YvArgs a) {
 #pragma unroll
         for (int p = 0; p < kYvPairs; ++p) {
 #pragma unroll
-            for (int r = 0; r < 32; ++r) {
-                const int row = 2 * r + br;
+            for (int r = 0; r < kYvBlk; ++r) {
+                const int row = kYvRowsPer * r + br;
                 blk[ch][p][row][bc] = (y0 + row < a.H && x0 + bc < a.W) ? t[p][r] : 0.0f;
             }
         }
     };
-    // g of a block: wave w moves rows 2 r + (l >> 5) for r in [8 w, 8 w + 8)
+    // g of a block: wave w moves the rows kYvRowsPer r + l / kYvBlk for r in
+    // [w kYvBlk / 4, (w + 1) kYvBlk / 4)
+    constexpr int NG = kYvBlk / 4;
     auto fetch_g = [&](int x0) {
         const int x = min(x0 + bc, a.W - 1);
 #pragma unroll
-        for (int r = 0; r < 8; ++r) {
-            const int y = min(y0 + 2 * (8 * ch + r) + br, a.H - 1);
+        for (int r = 0; r < NG; ++r) {
+            const int y = min(y0 + kYvRowsPer * (NG * ch + r) + br, a.H - 1);
             tg[r] = a.f[(size_t)y * a.W + x];
         }
     };
     auto put_g = [&](int x0) {
 #pragma unroll
-        for (int r = 0; r < 8; ++r) {
-            const int row = 2 * (8 * ch + r) + br;
+        for (int r = 0; r < NG; ++r) {
+            const int row = kYvRowsPer * (NG * ch + r) + br;
             gblk[row][bc] = (y0 + row < a.H && x0 + bc < a.W) ? tg[r] - a.center : 0.0f;
         }
     };
     auto store_blk = [&](int x0) {
         for (int p = 0; p < np; ++p) {
 #pragma unroll 8
-            for (int r = 0; r < 32; ++r) {
-                const int row = 2 * r + br, y = y0 + row, x = x0 + bc;
+            for (int r = 0; r < kYvBlk; ++r) {
+                const int row = kYvRowsPer * r + br, y = y0 + row, x = x0 + bc;
                 if (y < a.H && x < a.W)
                     planes[(size_t)p * 4 * HW + (size_t)y * a.W + x] = blk[ch][p][row][bc];
             }
@@ -317,8 +323,8 @@ __global__ void __launch_bounds__(kYvThreads, 2) bf_yvv_h(const YvArgs a) {
         __syncthreads();
         // den partial = C + S waves, num partial = gC + gS waves
         if (ch < 2) {
-            for (int r = 0; r < 32; ++r) {
-                const int row = 2 * r + br, y = y0 + row, x = x0 + bc;
+            for (int r = 0; r < kYvBlk; ++r) {
+                const int row = kYvRowsPer * r + br, y = y0 + row, x = x0 + bc;
                 if (y < a.H && x < a.W)
                     part[(size_t)ch * HW + (size_t)y * a.W + x] =
                         blk[ch][0][row][bc] + blk[ch + 2][0][row][bc];
